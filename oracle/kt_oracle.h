@@ -1,0 +1,134 @@
+/*
+ * kt_oracle.h -- plain FP64 CPU oracle for backward ray tracing of null
+ * geodesics in Kerr spacetime (Boyer-Lindquist coordinates, Hamiltonian form).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library.
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load it.  It shares no source, header, table or helper with the GPU
+ * path and includes nothing from it.
+ *
+ * Conventions (Velasquez-Cadavid et al., "OSIRIS", EPJC):
+ *   signature (-,+,+,+), geometrized units (Sect. 1, last paragraph);
+ *   coordinates {t, r, theta, phi}; momenta p_mu covariant;
+ *   E = -p_t and L = p_phi are constants of motion (Sect. 2.1).
+ *
+ * Every function is re-entrant; the image drivers are OpenMP-parallel over
+ * pixels with schedule(dynamic, 64).
+ */
+#ifndef KT_ORACLE_H
+#define KT_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* fate codes */
+#define KO_ESCAPED 0
+#define KO_CAPTURED 1
+#define KO_DISK 2
+#define KO_MAXSTEPS 3
+#define KO_STEPFAIL 4
+#define KO_INVALID 5
+
+/* integrators */
+#define KO_RK4_S 0 /* classic RK4, fixed step in s with d(lambda)/ds = Delta/r */
+#define KO_DP45 1  /* Dormand-Prince 5(4), adaptive, FSAL */
+
+typedef struct {
+    /* spacetime */
+    double M, a;
+    /* camera: observer at (r_obs, theta0 = incl, phi0 = 0); image plane
+       [-fov_x, fov_x] x [-fov_y, fov_y] sampled at nx x ny pixel centres */
+    double r_obs, incl, fov_x, fov_y;
+    int32_t nx, ny;
+    /* integrator */
+    int32_t method;
+    double h_fixed;      /* RK4_S step in s */
+    double rtol, atol;   /* DP45 tolerances */
+    double h_init;       /* DP45 first trial step in lambda */
+    double cap_buffer;   /* delta_r: captured when r < r_+ + cap_buffer */
+    double r_escape;     /* escaped when r > r_escape */
+    int64_t max_steps;   /* accepted-step cap */
+    /* thin equatorial disk */
+    int32_t disk_on;
+    double r_in, r_out, emis_q;
+    /* point source for the deflection diagnostics */
+    int32_t src_on;
+    double r_src;
+} ko_setup;
+
+/* Per-ray results.  Arrays hold one entry per traced ray; any pointer may be
+   NULL except fate. */
+typedef struct {
+    uint8_t *fate;
+    double *r_hit, *g, *intensity;
+    double *max_abs_h, *max_rel_h;
+    double *psi, *deflection;
+    double *theta_f, *phi_f;
+    uint8_t *n_cross;
+    int32_t *n_steps, *n_evals;
+} ko_out;
+
+/* Covariant Kerr metric at (r, theta): g = {g_tt, g_tph, g_rr, g_thth, g_phph}. */
+void ko_metric_cov(double M, double a, double r, double th, double g[5]);
+
+/* Contravariant metric and its r- and theta-derivatives, same ordering. */
+void ko_metric_inv(double M, double a, double r, double th, double gi[5],
+                   double dgi_dr[5], double dgi_dth[5]);
+
+/* H = 1/2 g^{mu nu} p_mu p_nu with p_t = -E, p_phi = L.
+   state = {r, theta, phi, p_r, p_theta}. */
+double ko_hamiltonian(double M, double a, const double state[5], double E, double L);
+
+/* Scale-free constraint residual |2 Sigma H| / D, D = sum of the magnitudes
+   of the terms of 2 Sigma H in Carter's separated form. */
+double ko_hamiltonian_rel(double M, double a, const double state[5], double E, double L);
+
+/* Hamilton's equations: out = d/dlambda {r, theta, phi, p_r, p_theta};
+   out[5] = dt/dlambda. */
+void ko_rhs(double M, double a, const double state[5], double E, double L, double out[6]);
+
+/* Camera: initial state for image-plane point (x, y).
+   out = {r, theta, phi, p_r, p_theta, E, L}.  Returns 0, or 1 when
+   x^2 + y^2 >= r_obs^2 (no real p_r). */
+int ko_camera_ray(double M, double a, double r_obs, double incl, double x, double y,
+                  double out[7]);
+
+/* Pixel-centre coordinates of pixel (i, j). */
+void ko_pixel_xy(const ko_setup *s, int32_t i, int32_t j, double *x, double *y);
+
+/* Trace rays through image-plane points (x[k], y[k]), k < n. */
+void ko_trace_xy(const ko_setup *s, const double *x, const double *y, int64_t n,
+                 const ko_out *o, int n_threads);
+
+/* Trace the pixels pix[k] (row-major j*nx+i), k < n; pix == NULL means all
+   nx*ny pixels in order.  Outputs are indexed by k. */
+void ko_trace_pixels(const ko_setup *s, const int32_t *pix, int64_t n, const ko_out *o,
+                     int n_threads);
+
+/* Trace one ray and record every accepted state:
+   traj[6*k + {0..5}] = {lambda (RK4_S: s), r, theta, phi, p_r, p_theta}.
+   Returns the number of recorded states (<= max_points); the first is the
+   initial state.  Fate etc. go to entry 0 of o. */
+int64_t ko_trace_one(const ko_setup *s, double x, double y, double *traj, int64_t max_points,
+                     const ko_out *o);
+
+/* Ring-flag post-pass over a full nx x ny image of deflection angles: pixel
+   p is flagged when, for its +i or +j neighbour q with both deflections
+   finite, an odd multiple of pi lies between Psi_p and Psi_q. */
+void ko_ring_flags(int32_t nx, int32_t ny, const double *deflection, uint8_t *ring);
+
+/* Outer horizon r_+ = M + sqrt(M^2 - a^2). */
+double ko_horizon(double M, double a);
+
+/* Integrator self-test on y'' = -y, y(0) = 0, y'(0) = 1 over [0, T] with n
+   fixed steps of the given method's underlying tableau (DP5 propagates the
+   5th-order solution).  Returns the final (y, y') in out[2]. */
+void ko_harmonic_fixed(int32_t method, double T, int64_t n, double out[2]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
