@@ -1,0 +1,180 @@
+/*
+ * kerrtrace.h -- C ABI of the MI355X (gfx950) Kerr backward ray tracer.
+ *
+ * One null geodesic per image pixel is integrated backward from the observer
+ * (Velasquez-Cadavid et al., "OSIRIS", Sect. 2.2) with Hamilton's equations
+ * in Boyer-Lindquist Kerr coordinates (eq:edm, eq:ligH, eq:Kerr) while the
+ * constraint H = 0 is tracked (Sect. 3.1).  Each ray ends on the horizon, on
+ * a thin equatorial disk or on escape (Sect. 4.1, Sect. 5).
+ *
+ * Conventions
+ *   - Geometrized units; M is a parameter (the paper sets M = 1, Sect. 1).
+ *   - The observer sits at (r_obs, theta_0 = incl, phi_0 = 0).  Pixel (i, j)
+ *     has image-plane centre x = -fov_x + (i + 1/2) 2 fov_x / nx,
+ *     y = -fov_y + (j + 1/2) 2 fov_y / ny (image plane of Sect. 2.3) and
+ *     row-major index j*nx + i.
+ *   - Initial momenta follow the second eq:momentums (Sect. 2.3) with p_r < 0
+ *     (ingoing), E = -p_t, L = p_phi.
+ *   - Every array is a DEVICE pointer into memory the caller owns.  The
+ *     library allocates nothing and frees nothing.  Work is enqueued on
+ *     hip_stream (a hipStream_t; NULL means the null stream) and the call
+ *     returns without waiting; outputs are valid once the stream has been
+ *     synchronised.  Structs are read during the call only.
+ *   - Calls on one GPU that share a workspace must not overlap.
+ *
+ * Errors: every int-returning call returns KT_OK or a negative code and
+ * leaves a message for kt_last_error().  Per-ray problems are never errors:
+ * they become fate codes.
+ */
+#ifndef KERRTRACE_H
+#define KERRTRACE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KT_VERSION_NUMBER 100
+
+/* return codes */
+#define KT_OK 0
+#define KT_EINVAL (-1)   /* an argument is out of range, non-finite or NULL */
+#define KT_EDEVICE (-2)  /* a HIP call or kernel launch failed */
+#define KT_ENOMEM (-3)   /* the workspace is smaller than kt_workspace_bytes() */
+
+/* per-ray fate codes (uint8 per pixel) */
+#define KT_FATE_ESCAPED 0   /* r > r_escape (celestial sphere r_cs, Sect. 4.1) */
+#define KT_FATE_CAPTURED 1  /* r < r_H + capture_buffer (Sect. 4.1) */
+#define KT_FATE_DISK 2      /* hit the disk between r_in and r_out (Sect. 5) */
+#define KT_FATE_MAXSTEPS 3  /* step budget exhausted */
+#define KT_FATE_STEPFAIL 4  /* step size underflow or non-finite state */
+#define KT_FATE_INVALID 5   /* x^2 + y^2 >= r_obs^2: no real p_r */
+
+/* integrators */
+#define KT_RK4_S 0  /* classic RK4, fixed step h_fixed in s, d(lambda)/ds = Delta/r */
+#define KT_DP45 1   /* Dormand-Prince 5(4), adaptive, FSAL (Sect. 3.1) */
+
+/* arithmetic of the RHS */
+#define KT_FP64 0
+#define KT_MIXED 1  /* FP32 mass-dependent RHS part for r >= r_switch, FP64 re-run
+                       of every ray whose max |H|_rel exceeds h_budget */
+
+/* Observer and image plane (Sect. 2.3). */
+typedef struct kt_camera {
+    double r_obs;   /* observer radius, > r_H + capture_buffer */
+    double incl;    /* theta_0 in (0, pi), radians */
+    double fov_x;   /* half-width of the image plane, > 0 */
+    double fov_y;   /* half-height, > 0 */
+    int32_t nx, ny; /* resolution, >= 1 each, nx*ny < 2^31 */
+} kt_camera;
+
+/* Kerr spacetime (eq:Kerr): mass M > 0, spin |a| <= M. */
+typedef struct kt_spacetime {
+    double M, a;
+} kt_spacetime;
+
+/* Thin equatorial Keplerian disk (Sect. 5). Emissivity (M/r)^emis_index. */
+typedef struct kt_disk {
+    int32_t enabled;
+    double r_in, r_out, emis_index;
+} kt_disk;
+
+/* Point source at (r_src, pi - incl, pi), behind the hole: deflection
+   diagnostics for Einstein rings (Sect. 4.3). */
+typedef struct kt_source {
+    int32_t enabled;
+    double r_src;
+} kt_source;
+
+typedef struct kt_integrator {
+    int32_t method;         /* KT_RK4_S or KT_DP45 */
+    int32_t precision;      /* KT_FP64 or KT_MIXED */
+    double h_fixed;         /* RK4_S step in s, > 0 */
+    double rtol, atol;      /* DP45 tolerances, > 0 */
+    double h_init;          /* DP45 first trial step in lambda, > 0 */
+    double capture_buffer;  /* delta_r of Sect. 4.1, >= 0 */
+    double r_escape;        /* r_cs; 0 selects 1.1 r_obs */
+    double h_budget;        /* MIXED: re-run in FP64 when max |H|_rel > h_budget */
+    double r_switch;        /* MIXED: FP32 RHS part only where r >= r_switch */
+    int64_t max_steps;      /* accepted-step budget per ray, >= 1 */
+} kt_integrator;
+
+/* Launch shape.  Pass NULL for the defaults. */
+typedef struct kt_launch {
+    int32_t persistent;     /* 1: persistent waves refill lanes from a global ticket;
+                               0: one ray per lane, no refill */
+    int32_t block;          /* threads per workgroup: 64, 128, 256 or 512 */
+    int32_t blocks_per_cu;  /* persistent grid = CUs * blocks_per_cu; 0 = occupancy */
+    int32_t batch;          /* ray ids taken per ticket fetch, 1..4096 */
+} kt_launch;
+
+/* Launch statistics (device memory, written at the end of a render). */
+typedef struct kt_stats {
+    uint64_t rays;           /* nx * ny */
+    uint64_t evals;          /* all RHS evaluations, both passes */
+    uint64_t evals_fp32;     /* evaluations whose mass term ran in FP32 */
+    uint64_t fallback_rays;  /* MIXED: rays re-run in FP64 */
+    uint64_t fate_count[8];  /* histogram of final fates */
+} kt_stats;
+
+/* Per-pixel outputs: device arrays of nx*ny entries, row-major j*nx + i.
+   Any pointer except fate may be NULL (that output is skipped).
+   Values that do not apply to a ray are NaN (r_hit, g, psi, deflection) or
+   0 (intensity, ring). */
+typedef struct kt_outputs {
+    uint8_t *fate;
+    double *r_hit;       /* disk hit radius */
+    double *g;           /* redshift nu_obs/nu_em at the disk (eq:redshift) */
+    double *intensity;   /* g^3 I_em, I_em = (M/r_hit)^emis_index */
+    double *max_abs_h;   /* max |H| over accepted states (Error of Sect. 3.1) */
+    double *max_rel_h;   /* max |2 Sigma H| / D, D = sum of |terms| of 2 Sigma H */
+    double *psi;         /* source: angle between ray and source direction at r_src */
+    double *deflection;  /* source: swept angle from the observer to r_src */
+    double *theta_f, *phi_f;  /* final (or disk-crossing) angles */
+    uint8_t *n_cross;    /* equatorial crossings outside the disk before the end */
+    uint8_t *used_fp64;  /* MIXED: 1 when the ray was re-run in FP64 */
+    uint8_t *ring;       /* source: an odd multiple of pi lies between this pixel's
+                            deflection and its +i or +j neighbour's */
+    int32_t *n_steps;    /* accepted steps */
+    int32_t *n_evals;    /* RHS evaluations */
+    kt_stats *stats;     /* may be NULL */
+} kt_outputs;
+
+/* Render one image.  disk and source may be NULL (disabled).  workspace is a
+   device buffer of at least kt_workspace_bytes(camera, integ) bytes, aligned
+   to 256 bytes; its contents on entry do not matter.
+   Returns KT_OK, KT_EINVAL, KT_ENOMEM or KT_EDEVICE. */
+int kt_render(const kt_camera *camera, const kt_spacetime *spacetime, const kt_disk *disk,
+              const kt_source *source, const kt_integrator *integ, const kt_outputs *out,
+              void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/* kt_render with an explicit launch shape (NULL = defaults).  Per-ray
+   arithmetic does not depend on the launch shape: outputs are bit-identical
+   for every valid shape. */
+int kt_render_ex(const kt_camera *camera, const kt_spacetime *spacetime, const kt_disk *disk,
+                 const kt_source *source, const kt_integrator *integ, const kt_outputs *out,
+                 void *workspace, size_t workspace_bytes, void *hip_stream,
+                 const kt_launch *launch);
+
+/* Workspace size in bytes for this camera and integrator (0 on bad input). */
+size_t kt_workspace_bytes(const kt_camera *camera, const kt_integrator *integ);
+
+/* Initial state of every pixel (Sect. 2.3), for checking the camera alone:
+   state is a device array of 7*nx*ny doubles laid out SoA as
+   [r | theta | phi | p_r | p_theta | E | L], each block nx*ny long;
+   invalid (device, nx*ny bytes) is 1 where x^2 + y^2 >= r_obs^2. */
+int kt_init_rays(const kt_camera *camera, const kt_spacetime *spacetime, double *state,
+                 uint8_t *invalid, void *hip_stream);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char *kt_last_error(void);
+
+/* KT_VERSION_NUMBER of the built library. */
+int kt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,75 @@
+// kt_internal.h -- parameter block shared by the host runtime and the kernels.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "kerrtrace.h"
+
+namespace kt {
+
+// Workspace layout (bytes from the start of the caller's buffer).
+constexpr size_t WS_TICKET = 0;       // uint32 ray ticket
+constexpr size_t WS_ACC = 64;         // uint64[16]: evals, evals_fp32, -, fate histogram at 8..15
+constexpr size_t WS_FB_COUNT = 192;   // uint32 fallback list length
+constexpr size_t WS_RC = 256;         // double[n_rays] disk crossing radius per ray
+// then, for KT_MIXED only, uint32[n_rays] ray ids for the FP64 re-run
+inline size_t ws_fb_list_offset(size_t n_rays) { return (WS_RC + 8 * n_rays + 255) & ~size_t(255); }
+constexpr int ACC_EVALS = 0, ACC_EVALS_FP32 = 1;
+
+struct Outputs {
+    uint8_t* fate;
+    double *r_hit, *g, *intensity, *max_abs_h, *max_rel_h, *psi, *deflection, *theta_f, *phi_f;
+    uint8_t *n_cross, *used_fp64, *ring;
+    int32_t *n_steps, *n_evals;
+    kt_stats* stats;
+};
+
+// Everything a trace kernel needs, passed by value.
+struct Params {
+    // spacetime
+    double M, a, a2, two_a2;
+    double r_cap, r_esc;
+    // camera and per-image camera constants (Sect. 2.3)
+    double r0, incl, inv_r0, fov_x, fov_y, dx, dy;
+    double E0;      // 1 / A_t
+    double cE;      // g_tphi / (r0 sqrt(g_phph)):  E = E0 + x cE
+    double cL;      // -sqrt(g_phph) / r0:          L = x cL
+    double cth;     // sqrt(g_thth) / r0:           p_theta = y cth
+    double g_rr;    // g_rr at the camera:          p_r = -sqrt(g_rr (1 - (y/r0)^2 - (x/r0)^2))
+    int32_t nx, ny, n_rays;
+    // integrator
+    int32_t method, precision;
+    double h_fixed, rtol, atol, h_init;
+    int64_t max_steps, max_evals;
+    double h_budget, r_switch;
+    // disk (Sect. 5)
+    int32_t disk_on;
+    double r_in, r_out, emis_q;
+    // source for the deflection diagnostics
+    int32_t src_on;
+    double r_src, src_tol;
+    double src_n[3];  // unit vector towards the source
+    // outputs and workspace
+    Outputs out;
+    uint32_t* ticket;
+    unsigned long long* acc;
+    uint32_t* fb_list;
+    uint32_t* fb_count;
+    double* rc_buf;
+    // launch
+    int32_t persistent, batch;
+    int32_t from_list;  // take ray ids from fb_list[0 .. *fb_count)
+};
+
+// Host-side launchers (kt_trace.hip).
+int launch_ws_init(const Params& p, void* stream);
+int launch_trace(const Params& p, int grid, int block, void* stream);
+int launch_reset_ticket(const Params& p, void* stream);
+int launch_ring(const Params& p, void* stream);
+int launch_disk_obs(const Params& p, void* stream);
+int launch_stats(const Params& p, void* stream);
+int launch_init_rays(const Params& p, double* state, uint8_t* invalid, void* stream);
+int trace_max_blocks_per_cu(const Params& p, int block);
+
+}  // namespace kt

@@ -1,0 +1,572 @@
+// kt_trace.hip -- gfx950 kernels of the Kerr backward ray tracer.
+//
+// trace_kernel<METHOD>: one ray per lane.  Each lane holds its ray's state
+// (r, theta, phi, p_r, p_theta), its constants (E, L) and its step control in
+// VGPRs and advances one integrator step per loop iteration; all busy lanes
+// of a wave evaluate the six (DP45) or four (RK4) right-hand sides together.
+// When a ray ends, the lane writes that ray's outputs and takes the next ray
+// id from its wave's queue, a contiguous range of ids that the wave refills
+// in batches from a global atomic ticket (persistent mode).  A wave exits
+// once the ticket has passed the last ray and all its lanes are idle.
+//
+// Event location (disk plane, source sphere) reuses the same loop: a lane in
+// LOCATE mode takes trial steps of size h' from the step's start state, so
+// trial steps run in lockstep with other lanes' ordinary steps.
+#include <hip/hip_runtime.h>
+
+#include "kt_device.h"
+#include "kt_internal.h"
+
+#ifndef KT_WAVES_PER_EU
+#define KT_WAVES_PER_EU 4
+#endif
+
+namespace kt {
+
+constexpr double HALF_PI = 1.57079632679489661923;
+
+// Great-circle angle between the directions (theta1, phi1) and
+// (theta2, phi1 + dphi), given sin/cos of the thetas.
+__device__ __forceinline__ double arc_angle(double s1, double c1, double s2, double c2, double dphi) {
+    double sd, cd;
+    sincos_fast(dphi, &sd, &cd);
+    // frame rotated so that phi1 = 0: n1 = (s1, 0, c1), n2 = (s2 cd, s2 sd, c2)
+    const double cx = -c1 * s2 * sd;
+    const double cy = fma(c1 * s2, cd, -s1 * c2);
+    const double cz = s1 * s2 * sd;
+    const double cr = sqrt(fma(cx, cx, fma(cy, cy, cz * cz)));
+    const double dt = fma(s1 * s2, cd, c1 * c2);
+    return atan2_upper(cr, dt);
+}
+
+// Initial state of pixel `ray` (second eq:momentums with p_r ingoing).
+// Returns false when x^2 + y^2 >= r0^2 (no real p_r).
+__device__ __forceinline__ bool camera_state(const Params& p, int32_t ray, double z[5], double* E,
+                                             double* L) {
+    const int32_t j = ray / p.nx;
+    const int32_t i = ray - j * p.nx;
+    const double x = __dadd_rn(-p.fov_x, __dmul_rn(static_cast<double>(i) + 0.5, p.dx));
+    const double y = __dadd_rn(-p.fov_y, __dmul_rn(static_cast<double>(j) + 0.5, p.dy));
+    const double Pth = y / p.r0;   // observer-frame P^theta with P^t = 1
+    const double Pph = -x / p.r0;  // observer-frame P^phi
+    const double rad = __dsub_rn(__dsub_rn(1.0, __dmul_rn(Pth, Pth)), __dmul_rn(Pph, Pph));
+    *E = __dadd_rn(p.E0, __dmul_rn(x, p.cE));
+    *L = __dmul_rn(x, p.cL);
+    z[0] = p.r0;
+    z[1] = p.incl;
+    z[2] = 0.0;
+    z[3] = rad > 0.0 ? -sqrt(__dmul_rn(p.g_rr, rad)) : 0.0;
+    z[4] = __dmul_rn(y, p.cth);
+    return rad > 0.0;
+}
+
+// Lane flags, packed in one int.
+enum : int {
+    F_VALID = 1 << 0,     // pixel has a real initial p_r
+    F_FRESH = 1 << 1,     // k1 = f(y0) not evaluated yet
+    F_LOCATE = 1 << 2,    // taking trial steps to locate an event
+    F_REJECTED = 1 << 3,  // previous attempt was rejected (no step growth)
+    F_RETAKE = 1 << 4,    // re-taking an accepted step after locating an event in it
+    F_SKIPDISK = 1 << 5,  // disk crossing of the re-taken step already handled
+    F_SRCDONE = 1 << 6,   // source sphere crossed
+    F_EVSRC = 1 << 7,     // event being located: 0 disk plane, 1 source sphere
+};
+constexpr int NCROSS_SHIFT = 8;   // 8 bits: equatorial crossings outside the disk
+constexpr int EVIT_SHIFT = 16;    // 8 bits: trial steps of the current event
+
+// Per-lane state that is touched at most once per step lives in LDS,
+// laid out [field][thread] so a wave's accesses are consecutive words.
+// C_PSI accumulates the swept angle and, once the source sphere is crossed,
+// holds the deflection; C_SRCPSI holds the angle to the source.
+enum : int {
+    C_MAXABS = 0, C_MAXREL, C_LAM, C_PSI, C_SRCPSI, C_CS, C_CC, C_EVA, C_EVFA, C_EVB, C_EVFB, C_EVC,
+    N_COLD
+};
+constexpr int BLOCK_MAX = 256;
+
+template <int METHOD>
+__device__ __forceinline__ void take_step(const Spacetime& st, const RayConst& rc, const double y[5],
+                                          const double k1[5], double h, double yn[5], double kn[5],
+                                          double er[5], Diag* dg) {
+    if constexpr (METHOD == KT_DP45) {
+        dp45_step(st, rc, y, k1, h, yn, kn, er, dg);
+    } else {
+        rk4s_step(st, rc, y, k1, h, yn, kn, dg);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) er[i] = 0.0;
+    }
+}
+
+// Step-size factor err^(-1/5) * 0.9 from the mean-square error msq = err^2,
+// evaluated in FP32: it only steers the step size.
+__device__ __forceinline__ float step_factor(double msq) {
+    return 0.9f * __builtin_amdgcn_exp2f(-0.1f * __builtin_amdgcn_logf(static_cast<float>(msq)));
+}
+
+template <int METHOD>
+__global__ void __launch_bounds__(BLOCK_MAX) __attribute__((amdgpu_waves_per_eu(KT_WAVES_PER_EU)))
+trace_kernel(const Params p) {
+    constexpr int EVALS_PER_STEP = (METHOD == KT_DP45) ? 6 : 4;
+    constexpr bool S_TIME = (METHOD == KT_RK4_S);
+    __shared__ double cold[N_COLD][BLOCK_MAX];
+    const int tid = threadIdx.x;
+#define COLD(f) cold[f][tid]
+
+    const Spacetime st{p.M, p.a, p.a2, p.two_a2};
+    const uint32_t lane = __lane_id();
+    const uint32_t n_total = p.from_list ? *p.fb_count : static_cast<uint32_t>(p.n_rays);
+
+    // this wave's queue of ray ids [q_next, q_end)
+    uint32_t q_next, q_end;
+    bool exhausted;
+    if (p.persistent) {
+        q_next = q_end = 0;
+        exhausted = false;
+    } else {
+        const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+        q_next = min(wave * 64u, n_total);
+        q_end = min(q_next + 64u, n_total);
+        exhausted = true;
+    }
+
+    int32_t ray = -1;
+    int fl = 0;
+    double y[5], k1[5];
+    double E = 0.0, L = 0.0, h = 0.0;
+    int nsteps = 0, nevals = 0;
+    unsigned long long evals_acc = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) y[i] = k1[i] = 0.0;
+
+    for (;;) {
+        // ---- refill idle lanes from the wave queue -------------------------
+        unsigned long long idle = __ballot(ray < 0);
+        while (idle != 0ull) {
+            if (q_next >= q_end) {
+                if (exhausted) break;
+                const int leader = __ffsll(idle) - 1;
+                uint32_t base = 0;
+                if (static_cast<int>(lane) == leader) base = atomicAdd(p.ticket, static_cast<uint32_t>(p.batch));
+                base = static_cast<uint32_t>(__shfl(static_cast<int>(base), leader));
+                if (base >= n_total) {
+                    exhausted = true;
+                    break;
+                }
+                q_next = base;
+                q_end = min(base + static_cast<uint32_t>(p.batch), n_total);
+            }
+            const uint32_t rank = static_cast<uint32_t>(__popcll(idle & ((1ull << lane) - 1ull)));
+            const uint32_t avail = q_end - q_next;
+            if (ray < 0 && rank < avail) {
+                const uint32_t slot = q_next + rank;
+                ray = p.from_list ? static_cast<int32_t>(p.fb_list[slot]) : static_cast<int32_t>(slot);
+                fl = camera_state(p, ray, y, &E, &L) ? (F_VALID | F_FRESH) : 0;
+                h = (METHOD == KT_DP45) ? p.h_init : p.h_fixed;
+                nsteps = 0;
+                nevals = 0;
+            }
+            q_next += min(static_cast<uint32_t>(__popcll(idle)), avail);
+            idle = __ballot(ray < 0);
+        }
+        if (__ballot(ray >= 0) == 0ull) break;
+        if (ray < 0) continue;
+
+        // ---- one step per busy lane ----------------------------------------
+        const RayConst rc = make_ray_const(st, E, L);
+        const double NaN = __builtin_nan("");
+        int fate = -1;  // >= 0 once the ray ends
+        double thf = y[1], phf = y[2], r_c = NaN, psi = NaN, defl = NaN;
+
+        if (!(fl & F_VALID)) {
+            fate = KT_FATE_INVALID;
+            COLD(C_MAXABS) = NaN;
+            COLD(C_MAXREL) = NaN;
+        } else if (fl & F_FRESH) {
+            // first evaluation: k1 = f(y0) (FSAL seed) and H at lambda = 0
+            Diag dg;
+            rhs<true, S_TIME>(st, rc, y, k1, &dg);
+            nevals = 1;
+            COLD(C_MAXABS) = fabs(dg.H);
+            COLD(C_MAXREL) = dg.rel;
+            COLD(C_LAM) = 0.0;
+            COLD(C_PSI) = 0.0;
+            COLD(C_CS) = dg.s;
+            COLD(C_CC) = dg.c;
+            fl &= ~F_FRESH;
+        } else if (!(fl & (F_LOCATE | F_RETAKE)) && (nsteps >= p.max_steps || nevals >= p.max_evals)) {
+            fate = KT_FATE_MAXSTEPS;
+        } else {
+            const bool locating = (fl & F_LOCATE) != 0;
+            const double hs = locating ? COLD(C_EVC) : h;
+            double yn[5], kn[5], er[5];
+            Diag dg;
+            take_step<METHOD>(st, rc, y, k1, hs, yn, kn, er, &dg);
+            nevals += EVALS_PER_STEP;
+            if (locating) {
+                // Illinois regula falsi on the event function
+                const bool src = (fl & F_EVSRC) != 0;
+                const double fc = src ? yn[0] - p.r_src : yn[1] - HALF_PI;
+                const double tol = src ? p.src_tol : 1e-14;
+                const int it = ((fl >> EVIT_SHIFT) & 0xff) + 1;
+                fl = (fl & ~(0xff << EVIT_SHIFT)) | (it << EVIT_SHIFT);
+                if (fabs(fc) <= tol || it >= 64) {
+                    if (!src) {
+                        if (yn[0] >= p.r_in && yn[0] <= p.r_out) {
+                            fate = KT_FATE_DISK;
+                            r_c = yn[0];
+                            thf = yn[1];
+                            phf = yn[2];
+                        } else {
+                            const int nc = min(((fl >> NCROSS_SHIFT) & 0xff) + 1, 255);
+                            fl = (fl & ~(0xff << NCROSS_SHIFT)) | (nc << NCROSS_SHIFT) | F_SKIPDISK;
+                        }
+                    } else {
+                        defl = COLD(C_PSI) + arc_angle(COLD(C_CS), COLD(C_CC), dg.s, dg.c, yn[2] - y[2]);
+                        double sp, cp;
+                        sincos_fast(yn[2], &sp, &cp);
+                        const double nx = dg.s * cp, ny = dg.s * sp, nz = dg.c;
+                        const double cx = ny * p.src_n[2] - nz * p.src_n[1];
+                        const double cy = nz * p.src_n[0] - nx * p.src_n[2];
+                        const double cz = nx * p.src_n[1] - ny * p.src_n[0];
+                        psi = atan2_upper(sqrt(fma(cx, cx, fma(cy, cy, cz * cz))),
+                                          fma(nx, p.src_n[0], fma(ny, p.src_n[1], nz * p.src_n[2])));
+                        COLD(C_PSI) = defl;  // parked until the ray ends
+                        COLD(C_SRCPSI) = psi;
+                        fl |= F_SRCDONE;
+                    }
+                    // continue from the end of the accepted step: retake it (bit-identical)
+                    fl = (fl & ~F_LOCATE) | F_RETAKE;
+                } else {
+                    double a = COLD(C_EVA), fa = COLD(C_EVFA), b = COLD(C_EVB), fb = COLD(C_EVFB);
+                    if (fc * fb < 0.0) {
+                        a = b;
+                        fa = fb;
+                    } else {
+                        fa *= 0.5;
+                    }
+                    b = COLD(C_EVC);
+                    fb = fc;
+                    COLD(C_EVA) = a;
+                    COLD(C_EVFA) = fa;
+                    COLD(C_EVB) = b;
+                    COLD(C_EVFB) = fb;
+                    COLD(C_EVC) = b - fb * (b - a) / (fb - fa);
+                }
+            } else {
+                bool finite = true;
+#pragma unroll
+                for (int i = 0; i < 5; ++i) finite = finite && isfinite(yn[i]);
+                double h_next = h;
+                bool accept = true;
+                if (!finite) {
+                    fate = KT_FATE_STEPFAIL;
+                    accept = false;
+                } else if constexpr (METHOD == KT_DP45) {
+                    // mean square of err_i / (atol + rtol max(|y_i|, |yn_i|))
+                    double acc = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) {
+                        const double sc = fma(p.rtol, fmax(fabs(y[i]), fabs(yn[i])), p.atol);
+                        const double q = er[i] * rcp(sc);
+                        acc = fma(q, q, acc);
+                    }
+                    const double msq = acc * 0.2;
+                    if (isnan(msq)) {
+                        fate = KT_FATE_STEPFAIL;
+                        accept = false;
+                    } else if (msq > 1.0) {
+                        h *= static_cast<double>(fmaxf(0.2f, step_factor(msq)));
+                        fl |= F_REJECTED;
+                        accept = false;
+                        if (h < 1e-12 * fmax(1.0, fabs(COLD(C_LAM)))) fate = KT_FATE_STEPFAIL;
+                    } else {
+                        double fac = 5.0;
+                        if (msq >= 1e-20) fac = static_cast<double>(fminf(5.0f, fmaxf(0.2f, step_factor(msq))));
+                        if (fl & F_REJECTED) fac = fmin(fac, 1.0);
+                        h_next = h * fac;
+                    }
+                }
+                if (accept) {
+                    if (!(fl & F_RETAKE)) {
+                        ++nsteps;
+                        COLD(C_MAXABS) = fmax(COLD(C_MAXABS), fabs(dg.H));
+                        COLD(C_MAXREL) = fmax(COLD(C_MAXREL), dg.rel);
+                    }
+                    fl &= ~F_RETAKE;
+                    bool locate = false;
+                    // thin disk: sign change of theta - pi/2 over the step
+                    if (p.disk_on && !(fl & F_SKIPDISK)) {
+                        const double ga = y[1] - HALF_PI, gb = yn[1] - HALF_PI;
+                        if (ga * gb < 0.0) {
+                            fl = (fl & ~(F_EVSRC | (0xff << EVIT_SHIFT))) | F_LOCATE;
+                            COLD(C_EVA) = 0.0;
+                            COLD(C_EVFA) = ga;
+                            COLD(C_EVB) = h;
+                            COLD(C_EVFB) = gb;
+                            COLD(C_EVC) = h - gb * h / (gb - ga);
+                            locate = true;
+                        } else if (gb == 0.0) {
+                            if (yn[0] >= p.r_in && yn[0] <= p.r_out) {
+                                fate = KT_FATE_DISK;
+                                r_c = yn[0];
+                                thf = yn[1];
+                                phf = yn[2];
+                            } else {
+                                const int nc = min(((fl >> NCROSS_SHIFT) & 0xff) + 1, 255);
+                                fl = (fl & ~(0xff << NCROSS_SHIFT)) | (nc << NCROSS_SHIFT);
+                            }
+                        }
+                    }
+                    if (!locate && fate < 0) {
+                        if (yn[0] < p.r_cap) {
+                            fate = KT_FATE_CAPTURED;
+                            thf = yn[1];
+                            phf = yn[2];
+                        } else {
+                            if (p.src_on && !(fl & F_SRCDONE)) {
+                                if (y[0] < p.r_src && yn[0] >= p.r_src) {
+                                    const double fa = y[0] - p.r_src, fb = yn[0] - p.r_src;
+                                    fl = (fl & ~(0xff << EVIT_SHIFT)) | F_EVSRC | F_LOCATE;
+                                    COLD(C_EVA) = 0.0;
+                                    COLD(C_EVFA) = fa;
+                                    COLD(C_EVB) = h;
+                                    COLD(C_EVFB) = fb;
+                                    COLD(C_EVC) = h - fb * h / (fb - fa);
+                                    locate = true;
+                                } else {
+                                    COLD(C_PSI) += arc_angle(COLD(C_CS), COLD(C_CC), dg.s, dg.c, yn[2] - y[2]);
+                                }
+                            }
+                            if (!locate) {
+                                if (yn[0] > p.r_esc) {
+                                    fate = KT_FATE_ESCAPED;
+                                    thf = yn[1];
+                                    phf = yn[2];
+                                } else {
+                                    // commit the step
+#pragma unroll
+                                    for (int i = 0; i < 5; ++i) {
+                                        y[i] = yn[i];
+                                        k1[i] = kn[i];
+                                    }
+                                    COLD(C_LAM) += h;
+                                    h = h_next;
+                                    fl &= ~(F_REJECTED | F_SKIPDISK);
+                                    COLD(C_CS) = dg.s;
+                                    COLD(C_CC) = dg.c;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+
+        if (fate >= 0) {
+            const Outputs& o = p.out;
+            if (fl & F_SRCDONE) {
+                defl = COLD(C_PSI);
+                psi = COLD(C_SRCPSI);
+            }
+            o.fate[ray] = static_cast<uint8_t>(fate);
+            p.rc_buf[ray] = r_c;
+            if (o.max_abs_h) o.max_abs_h[ray] = COLD(C_MAXABS);
+            if (o.max_rel_h) o.max_rel_h[ray] = COLD(C_MAXREL);
+            if (o.psi) o.psi[ray] = psi;
+            if (o.deflection) o.deflection[ray] = defl;
+            if (o.theta_f) o.theta_f[ray] = thf;
+            if (o.phi_f) o.phi_f[ray] = phf;
+            if (o.n_cross) o.n_cross[ray] = static_cast<uint8_t>((fl >> NCROSS_SHIFT) & 0xff);
+            if (o.used_fp64) o.used_fp64[ray] = static_cast<uint8_t>(p.from_list ? 1 : 0);
+            if (o.n_steps) o.n_steps[ray] = nsteps;
+            if (o.n_evals) o.n_evals[ray] = nevals;
+            evals_acc += static_cast<unsigned long long>(nevals);
+            ray = -1;
+        }
+    }
+#undef COLD
+
+    // one atomic per wave for the evaluation counter
+    for (int off = 32; off > 0; off >>= 1) evals_acc += __shfl_down(evals_acc, off);
+    if (lane == 0 && evals_acc != 0ull) atomicAdd(p.acc + ACC_EVALS, evals_acc);
+}
+
+// Keplerian redshift and observed intensity of every disk pixel from the
+// crossing radius the trace kernel parked in rc_buf (eq:redshift read as
+// g = 1 / (u^t (E - Omega L)); I_obs = g^3 I_em with I_em = (M/r)^q).
+__global__ void disk_obs_kernel(const Params p) {
+    const int64_t n = p.n_rays;
+    const double NaN = __builtin_nan("");
+    for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < n;
+         k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        double r_hit = NaN, g = NaN, inten = 0.0;
+        if (p.out.fate[k] == KT_FATE_DISK) {
+            double z[5], E, L;
+            camera_state(p, static_cast<int32_t>(k), z, &E, &L);
+            const double rc = p.rc_buf[k];
+            const double sM = sqrt(p.M);
+            const double Om = sM / fma(rc, sqrt(rc), p.a * sM);
+            const double inv_rc = 1.0 / rc;
+            const double gtt = -(1.0 - 2.0 * p.M * inv_rc);
+            const double gtp = -2.0 * p.M * p.a * inv_rc;
+            const double gpp = rc * rc + p.a2 + 2.0 * p.M * p.a2 * inv_rc;
+            const double norm = -gtt - 2.0 * Om * gtp - Om * Om * gpp;  // (u^t)^-2
+            r_hit = rc;
+            g = sqrt(norm) / (E - Om * L);
+            inten = g * g * g * pow(p.M * inv_rc, p.emis_q);
+        }
+        if (p.out.r_hit) p.out.r_hit[k] = r_hit;
+        if (p.out.g) p.out.g[k] = g;
+        if (p.out.intensity) p.out.intensity[k] = inten;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Small kernels
+// ---------------------------------------------------------------------------
+
+__global__ void ws_init_kernel(uint32_t* ticket, unsigned long long* acc, uint32_t* fb_count) {
+    const int t = threadIdx.x;
+    if (t == 0) {
+        *ticket = 0u;
+        *fb_count = 0u;
+    }
+    if (t < 16) acc[t] = 0ull;
+}
+
+__global__ void reset_ticket_kernel(uint32_t* ticket) {
+    if (threadIdx.x == 0) *ticket = 0u;
+}
+
+// Odd multiples of pi that are <= v.
+__device__ __forceinline__ double odd_pi_count(double v) {
+    constexpr double PI = 3.14159265358979323846;
+    return floor((v + PI) / (2.0 * PI));
+}
+
+__global__ void ring_kernel(const double* __restrict__ defl, uint8_t* __restrict__ ring, int32_t nx,
+                            int32_t ny) {
+    const int64_t n = static_cast<int64_t>(nx) * ny;
+    for (int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; p < n;
+         p += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int32_t j = static_cast<int32_t>(p / nx);
+        const int32_t i = static_cast<int32_t>(p - static_cast<int64_t>(j) * nx);
+        const double d = defl[p];
+        uint8_t flag = 0;
+        if (isfinite(d)) {
+            const double k = odd_pi_count(d);
+            if (i + 1 < nx && isfinite(defl[p + 1]) && odd_pi_count(defl[p + 1]) != k) flag = 1;
+            if (j + 1 < ny && isfinite(defl[p + nx]) && odd_pi_count(defl[p + nx]) != k) flag = 1;
+        }
+        ring[p] = flag;
+    }
+}
+
+// Fate histogram into acc[8..15].
+__global__ void fate_hist_kernel(const uint8_t* __restrict__ fate, int64_t n, unsigned long long* acc) {
+    __shared__ unsigned int hist[8];
+    if (threadIdx.x < 8) hist[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; p < n;
+         p += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        atomicAdd(&hist[fate[p] & 7], 1u);
+    __syncthreads();
+    if (threadIdx.x < 8 && hist[threadIdx.x]) atomicAdd(acc + 8 + threadIdx.x, static_cast<unsigned long long>(hist[threadIdx.x]));
+}
+
+__global__ void stats_kernel(const unsigned long long* acc, const uint32_t* fb_count, int64_t n_rays,
+                             kt_stats* out) {
+    if (threadIdx.x == 0) {
+        out->rays = static_cast<uint64_t>(n_rays);
+        out->evals = acc[ACC_EVALS];
+        out->evals_fp32 = acc[ACC_EVALS_FP32];
+        out->fallback_rays = *fb_count;
+        for (int k = 0; k < 8; ++k) out->fate_count[k] = acc[8 + k];
+    }
+}
+
+__global__ void init_rays_kernel(const Params p, double* state, uint8_t* invalid) {
+    const int64_t n = p.n_rays;
+    for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < n;
+         k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        double z[5], E, L;
+        const bool ok = camera_state(p, static_cast<int32_t>(k), z, &E, &L);
+        for (int c = 0; c < 5; ++c) state[c * n + k] = z[c];
+        state[5 * n + k] = E;
+        state[6 * n + k] = L;
+        invalid[k] = ok ? 0 : 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+
+static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
+
+static int small_grid(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    if (g > 4096) g = 4096;
+    return g < 1 ? 1 : static_cast<int>(g);
+}
+
+int launch_ws_init(const Params& p, void* stream) {
+    hipLaunchKernelGGL(ws_init_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), p.ticket,
+                       p.acc, p.fb_count);
+    return check_launch();
+}
+
+int launch_reset_ticket(const Params& p, void* stream) {
+    hipLaunchKernelGGL(reset_ticket_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream),
+                       p.ticket);
+    return check_launch();
+}
+
+int launch_trace(const Params& p, int grid, int block, void* stream) {
+    if (p.method == KT_DP45)
+        hipLaunchKernelGGL(trace_kernel<KT_DP45>, dim3(grid), dim3(block), 0,
+                           static_cast<hipStream_t>(stream), p);
+    else
+        hipLaunchKernelGGL(trace_kernel<KT_RK4_S>, dim3(grid), dim3(block), 0,
+                           static_cast<hipStream_t>(stream), p);
+    return check_launch();
+}
+
+int trace_max_blocks_per_cu(const Params& p, int block) {
+    int nb = 0;
+    hipError_t e = (p.method == KT_DP45)
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<KT_DP45>, block, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<KT_RK4_S>, block, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+int launch_disk_obs(const Params& p, void* stream) {
+    hipLaunchKernelGGL(disk_obs_kernel, dim3(small_grid(p.n_rays, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), p);
+    return check_launch();
+}
+
+int launch_ring(const Params& p, void* stream) {
+    const int64_t n = p.n_rays;
+    hipLaunchKernelGGL(ring_kernel, dim3(small_grid(n, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), p.out.deflection, p.out.ring, p.nx, p.ny);
+    return check_launch();
+}
+
+int launch_stats(const Params& p, void* stream) {
+    const int64_t n = p.n_rays;
+    hipLaunchKernelGGL(fate_hist_kernel, dim3(small_grid(n, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), p.out.fate, n, p.acc);
+    if (check_launch()) return -1;
+    hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), p.acc,
+                       p.fb_count, n, p.out.stats);
+    return check_launch();
+}
+
+int launch_init_rays(const Params& p, double* state, uint8_t* invalid, void* stream) {
+    hipLaunchKernelGGL(init_rays_kernel, dim3(small_grid(p.n_rays, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), p, state, invalid);
+    return check_launch();
+}
+
+}  // namespace kt

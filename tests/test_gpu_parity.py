@@ -1,0 +1,202 @@
+"""GPU library vs CPU oracle, element by element, through the C ABI.
+
+Every test prints the case it runs (and flushes) before touching the GPU.
+Sizes are small enough for the oracle to finish in seconds while spanning
+many waves and a ragged tail; the full-size image is checked on a sampled
+set of pixels the oracle traces one by one.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2202_00086_amd import workloads as W
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(*what):
+    print("[gpu-case]", *what, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2202_00086_amd import kerrtrace
+    return kerrtrace
+
+
+def gpu_render(K, params, launch=None, want=None):
+    import torch
+    r = K.Renderer(device="cuda:0", launch=launch, **params) if want is None else \
+        K.Renderer(device="cuda:0", launch=launch, want=want, **params)
+    out = r.render()
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items() if k != "stats"}
+    res["stats"] = K.read_stats(out)
+    return res
+
+
+def ora_render(params, pix=None):
+    return O.trace_pixels(O.Setup(**params), pix)
+
+
+# ---------------------------------------------------------------------------
+
+def test_init_rays_match_oracle(K):
+    import torch
+    for params in [W.kerr_ring(0.9, n=64), W.schwarzschild_disk(n=37), W.schwarzschild_shadow_64(),
+                   dict(W.kerr_ring(0.998, n=16), r_obs=40.0, fov_x=45.0, fov_y=45.0)]:
+        _announce("init_rays", params["a"], params["nx"], params["r_obs"])
+        state, invalid = K.init_rays(**params)
+        torch.cuda.synchronize()
+        st = state.cpu().numpy()
+        inv = invalid.cpu().numpy()
+        s = O.Setup(**params)
+        for p in range(params["nx"] * params["ny"]):
+            x, y = O.pixel_xy(s, p % params["nx"], p // params["nx"])
+            want, bad = O.camera_ray(params["M"], params["a"], params["r_obs"], params["incl"], x, y)
+            assert bool(inv[p]) == bad
+            if not bad:
+                np.testing.assert_allclose(st[:, p], want, rtol=4e-16, atol=1e-300)
+
+
+def test_schwarzschild_shadow_64(K):
+    """a = 0, 64x64, fixed-step RK4 in s: identical fates (872 captured) and
+    max |H| agreement with the oracle."""
+    params = W.schwarzschild_shadow_64()
+    _announce("schwarzschild_shadow_64")
+    g = gpu_render(K, params)
+    o = ora_render(params)
+    np.testing.assert_array_equal(g["fate"], o["fate"])
+    assert (g["fate"] == K.CAPTURED).sum() == 872
+    np.testing.assert_array_equal(g["n_steps"], o["n_steps"])
+    mask = np.ones(64 * 64, bool)
+    P.check_max_h(g, o, "max_abs_h", mask)
+    P.check_max_h(g, o, "max_rel_h", mask)
+    assert g["stats"].rays == 4096
+    assert list(g["stats"].fate_count[:6]) == list(np.bincount(g["fate"], minlength=6)[:6])
+    assert g["stats"].evals == g["n_evals"].sum()
+
+
+@pytest.mark.parametrize("a", [0.5, 0.9, 0.998])
+def test_kerr_ring_128(K, a):
+    """Kerr shadow + deflection diagnostics, i = 60 deg, +-12M at 128x128."""
+    params = W.kerr_ring(a, n=128)
+    _announce("kerr_ring_128", a)
+    g = gpu_render(K, params)
+    o = ora_render(params)
+    P.check_fates(g["fate"], o["fate"], 128, 128)
+    m = P.value_mask(g, o, 128, 128)
+    assert m.sum() > 0.9 * 128 * 128
+    P.check_values(g, o, "deflection", m, rtol=1e-8)
+    P.check_values(g, o, "psi", m & (o["psi"] > 1e-6), rtol=1e-7)
+    P.check_values(g, o, "theta_f", m, rtol=1e-8)
+    P.check_max_h(g, o, "max_rel_h", m)
+    P.check_max_h(g, o, "max_abs_h", m, abs_floor=1e-12)
+    # ring flags follow the same rule as the oracle's post-pass
+    np.testing.assert_array_equal(g["ring"], O.ring_flags(128, 128, g["deflection"]))
+    steps_rel = np.abs(g["n_steps"][m].astype(float) - o["n_steps"][m]) / o["n_steps"][m]
+    assert np.median(steps_rel) == 0.0 and steps_rel.max() < 0.02
+
+
+@pytest.mark.parametrize("case", ["schw_80", "kerr_60"])
+def test_disk_images(K, case):
+    """Thin Keplerian disk: hit radius, redshift and intensity."""
+    if case == "schw_80":
+        params = W.schwarzschild_disk(n=160)
+    else:
+        params = W.kerr_disk(a=0.9, incl_deg=60.0, n=128, r_in=2.320883)
+    _announce("disk", case)
+    g = gpu_render(K, params)
+    o = ora_render(params)
+    n = params["nx"]
+    P.check_fates(g["fate"], o["fate"], n, n)
+    m = P.value_mask(g, o, n, n)
+    disk = m & (o["fate"] == O.DISK)
+    assert disk.sum() > 0.1 * n * n
+    for key in ("r_hit", "g", "intensity"):
+        P.check_values(g, o, key, disk, rtol=1e-8)
+    np.testing.assert_array_equal(g["n_cross"][m], o["n_cross"][m])
+    nd = ~np.isin(g["fate"], [O.DISK])
+    assert np.isnan(g["r_hit"][nd]).all() and (g["intensity"][nd] == 0).all()
+    assert (g["n_cross"][disk] == 1).any()  # secondary images present
+
+
+def test_ragged_and_tiny_images(K):
+    for nx, ny in [(1, 1), (37, 23), (65, 3), (3, 129)]:
+        params = dict(W.kerr_ring(0.7, n=8), nx=nx, ny=ny)
+        _announce("ragged", nx, ny)
+        g = gpu_render(K, params)
+        o = ora_render(params)
+        P.check_fates(g["fate"], o["fate"], nx, ny, min_allowed=1)
+        m = P.value_mask(g, o, nx, ny)
+        P.check_values(g, o, "deflection", m, rtol=1e-8)
+
+
+def test_launch_shapes_are_bit_identical(K):
+    """Per-ray arithmetic does not depend on which lane or wave runs the ray:
+    persistent / one-ray-per-lane / queue batch 1 / small blocks give
+    bit-identical outputs."""
+    params = dict(W.kerr_ring(0.9, n=96), disk_on=1, r_in=2.320883, r_out=30.0)
+    _announce("launch shapes")
+    base = gpu_render(K, params)
+    shapes = [K.kt_launch(0, 256, 0, 32), K.kt_launch(1, 64, 1, 1), K.kt_launch(1, 128, 2, 7),
+              K.kt_launch(1, 256, 1, 4096)]
+    for ln in shapes:
+        _announce("launch", ln.persistent, ln.block, ln.blocks_per_cu, ln.batch)
+        g = gpu_render(K, params, launch=ln)
+        for key, v in base.items():
+            if key == "stats":
+                assert g[key].evals == v.evals
+                continue
+            np.testing.assert_array_equal(g[key].view(np.uint8), v.view(np.uint8), err_msg=key)
+
+
+def test_max_steps_forces_fate(K):
+    params = dict(W.kerr_ring(0.9, n=32), max_steps=10)
+    _announce("max_steps=10")
+    g = gpu_render(K, params)
+    assert (g["fate"] == K.MAXSTEPS).all()
+    assert (g["n_steps"] == 10).all()
+    o = ora_render(params)
+    np.testing.assert_array_equal(g["n_steps"], o["n_steps"])
+
+
+def test_invalid_pixels(K):
+    """Image-plane points with x^2 + y^2 >= r0^2 have no real p_r."""
+    params = dict(W.kerr_ring(0.5, n=16), r_obs=20.0, fov_x=25.0, fov_y=25.0, r_escape=30.0, r_src=25.0)
+    _announce("invalid pixels")
+    g = gpu_render(K, params)
+    o = ora_render(params)
+    np.testing.assert_array_equal(g["fate"] == K.INVALID, o["fate"] == O.INVALID)
+    assert (g["fate"] == K.INVALID).sum() > 0
+
+
+def test_full_size_kerr_ring_sampled(K):
+    """1024x1024, a = 0.9 in the launch configuration the benchmark times:
+    a fixed sample of pixels against the oracle traced one by one."""
+    params = W.kerr_ring(0.9, n=1024)
+    _announce("kerr_ring_1024 sampled")
+    g = gpu_render(K, params)
+    rng = np.random.default_rng(2022)
+    pix = np.sort(rng.choice(1024 * 1024, size=400, replace=False)).astype(np.int32)
+    o = ora_render(params, pix)
+    img_fate = g["fate"].reshape(1024, 1024)
+    near = P.boundary_mask(img_fate).ravel()[pix]
+    same = g["fate"][pix] == o["fate"]
+    assert (same | near).all()
+    ok = same & ~near
+    for key in ("deflection", "theta_f"):
+        e = P.rel_err(g[key][pix][ok], o[key][ok])
+        assert np.nanmax(e) < 1e-8, key
+    st = g["stats"]
+    assert st.rays == 1024 * 1024 and sum(st.fate_count) == 1024 * 1024
+    assert st.evals == g["n_evals"].astype(np.int64).sum()
+    assert (g["fate"] <= K.DISK).all()
+    assert np.nanmax(g["max_rel_h"]) < 1e-10
