@@ -43,20 +43,23 @@ __device__ __forceinline__ double arc_angle(double s1, double c1, double s2, dou
 // Returns false when x^2 + y^2 >= r0^2 (no real p_r).
 __device__ __forceinline__ bool camera_state(const Params& p, int32_t ray, double z[5], double* E,
                                              double* L) {
+    // separate roundings, no FMA: the pixel centre is the same double the
+    // plain expression -fov + (i + 1/2) dx gives on any IEEE machine
+#pragma clang fp contract(off)
     const int32_t j = ray / p.nx;
     const int32_t i = ray - j * p.nx;
-    const double x = __dadd_rn(-p.fov_x, __dmul_rn(static_cast<double>(i) + 0.5, p.dx));
-    const double y = __dadd_rn(-p.fov_y, __dmul_rn(static_cast<double>(j) + 0.5, p.dy));
+    const double x = -p.fov_x + (static_cast<double>(i) + 0.5) * p.dx;
+    const double y = -p.fov_y + (static_cast<double>(j) + 0.5) * p.dy;
     const double Pth = y / p.r0;   // observer-frame P^theta with P^t = 1
     const double Pph = -x / p.r0;  // observer-frame P^phi
-    const double rad = __dsub_rn(__dsub_rn(1.0, __dmul_rn(Pth, Pth)), __dmul_rn(Pph, Pph));
-    *E = __dadd_rn(p.E0, __dmul_rn(x, p.cE));
-    *L = __dmul_rn(x, p.cL);
+    const double rad = 1.0 - Pth * Pth - Pph * Pph;
+    *E = p.E0 + x * p.cE;
+    *L = x * p.cL;
     z[0] = p.r0;
     z[1] = p.incl;
     z[2] = 0.0;
-    z[3] = rad > 0.0 ? -sqrt(__dmul_rn(p.g_rr, rad)) : 0.0;
-    z[4] = __dmul_rn(y, p.cth);
+    z[3] = rad > 0.0 ? -sqrt(p.g_rr * rad) : 0.0;
+    z[4] = y * p.cth;
     return rad > 0.0;
 }
 

@@ -71,10 +71,19 @@ def check_values(gpu, ora, key, mask, rtol=1e-8):
     return 0.0
 
 
-def check_max_h(gpu, ora, key, mask, abs_floor=1e-13, rel=1e-2):
+def check_max_h(gpu, ora, key, mask, abs_floor=1e-13, rel=1e-2, budget=0.0):
+    """Per pixel: both maxima within `budget`, or agreement to
+    abs_floor + rel * max.  With adaptive steps the two sides' step sequences
+    part at rounding level, so the truncation residues that set max |H| agree
+    only statistically: the percentiles of the two distributions must then
+    agree to 25%."""
     a = np.asarray(gpu[key])[mask]
     b = np.asarray(ora[key])[mask]
     d = np.abs(a - b)
     lim = abs_floor + rel * np.maximum(np.abs(a), np.abs(b))
-    bad = d > lim
+    bad = (d > lim) & ~((a <= budget) & (b <= budget))
     assert not bad.any(), f"{key}: {bad.sum()} pixels disagree, worst {a[bad][:3]} vs {b[bad][:3]}"
+    if budget > 0.0 and a.size:
+        for q in (50, 90, 99):
+            pa, pb = np.percentile(a, q), np.percentile(b, q)
+            assert abs(pa - pb) <= 0.25 * max(pa, pb) + abs_floor, (key, q, pa, pb)
