@@ -1,0 +1,185 @@
+"""Benchmark: rays/s and RK stage-evals/s of one 1024x1024 Kerr image on one
+MI355X.
+
+Workload (the headline configuration): Kerr a = 0.9, M = 1, observer at
+r = 1000M, inclination 60 deg, image plane +-12M at 1024x1024, Dormand-Prince
+5(4) at rtol = atol = 1e-12 in FP64, point source at r_src = 1000M behind the
+hole (deflection angle and ring mask), capture at r < r_+ + 0.01M, escape at
+r > 1100M.  Inputs are synthetic camera parameters; nothing is read from
+disk.
+
+One step = one kt_render call: the persistent trace kernel plus its small
+post-passes (redshift, ring flags, stats).  W untimed warmup steps, then K
+timed steps between two device synchronisations; HIP events on the stream
+the kernels run on give the per-launch duration used for the roofline.
+
+Prints ONE JSON line.  --gpus above 1 is refused: the library runs on one GPU.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "rays/s & RK stage-evals/s, 1024² Kerr a=0.9; mixed vs FP64 at |H|≤1e-10"
+
+# Algorithmic FP64 work, counted on the formulas the method evaluates
+# (+, -, x, /, sqrt = 1; FMA = 2; sincos, atan2, pow = 2), independent of how
+# the kernel computes them (e.g. three reciprocals count 3 even though the
+# kernel derives them from one):
+#   Hamiltonian RHS in Carter form                              58 per evaluation
+#   per Dormand-Prince step (six evaluations): stage sums and
+#   error estimate 290, error norm and step-size control 37,
+#   constraint diagnostics 7                                   334 per step
+#   swept angle between successive positions (source on)        22 per step
+RHS_FLOP = 58
+STEP_FLOP = 290 + 37 + 7
+ARC_FLOP = 22
+PEAK_FP64_VECTOR = 78.6e12  # MI355X FP64 vector, FLOP/s
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "trace_kernel_kerr_ring_1024_a0.9_counters.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_00086_amd", "csrc", f)
+                  for f in ("kt_device.h", "kt_trace.hip")]
+
+
+def flop_per_eval(src_on):
+    return RHS_FLOP + (STEP_FLOP + (ARC_FLOP if src_on else 0)) / 6.0
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per trace launch from the committed counter summary, if it
+    was taken on the current kernel source."""
+    if not os.path.exists(PROFILE_COUNTERS):
+        return None
+    vals = {}
+    for line in open(PROFILE_COUNTERS):
+        if ":" in line and line.strip().startswith("-"):
+            k, v = line.strip().lstrip("- ").split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(params, rows_every=16):
+    """The oracle, as it stands, on rows j = 0 mod rows_every of the image."""
+    import numpy as np
+
+    import oracle as O
+    try:
+        n_avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n_avail = os.cpu_count() or 1
+    threads = min(n_avail, int(os.environ.get("OMP_NUM_THREADS", n_avail)))
+    nx, ny = params["nx"], params["ny"]
+    pix = (np.arange(0, ny, rows_every)[:, None] * nx + np.arange(nx)[None, :]).ravel().astype(np.int32)
+    t0 = time.perf_counter()
+    o = O.trace_pixels(O.Setup(**params), pix, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": pix.size / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"rows j = 0 mod {rows_every} of the same image ({pix.size} rays, "
+                      f"{dt:.1f} s wall on {threads} threads; plain C FP64 oracle, -O2, OpenMP)",
+            "stage_evals_per_s": float(o["n_evals"].astype(np.int64).sum()) / dt}
+
+
+def run_form(K, torch, params, steps, warmup, launch=None):
+    r = K.Renderer(device="cuda:0", launch=launch, **params)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        r.render(stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        r.render(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [a.elapsed_time(b) for a, b in ev]
+    st = K.read_stats(r.out)
+    n = r.n
+    return {"wall_s": wall, "ms_per_step": 1e3 * wall / steps,
+            "launch_ms": sum(launch_ms) / len(launch_ms), "launch_ms_min": min(launch_ms),
+            "rays": n, "evals": int(st.evals), "fates": [int(c) for c in st.fate_count[:6]],
+            "max_rel_h": float(r.out["max_rel_h"].max().item()),
+            "p999_rel_h": float(torch.quantile(r.out["max_rel_h"].float()[::16], 0.999).item())}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-forms", action="store_true", help="skip the extra forms")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported: the ray tracer runs on one GPU "
+              "(rays are independent; see the sharding notes in the design document)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2202_00086_amd import kerrtrace as K
+    from paper_2202_00086_amd import workloads as W
+
+    params = W.kerr_ring(0.9, n=1024, rtol=1e-12)
+    main_form = run_form(K, torch, params, args.steps, args.warmup)
+    secs = main_form["ms_per_step"] / 1e3
+    rays_per_s = main_form["rays"] / secs
+    evals_per_s = main_form["evals"] / secs
+
+    fpe = flop_per_eval(src_on=True)
+    flop = main_form["evals"] * fpe
+    achieved = flop / (main_form["launch_ms"] / 1e3)
+    traffic = traffic_from_profile()
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
+                "flop_per_eval": fpe, "evals_per_launch": main_form["evals"],
+                "launch_ms": main_form["launch_ms"]}
+
+    forms = {}
+    if not args.no_forms:
+        p11 = W.kerr_ring(0.9, n=1024, rtol=1e-11)
+        f = run_form(K, torch, p11, max(3, args.steps // 4), 1)
+        forms["fp64_rtol1e-11"] = {"rays_per_s": f["rays"] / (f["ms_per_step"] / 1e3),
+                                   "stage_evals_per_s": f["evals"] / (f["ms_per_step"] / 1e3),
+                                   "ms_per_step": f["ms_per_step"], "max_rel_h": f["max_rel_h"],
+                                   "p999_rel_h": f["p999_rel_h"]}
+
+    out = {"metric": METRIC, "value": rays_per_s, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": main_form["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "Kerr a=0.9, 1024x1024, i=60 deg, r_obs=1000M, +-12M, DP45 "
+                                  "rtol=atol=1e-12, FP64, point source r_src=1000M",
+                      "rays": main_form["rays"], "precision": "fp64", "integrator": "dp45"},
+           "stage_evals_per_s": evals_per_s, "evals_per_ray": main_form["evals"] / main_form["rays"],
+           "max_rel_h": main_form["max_rel_h"], "p999_rel_h": main_form["p999_rel_h"],
+           "fates": main_form["fates"], "roofline": roofline,
+           "kernel_source_sha256": kernel_source_hash()}
+    if forms:
+        out["forms"] = forms
+    if not args.no_cpu:
+        cb = cpu_baseline(params)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

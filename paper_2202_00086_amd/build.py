@@ -21,13 +21,13 @@ FLAGS = [
 ]
 
 
-def build(verbose=False, extra=()):
-    cmd = [HIPCC, *FLAGS, *extra, "-o", LIB + ".tmp", *SOURCES]
+def build(verbose=False, extra=(), out=LIB):
+    cmd = [HIPCC, *FLAGS, *extra, "-o", out + ".tmp", *SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

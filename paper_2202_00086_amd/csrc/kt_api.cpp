@@ -244,6 +244,7 @@ int kt_render_ex(const kt_camera* camera, const kt_spacetime* spacetime, const k
     p.acc = reinterpret_cast<unsigned long long*>(ws + kt::WS_ACC);
     p.fb_count = reinterpret_cast<uint32_t*>(ws + kt::WS_FB_COUNT);
     p.rc_buf = reinterpret_cast<double*>(ws + kt::WS_RC);
+    p.ws_params = reinterpret_cast<kt::Params*>(ws + kt::WS_PARAMS);
     p.fb_list = reinterpret_cast<uint32_t*>(ws + kt::ws_fb_list_offset(static_cast<size_t>(p.n_rays)));
     p.persistent = ln.persistent ? 1 : 0;
     p.batch = ln.batch;

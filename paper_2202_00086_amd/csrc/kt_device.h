@@ -89,6 +89,54 @@ __device__ __forceinline__ double atan2_upper(double y, double x) {
     return PI + atan_unit(y / x);
 }
 
+// sin and cos of a small angle, |x| <= 1/2, from their Taylor series (sin
+// through x^15, cos through x^16: truncation below 1e-19); no reduction.
+__device__ __forceinline__ void sincos_small(double x, double* s_out, double* c_out) {
+    const double x2 = x * x;
+    double ps = -1.0 / 1307674368000.0;
+    ps = fma(ps, x2, 1.0 / 6227020800.0);
+    ps = fma(ps, x2, -1.0 / 39916800.0);
+    ps = fma(ps, x2, 1.0 / 362880.0);
+    ps = fma(ps, x2, -1.0 / 5040.0);
+    ps = fma(ps, x2, 1.0 / 120.0);
+    ps = fma(ps, x2, -1.0 / 6.0);
+    *s_out = fma(ps * x2, x, x);
+    double pc = 1.0 / 20922789888000.0;
+    pc = fma(pc, x2, -1.0 / 87178291200.0);
+    pc = fma(pc, x2, 1.0 / 479001600.0);
+    pc = fma(pc, x2, -1.0 / 3628800.0);
+    pc = fma(pc, x2, 1.0 / 40320.0);
+    pc = fma(pc, x2, -1.0 / 720.0);
+    pc = fma(pc, x2, 1.0 / 24.0);
+    pc = fma(pc, x2, -0.5);
+    *c_out = fma(pc, x2, 1.0);
+}
+
+// Coefficient k of the series asin x = sum_k c_k x^(2k+1),
+// c_k = (2k)! / (4^k (k!)^2 (2k+1)), from c_0 = 1 and
+// c_k = c_(k-1) (2k-1)^2 / ((2k)(2k+1)).
+constexpr double asin_coef(int k) {
+    double c = 1.0;
+    for (int j = 1; j <= k; ++j) c *= static_cast<double>((2 * j - 1) * (2 * j - 1)) / ((2.0 * j) * (2.0 * j + 1));
+    return c;
+}
+
+// asin x for 0 <= x <= 1/16 from the series through x^15 (truncation below
+// 1e-19 relative).
+__device__ __forceinline__ double asin_small(double x) {
+    constexpr double C1 = asin_coef(1), C2 = asin_coef(2), C3 = asin_coef(3), C4 = asin_coef(4),
+                     C5 = asin_coef(5), C6 = asin_coef(6), C7 = asin_coef(7);
+    const double x2 = x * x;
+    double p = C7;
+    p = fma(p, x2, C6);
+    p = fma(p, x2, C5);
+    p = fma(p, x2, C4);
+    p = fma(p, x2, C3);
+    p = fma(p, x2, C2);
+    p = fma(p, x2, C1);
+    return fma(p * x2, x, x);
+}
+
 // ---------------------------------------------------------------------------
 // Per-launch and per-ray constants
 // ---------------------------------------------------------------------------
@@ -139,9 +187,15 @@ __device__ __forceinline__ void rhs(const Spacetime& st, const RayConst& rc, con
     const double rho2 = r2 + st.a2;
     const double Sig = fma(st.a2 * c, c, r2);
     const double Del = fma(r, r - 2.0 * st.M, st.a2);
-    const double inv_s = rcp(s);
-    const double inv_Sig = rcp(Sig);
-    const double inv_Del = rcp(Del);
+    // 1/sin, 1/Sigma, 1/Delta (and 1/r for the s-time scaling) from one
+    // reciprocal of their product
+    const double SD = Sig * Del;
+    const double P = S_TIME ? SD * s * r : SD * s;
+    const double q = rcp(P);
+    const double inv_s = S_TIME ? SD * r * q : SD * q;
+    const double inv_SD = S_TIME ? s * r * q : s * q;
+    const double inv_Sig = Del * inv_SD;
+    const double inv_Del = Sig * inv_SD;
     const double W = fma(rho2, rc.E, -rc.aL);
     const double T = fma(rc.L, inv_s, -rc.aE * s);
     const double Wd = W * inv_Del;
@@ -160,7 +214,7 @@ __device__ __forceinline__ void rhs(const Spacetime& st, const RayConst& rc, con
     double d3 = fma(4.0 * r, H, -dKdr) * hs;
     double d4 = -fma(T, dT, st.two_a2 * H * s * c) * inv_Sig;
     if (S_TIME) {
-        const double w = Del * rcp(r);
+        const double w = Del * (s * SD * q);  // Delta / r
         d0 *= w;
         d1 *= w;
         d2 *= w;

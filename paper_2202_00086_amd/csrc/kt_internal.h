@@ -12,7 +12,9 @@ namespace kt {
 constexpr size_t WS_TICKET = 0;       // uint32 ray ticket
 constexpr size_t WS_ACC = 64;         // uint64[16]: evals, evals_fp32, -, fate histogram at 8..15
 constexpr size_t WS_FB_COUNT = 192;   // uint32 fallback list length
-constexpr size_t WS_RC = 256;         // double[n_rays] disk crossing radius per ray
+constexpr size_t WS_PARAMS = 256;     // device copy of Params (read by the kernels' cold paths)
+constexpr size_t WS_PARAMS_MAX = 1792;
+constexpr size_t WS_RC = WS_PARAMS + WS_PARAMS_MAX;  // double[n_rays] disk crossing radius per ray
 // then, for KT_MIXED only, uint32[n_rays] ray ids for the FP64 re-run
 inline size_t ws_fb_list_offset(size_t n_rays) { return (WS_RC + 8 * n_rays + 255) & ~size_t(255); }
 constexpr int ACC_EVALS = 0, ACC_EVALS_FP32 = 1;
@@ -57,13 +59,26 @@ struct Params {
     uint32_t* fb_list;
     uint32_t* fb_count;
     double* rc_buf;
+    Params* ws_params;  // where ws_init leaves the device copy of this struct
     // launch
     int32_t persistent, batch;
     int32_t from_list;  // take ray ids from fb_list[0 .. *fb_count)
 };
 
+static_assert(sizeof(Params) <= WS_PARAMS_MAX, "Params must fit its workspace slot");
+
+// The values the trace kernel's inner loop reads every step, passed by value
+// so they sit in scalar registers; everything else is read through `cold`.
+struct Hot {
+    double M, a, a2, two_a2;
+    double rtol, atol, r_cap, r_esc, r_src, r_in, r_out;
+    int32_t disk_on, src_on;
+    int32_t max_steps, max_evals;
+    const Params* cold;  // the workspace copy of Params
+};
+
 // Host-side launchers (kt_trace.hip).
-int launch_ws_init(const Params& p, void* stream);
+int launch_ws_init(const Params& p, void* stream);  // also copies p into the workspace
 int launch_trace(const Params& p, int grid, int block, void* stream);
 int launch_reset_ticket(const Params& p, void* stream);
 int launch_ring(const Params& p, void* stream);

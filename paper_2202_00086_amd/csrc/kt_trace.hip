@@ -18,7 +18,7 @@
 #include "kt_internal.h"
 
 #ifndef KT_WAVES_PER_EU
-#define KT_WAVES_PER_EU 4
+#define KT_WAVES_PER_EU 2
 #endif
 
 namespace kt {
@@ -26,7 +26,7 @@ namespace kt {
 constexpr double HALF_PI = 1.57079632679489661923;
 
 // Great-circle angle between the directions (theta1, phi1) and
-// (theta2, phi1 + dphi), given sin/cos of the thetas.
+// (theta2, phi1 + dphi), given sin/cos of the thetas: atan2(|n1 x n2|, n1.n2).
 __device__ __forceinline__ double arc_angle(double s1, double c1, double s2, double c2, double dphi) {
     double sd, cd;
     sincos_fast(dphi, &sd, &cd);
@@ -37,6 +37,22 @@ __device__ __forceinline__ double arc_angle(double s1, double c1, double s2, dou
     const double cr = sqrt(fma(cx, cx, fma(cy, cy, cz * cz)));
     const double dt = fma(s1 * s2, cd, c1 * c2);
     return atan2_upper(cr, dt);
+}
+
+// The same angle for the short arcs of single steps: 2 asin(|n2 - n1| / 2)
+// with the small-angle series.  Returns a negative value when the arc is
+// outside the range of the series (|dphi| > 1/2 or chord/2 > 1/16); the
+// caller then takes arc_angle.
+__device__ __forceinline__ double arc_angle_short(double s1, double c1, double s2, double c2,
+                                                  double dphi) {
+    if (!(fabs(dphi) <= 0.5)) return -1.0;
+    double sd, cd;
+    sincos_small(dphi, &sd, &cd);
+    const double dx = fma(s2, cd, -s1);
+    const double dy = s2 * sd;
+    const double dz = c2 - c1;
+    const double h = 0.5 * sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
+    return h <= 0.0625 ? 2.0 * asin_small(h) : -1.0;
 }
 
 // Initial state of pixel `ray` (second eq:momentums with p_r ingoing).
@@ -106,23 +122,43 @@ __device__ __forceinline__ float step_factor(double msq) {
     return 0.9f * __builtin_amdgcn_exp2f(-0.1f * __builtin_amdgcn_logf(static_cast<float>(msq)));
 }
 
+// Mean square of err_i / sc_i over the five components.  The five
+// reciprocals come from one hardware reciprocal estimate of the product of
+// the scales (relative error ~5e-8: this number only steers the step size).
+__device__ __forceinline__ double error_msq(const double er[5], const double sc[5]) {
+    const double p01 = sc[0] * sc[1], p34 = sc[3] * sc[4];
+    const double p012 = p01 * sc[2];
+    const double q = __builtin_amdgcn_rcp(p012 * p34);
+    const double q012 = q * p34;           // 1 / (sc0 sc1 sc2)
+    const double q34 = q * p012;           // 1 / (sc3 sc4)
+    const double q01 = q012 * sc[2];       // 1 / (sc0 sc1)
+    const double e0 = er[0] * (q01 * sc[1]);
+    const double e1 = er[1] * (q01 * sc[0]);
+    const double e2 = er[2] * (q012 * p01);
+    const double e3 = er[3] * (q34 * sc[4]);
+    const double e4 = er[4] * (q34 * sc[3]);
+    return 0.2 * fma(e0, e0, fma(e1, e1, fma(e2, e2, fma(e3, e3, e4 * e4))));
+}
+
 template <int METHOD>
 __global__ void __launch_bounds__(BLOCK_MAX) __attribute__((amdgpu_waves_per_eu(KT_WAVES_PER_EU)))
-trace_kernel(const Params p) {
+trace_kernel(const Hot hp) {
     constexpr int EVALS_PER_STEP = (METHOD == KT_DP45) ? 6 : 4;
     constexpr bool S_TIME = (METHOD == KT_RK4_S);
     __shared__ double cold[N_COLD][BLOCK_MAX];
     const int tid = threadIdx.x;
 #define COLD(f) cold[f][tid]
+    // cold parameters are read from the workspace copy where needed
+    const Params& P = *hp.cold;
 
-    const Spacetime st{p.M, p.a, p.a2, p.two_a2};
+    const Spacetime st{hp.M, hp.a, hp.a2, hp.two_a2};
     const uint32_t lane = __lane_id();
-    const uint32_t n_total = p.from_list ? *p.fb_count : static_cast<uint32_t>(p.n_rays);
+    const uint32_t n_total = P.from_list ? *P.fb_count : static_cast<uint32_t>(P.n_rays);
 
     // this wave's queue of ray ids [q_next, q_end)
     uint32_t q_next, q_end;
     bool exhausted;
-    if (p.persistent) {
+    if (P.persistent) {
         q_next = q_end = 0;
         exhausted = false;
     } else {
@@ -149,22 +185,22 @@ trace_kernel(const Params p) {
                 if (exhausted) break;
                 const int leader = __ffsll(idle) - 1;
                 uint32_t base = 0;
-                if (static_cast<int>(lane) == leader) base = atomicAdd(p.ticket, static_cast<uint32_t>(p.batch));
+                if (static_cast<int>(lane) == leader) base = atomicAdd(P.ticket, static_cast<uint32_t>(P.batch));
                 base = static_cast<uint32_t>(__shfl(static_cast<int>(base), leader));
                 if (base >= n_total) {
                     exhausted = true;
                     break;
                 }
                 q_next = base;
-                q_end = min(base + static_cast<uint32_t>(p.batch), n_total);
+                q_end = min(base + static_cast<uint32_t>(P.batch), n_total);
             }
             const uint32_t rank = static_cast<uint32_t>(__popcll(idle & ((1ull << lane) - 1ull)));
             const uint32_t avail = q_end - q_next;
             if (ray < 0 && rank < avail) {
                 const uint32_t slot = q_next + rank;
-                ray = p.from_list ? static_cast<int32_t>(p.fb_list[slot]) : static_cast<int32_t>(slot);
-                fl = camera_state(p, ray, y, &E, &L) ? (F_VALID | F_FRESH) : 0;
-                h = (METHOD == KT_DP45) ? p.h_init : p.h_fixed;
+                ray = P.from_list ? static_cast<int32_t>(P.fb_list[slot]) : static_cast<int32_t>(slot);
+                fl = camera_state(P, ray, y, &E, &L) ? (F_VALID | F_FRESH) : 0;
+                h = (METHOD == KT_DP45) ? P.h_init : P.h_fixed;
                 nsteps = 0;
                 nevals = 0;
             }
@@ -196,7 +232,7 @@ trace_kernel(const Params p) {
             COLD(C_CS) = dg.s;
             COLD(C_CC) = dg.c;
             fl &= ~F_FRESH;
-        } else if (!(fl & (F_LOCATE | F_RETAKE)) && (nsteps >= p.max_steps || nevals >= p.max_evals)) {
+        } else if (!(fl & (F_LOCATE | F_RETAKE)) && (nsteps >= hp.max_steps || nevals >= hp.max_evals)) {
             fate = KT_FATE_MAXSTEPS;
         } else {
             const bool locating = (fl & F_LOCATE) != 0;
@@ -208,13 +244,13 @@ trace_kernel(const Params p) {
             if (locating) {
                 // Illinois regula falsi on the event function
                 const bool src = (fl & F_EVSRC) != 0;
-                const double fc = src ? yn[0] - p.r_src : yn[1] - HALF_PI;
-                const double tol = src ? p.src_tol : 1e-14;
+                const double fc = src ? yn[0] - hp.r_src : yn[1] - HALF_PI;
+                const double tol = src ? P.src_tol : 1e-14;
                 const int it = ((fl >> EVIT_SHIFT) & 0xff) + 1;
                 fl = (fl & ~(0xff << EVIT_SHIFT)) | (it << EVIT_SHIFT);
                 if (fabs(fc) <= tol || it >= 64) {
                     if (!src) {
-                        if (yn[0] >= p.r_in && yn[0] <= p.r_out) {
+                        if (yn[0] >= hp.r_in && yn[0] <= hp.r_out) {
                             fate = KT_FATE_DISK;
                             r_c = yn[0];
                             thf = yn[1];
@@ -228,11 +264,11 @@ trace_kernel(const Params p) {
                         double sp, cp;
                         sincos_fast(yn[2], &sp, &cp);
                         const double nx = dg.s * cp, ny = dg.s * sp, nz = dg.c;
-                        const double cx = ny * p.src_n[2] - nz * p.src_n[1];
-                        const double cy = nz * p.src_n[0] - nx * p.src_n[2];
-                        const double cz = nx * p.src_n[1] - ny * p.src_n[0];
+                        const double cx = ny * P.src_n[2] - nz * P.src_n[1];
+                        const double cy = nz * P.src_n[0] - nx * P.src_n[2];
+                        const double cz = nx * P.src_n[1] - ny * P.src_n[0];
                         psi = atan2_upper(sqrt(fma(cx, cx, fma(cy, cy, cz * cz))),
-                                          fma(nx, p.src_n[0], fma(ny, p.src_n[1], nz * p.src_n[2])));
+                                          fma(nx, P.src_n[0], fma(ny, P.src_n[1], nz * P.src_n[2])));
                         COLD(C_PSI) = defl;  // parked until the ray ends
                         COLD(C_SRCPSI) = psi;
                         fl |= F_SRCDONE;
@@ -266,14 +302,10 @@ trace_kernel(const Params p) {
                     accept = false;
                 } else if constexpr (METHOD == KT_DP45) {
                     // mean square of err_i / (atol + rtol max(|y_i|, |yn_i|))
-                    double acc = 0.0;
+                    double sc[5];
 #pragma unroll
-                    for (int i = 0; i < 5; ++i) {
-                        const double sc = fma(p.rtol, fmax(fabs(y[i]), fabs(yn[i])), p.atol);
-                        const double q = er[i] * rcp(sc);
-                        acc = fma(q, q, acc);
-                    }
-                    const double msq = acc * 0.2;
+                    for (int i = 0; i < 5; ++i) sc[i] = fma(hp.rtol, fmax(fabs(y[i]), fabs(yn[i])), hp.atol);
+                    const double msq = error_msq(er, sc);
                     if (isnan(msq)) {
                         fate = KT_FATE_STEPFAIL;
                         accept = false;
@@ -298,7 +330,7 @@ trace_kernel(const Params p) {
                     fl &= ~F_RETAKE;
                     bool locate = false;
                     // thin disk: sign change of theta - pi/2 over the step
-                    if (p.disk_on && !(fl & F_SKIPDISK)) {
+                    if (hp.disk_on && !(fl & F_SKIPDISK)) {
                         const double ga = y[1] - HALF_PI, gb = yn[1] - HALF_PI;
                         if (ga * gb < 0.0) {
                             fl = (fl & ~(F_EVSRC | (0xff << EVIT_SHIFT))) | F_LOCATE;
@@ -309,7 +341,7 @@ trace_kernel(const Params p) {
                             COLD(C_EVC) = h - gb * h / (gb - ga);
                             locate = true;
                         } else if (gb == 0.0) {
-                            if (yn[0] >= p.r_in && yn[0] <= p.r_out) {
+                            if (yn[0] >= hp.r_in && yn[0] <= hp.r_out) {
                                 fate = KT_FATE_DISK;
                                 r_c = yn[0];
                                 thf = yn[1];
@@ -321,14 +353,14 @@ trace_kernel(const Params p) {
                         }
                     }
                     if (!locate && fate < 0) {
-                        if (yn[0] < p.r_cap) {
+                        if (yn[0] < hp.r_cap) {
                             fate = KT_FATE_CAPTURED;
                             thf = yn[1];
                             phf = yn[2];
                         } else {
-                            if (p.src_on && !(fl & F_SRCDONE)) {
-                                if (y[0] < p.r_src && yn[0] >= p.r_src) {
-                                    const double fa = y[0] - p.r_src, fb = yn[0] - p.r_src;
+                            if (hp.src_on && !(fl & F_SRCDONE)) {
+                                if (y[0] < hp.r_src && yn[0] >= hp.r_src) {
+                                    const double fa = y[0] - hp.r_src, fb = yn[0] - hp.r_src;
                                     fl = (fl & ~(0xff << EVIT_SHIFT)) | F_EVSRC | F_LOCATE;
                                     COLD(C_EVA) = 0.0;
                                     COLD(C_EVFA) = fa;
@@ -337,11 +369,14 @@ trace_kernel(const Params p) {
                                     COLD(C_EVC) = h - fb * h / (fb - fa);
                                     locate = true;
                                 } else {
-                                    COLD(C_PSI) += arc_angle(COLD(C_CS), COLD(C_CC), dg.s, dg.c, yn[2] - y[2]);
+                                    const double s1 = COLD(C_CS), c1 = COLD(C_CC), dphi = yn[2] - y[2];
+                                    double arc = arc_angle_short(s1, c1, dg.s, dg.c, dphi);
+                                    if (arc < 0.0) arc = arc_angle(s1, c1, dg.s, dg.c, dphi);
+                                    COLD(C_PSI) += arc;
                                 }
                             }
                             if (!locate) {
-                                if (yn[0] > p.r_esc) {
+                                if (yn[0] > hp.r_esc) {
                                     fate = KT_FATE_ESCAPED;
                                     thf = yn[1];
                                     phf = yn[2];
@@ -366,13 +401,13 @@ trace_kernel(const Params p) {
         }
 
         if (fate >= 0) {
-            const Outputs& o = p.out;
+            const Outputs& o = P.out;
             if (fl & F_SRCDONE) {
                 defl = COLD(C_PSI);
                 psi = COLD(C_SRCPSI);
             }
             o.fate[ray] = static_cast<uint8_t>(fate);
-            p.rc_buf[ray] = r_c;
+            P.rc_buf[ray] = r_c;
             if (o.max_abs_h) o.max_abs_h[ray] = COLD(C_MAXABS);
             if (o.max_rel_h) o.max_rel_h[ray] = COLD(C_MAXREL);
             if (o.psi) o.psi[ray] = psi;
@@ -380,7 +415,7 @@ trace_kernel(const Params p) {
             if (o.theta_f) o.theta_f[ray] = thf;
             if (o.phi_f) o.phi_f[ray] = phf;
             if (o.n_cross) o.n_cross[ray] = static_cast<uint8_t>((fl >> NCROSS_SHIFT) & 0xff);
-            if (o.used_fp64) o.used_fp64[ray] = static_cast<uint8_t>(p.from_list ? 1 : 0);
+            if (o.used_fp64) o.used_fp64[ray] = static_cast<uint8_t>(P.from_list ? 1 : 0);
             if (o.n_steps) o.n_steps[ray] = nsteps;
             if (o.n_evals) o.n_evals[ray] = nevals;
             evals_acc += static_cast<unsigned long long>(nevals);
@@ -391,7 +426,7 @@ trace_kernel(const Params p) {
 
     // one atomic per wave for the evaluation counter
     for (int off = 32; off > 0; off >>= 1) evals_acc += __shfl_down(evals_acc, off);
-    if (lane == 0 && evals_acc != 0ull) atomicAdd(p.acc + ACC_EVALS, evals_acc);
+    if (lane == 0 && evals_acc != 0ull) atomicAdd(P.acc + ACC_EVALS, evals_acc);
 }
 
 // Keplerian redshift and observed intensity of every disk pixel from the
@@ -428,13 +463,14 @@ __global__ void disk_obs_kernel(const Params p) {
 // Small kernels
 // ---------------------------------------------------------------------------
 
-__global__ void ws_init_kernel(uint32_t* ticket, unsigned long long* acc, uint32_t* fb_count) {
+__global__ void ws_init_kernel(const Params p) {
     const int t = threadIdx.x;
     if (t == 0) {
-        *ticket = 0u;
-        *fb_count = 0u;
+        *p.ticket = 0u;
+        *p.fb_count = 0u;
+        *p.ws_params = p;
     }
-    if (t < 16) acc[t] = 0ull;
+    if (t < 16) p.acc[t] = 0ull;
 }
 
 __global__ void reset_ticket_kernel(uint32_t* ticket) {
@@ -514,8 +550,7 @@ static int small_grid(int64_t n, int block) {
 }
 
 int launch_ws_init(const Params& p, void* stream) {
-    hipLaunchKernelGGL(ws_init_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), p.ticket,
-                       p.acc, p.fb_count);
+    hipLaunchKernelGGL(ws_init_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), p);
     return check_launch();
 }
 
@@ -525,13 +560,35 @@ int launch_reset_ticket(const Params& p, void* stream) {
     return check_launch();
 }
 
+static Hot make_hot(const Params& p) {
+    Hot hp;
+    hp.M = p.M;
+    hp.a = p.a;
+    hp.a2 = p.a2;
+    hp.two_a2 = p.two_a2;
+    hp.rtol = p.rtol;
+    hp.atol = p.atol;
+    hp.r_cap = p.r_cap;
+    hp.r_esc = p.r_esc;
+    hp.r_src = p.r_src;
+    hp.r_in = p.r_in;
+    hp.r_out = p.r_out;
+    hp.disk_on = p.disk_on;
+    hp.src_on = p.src_on;
+    hp.max_steps = static_cast<int32_t>(p.max_steps);
+    hp.max_evals = static_cast<int32_t>(p.max_evals);
+    hp.cold = p.ws_params;
+    return hp;
+}
+
 int launch_trace(const Params& p, int grid, int block, void* stream) {
+    const Hot hp = make_hot(p);
     if (p.method == KT_DP45)
         hipLaunchKernelGGL(trace_kernel<KT_DP45>, dim3(grid), dim3(block), 0,
-                           static_cast<hipStream_t>(stream), p);
+                           static_cast<hipStream_t>(stream), hp);
     else
         hipLaunchKernelGGL(trace_kernel<KT_RK4_S>, dim3(grid), dim3(block), 0,
-                           static_cast<hipStream_t>(stream), p);
+                           static_cast<hipStream_t>(stream), hp);
     return check_launch();
 }
 

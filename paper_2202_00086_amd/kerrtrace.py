@@ -15,7 +15,9 @@ import math
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libkerrtrace.so")
+# KERRTRACE_LIB selects another build of the same library (e.g. a variant
+# compiled with different occupancy) for side-by-side timing.
+LIB_PATH = os.environ.get("KERRTRACE_LIB") or os.path.join(HERE, "libkerrtrace.so")
 
 KT_OK, KT_EINVAL, KT_EDEVICE, KT_ENOMEM = 0, -1, -2, -3
 ESCAPED, CAPTURED, DISK, MAXSTEPS, STEPFAIL, INVALID = range(6)
