@@ -98,7 +98,7 @@ void camera_constants(const kt_camera* cam, const kt_spacetime* st, kt::Params& 
 size_t ws_bytes(const kt_camera* cam, const kt_integrator* integ) {
     size_t n = static_cast<size_t>(cam->nx) * static_cast<size_t>(cam->ny);
     size_t b = kt::ws_fb_list_offset(n);
-    if (integ->precision == KT_MIXED) b += 4 * n;
+    if (integ->precision == KT_MIXED) b = kt::ws_need_offset(n) + n;
     return (b + 255) & ~static_cast<size_t>(255);
 }
 
@@ -145,8 +145,11 @@ int kt_render_ex(const kt_camera* camera, const kt_spacetime* spacetime, const k
         return fail(KT_EINVAL, "unknown integrator method %d", integ->method);
     if (integ->precision != KT_FP64 && integ->precision != KT_MIXED)
         return fail(KT_EINVAL, "unknown precision %d", integ->precision);
-    if (integ->precision == KT_MIXED)
-        return fail(KT_EINVAL, "precision KT_MIXED is not available in this build");
+    if (integ->precision == KT_MIXED) {
+        if (integ->method != KT_DP45) return fail(KT_EINVAL, "KT_MIXED needs method KT_DP45");
+        if (!(integ->h_budget >= 0.0) || !(integ->r_switch > 0.0))
+            return fail(KT_EINVAL, "KT_MIXED needs h_budget >= 0 and r_switch > 0");
+    }
     if (!finite_all({integ->h_fixed, integ->rtol, integ->atol, integ->h_init, integ->capture_buffer,
                      integ->r_escape, integ->h_budget, integ->r_switch}))
         return fail(KT_EINVAL, "non-finite integrator parameter");
@@ -245,6 +248,7 @@ int kt_render_ex(const kt_camera* camera, const kt_spacetime* spacetime, const k
     p.fb_count = reinterpret_cast<uint32_t*>(ws + kt::WS_FB_COUNT);
     p.rc_buf = reinterpret_cast<double*>(ws + kt::WS_RC);
     p.ws_params = reinterpret_cast<kt::Params*>(ws + kt::WS_PARAMS);
+    p.need_fb = reinterpret_cast<uint8_t*>(ws + kt::ws_need_offset(static_cast<size_t>(p.n_rays)));
     p.fb_list = reinterpret_cast<uint32_t*>(ws + kt::ws_fb_list_offset(static_cast<size_t>(p.n_rays)));
     p.persistent = ln.persistent ? 1 : 0;
     p.batch = ln.batch;
@@ -264,6 +268,17 @@ int kt_render_ex(const kt_camera* camera, const kt_spacetime* spacetime, const k
     if (grid < 1) grid = 1;
     if (kt::launch_trace(p, grid, ln.block, hip_stream))
         return fail(KT_EDEVICE, "trace kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+    if (p.precision == KT_MIXED) {
+        // re-run every ray over the |H|_rel budget in FP64, from a compacted
+        // list whose length stays on the device
+        if (kt::launch_fallback_list(p, hip_stream))
+            return fail(KT_EDEVICE, "fallback list launch failed: %s", hipGetErrorString(hipGetLastError()));
+        int grid2 = ln.persistent ? grid
+                                  : static_cast<int>((static_cast<int64_t>(p.n_rays) + ln.block - 1) / ln.block);
+        if (grid2 < 1) grid2 = 1;
+        if (kt::launch_trace_fallback(p, grid2, ln.block, hip_stream))
+            return fail(KT_EDEVICE, "fallback trace launch failed: %s", hipGetErrorString(hipGetLastError()));
+    }
     if ((out->r_hit || out->g || out->intensity) && kt::launch_disk_obs(p, hip_stream))
         return fail(KT_EDEVICE, "disk observables launch failed: %s", hipGetErrorString(hipGetLastError()));
     if (out->ring && kt::launch_ring(p, hip_stream))

@@ -236,6 +236,93 @@ __device__ __forceinline__ void rhs(const Spacetime& st, const RayConst& rc, con
 }
 
 // ---------------------------------------------------------------------------
+// Split form for the mixed-precision policy: H = H0 + HM with
+//   H0 = 1/2 [-E^2 + (rho2 p_r^2 + p_th^2)/Sigma + L^2/(rho2 sin^2)]   (M = 0 part)
+//   HM = -(M r / Sigma) [W^2 / (rho2 Delta) + p_r^2]                    (mass part)
+// (rho2 = r^2 + a^2; H0 + HM equals the Carter form identically).  The flow
+// of H0 is evaluated in FP64 and that of HM in FP32; HM carries a factor
+// M/r, so its FP32 rounding is small where r is large.  With WANT_DIAG the
+// constraint diagnostics are computed from the full Carter form in FP64.
+// ---------------------------------------------------------------------------
+struct Spacetime32 {
+    float M, a, a2;
+};
+
+template <bool WANT_DIAG>
+__device__ __forceinline__ void rhs_split(const Spacetime& st, const Spacetime32& sf, const RayConst& rc,
+                                          const double z[5], double dz[5], Diag* dg) {
+    const double r = z[0], pr = z[3], pth = z[4];
+    double s, c;
+    sincos_fast(z[1], &s, &c);
+    const double r2 = r * r;
+    const double rho2 = r2 + st.a2;
+    const double Sig = fma(st.a2 * c, c, r2);
+    // 1/sin, 1/Sigma, 1/rho2 from one reciprocal of the product
+    const double SR = Sig * rho2;
+    const double q = rcp(SR * s);
+    const double inv_s = SR * q;
+    const double inv_SR = s * q;
+    const double inv_Sig = rho2 * inv_SR;
+    const double inv_rho2 = Sig * inv_SR;
+    const double pr2 = pr * pr;
+    const double A = fma(rho2, pr2, pth * pth);
+    const double inv_s2 = inv_s * inv_s;
+    const double L2r = rc.L * rc.L * inv_rho2 * inv_s2;  // L^2 / (rho2 sin^2)
+    const double AS2 = A * inv_Sig * inv_Sig;            // A / Sigma^2
+    double d0 = rho2 * pr * inv_Sig;
+    double d1 = pth * inv_Sig;
+    double d2 = rc.L * inv_rho2 * inv_s2;
+    double d3 = r * (AS2 - pr2 * inv_Sig + L2r * inv_rho2);
+    double d4 = c * (L2r * inv_s - st.a2 * s * AS2);
+
+    // mass part in FP32
+    const float rf = static_cast<float>(r), sfl = static_cast<float>(s), cf = static_cast<float>(c);
+    const float prf = static_cast<float>(pr), Ef = static_cast<float>(rc.E), Lf = static_cast<float>(rc.L);
+    const float rho2f = rf * rf + sf.a2;
+    const float Sigf = fmaf(sf.a2 * cf, cf, rf * rf);
+    const float Delf = fmaf(rf, rf - 2.0f * sf.M, sf.a2);
+    const float inv_Sigf = __builtin_amdgcn_rcpf(Sigf);
+    const float inv_RDf = __builtin_amdgcn_rcpf(rho2f * Delf);
+    const float Wf = fmaf(rho2f, Ef, -sf.a * Lf);
+    const float WR = Wf * inv_RDf;                        // W / (rho2 Delta)
+    const float G = fmaf(Wf, WR, prf * prf);              // W^2/(rho2 Delta) + p_r^2
+    const float qm = sf.M * rf * inv_Sigf;                // M r / Sigma
+    // d G / d r = 4 r E W/(rho2 Delta) - W^2 (2 r Delta + 2 rho2 (r - M)) / (rho2 Delta)^2
+    const float dG = fmaf(4.0f * rf * Ef, WR, -WR * WR * 2.0f * fmaf(rf, Delf, rho2f * (rf - sf.M)));
+    const float m0 = -2.0f * qm * prf;
+    const float m2 = 2.0f * sf.a * qm * WR;
+    const float m3 = fmaf(sf.M * inv_Sigf * G, fmaf(-2.0f * rf * rf, inv_Sigf, 1.0f), qm * dG);
+    const float m4 = 2.0f * sf.a2 * sfl * cf * qm * G * inv_Sigf;
+    dz[0] = d0 + static_cast<double>(m0);
+    dz[1] = d1;
+    dz[2] = d2 + static_cast<double>(m2);
+    dz[3] = d3 + static_cast<double>(m3);
+    dz[4] = d4 + static_cast<double>(m4);
+    if (WANT_DIAG) {
+        const double Del = fma(r, r - 2.0 * st.M, st.a2);
+        const double W = fma(rho2, rc.E, -rc.aL);
+        const double T = fma(rc.L, inv_s, -rc.aE * s);
+        const double WWd = W * W * rcp(Del);
+        const double K = fma(Del, pr2, fma(pth, pth, fma(T, T, -WWd)));
+        const double D = fma(Del, pr2, fma(pth, pth, fma(T, T, WWd)));
+        dg->H = 0.5 * K * inv_Sig;
+        dg->rel = fabs(K) * rcp(D);
+        dg->s = s;
+        dg->c = c;
+    }
+}
+
+// The right-hand side of the stepper: Carter form in FP64, or the split form.
+template <bool SPLIT, bool D>
+__device__ __forceinline__ void eval_rhs(const Spacetime& st, const Spacetime32* sf, const RayConst& rc,
+                                         const double* z, double* out, Diag* dg) {
+    if constexpr (SPLIT)
+        rhs_split<D>(st, *sf, rc, z, out, dg);
+    else
+        rhs<D, false>(st, rc, z, out, dg);
+}
+
+// ---------------------------------------------------------------------------
 // Dormand & Prince (1980) RK5(4)7M, first-same-as-last.
 // ---------------------------------------------------------------------------
 namespace dp {
@@ -257,29 +344,30 @@ constexpr double E1 = 71.0 / 57600, E3 = -71.0 / 16695, E4 = 71.0 / 1920,
 // One DP5(4) step of size h from y with k1 = f(y).  Writes the 5th-order
 // solution yn, kn = f(yn) with its diagnostics, and the error vector err.
 // Six RHS evaluations.
+template <bool SPLIT = false>
 __device__ __forceinline__ void dp45_step(const Spacetime& st, const RayConst& rc, const double y[5],
                                           const double k1[5], double h, double yn[5], double kn[5],
-                                          double err[5], Diag* dg) {
+                                          double err[5], Diag* dg, const Spacetime32* sf = nullptr) {
     using namespace dp;
     double k2[5], k3[5], k4[5], k5[5], k6[5], ys[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) ys[i] = fma(h, A21 * k1[i], y[i]);
-    rhs<false, false>(st, rc, ys, k2, nullptr);
+    eval_rhs<SPLIT, false>(st, sf, rc, ys, k2, dg);
 #pragma unroll
     for (int i = 0; i < 5; ++i) ys[i] = fma(h, fma(A31, k1[i], A32 * k2[i]), y[i]);
-    rhs<false, false>(st, rc, ys, k3, nullptr);
+    eval_rhs<SPLIT, false>(st, sf, rc, ys, k3, dg);
 #pragma unroll
     for (int i = 0; i < 5; ++i) ys[i] = fma(h, fma(A41, k1[i], fma(A42, k2[i], A43 * k3[i])), y[i]);
-    rhs<false, false>(st, rc, ys, k4, nullptr);
+    eval_rhs<SPLIT, false>(st, sf, rc, ys, k4, dg);
 #pragma unroll
     for (int i = 0; i < 5; ++i)
         ys[i] = fma(h, fma(A51, k1[i], fma(A52, k2[i], fma(A53, k3[i], A54 * k4[i]))), y[i]);
-    rhs<false, false>(st, rc, ys, k5, nullptr);
+    eval_rhs<SPLIT, false>(st, sf, rc, ys, k5, dg);
 #pragma unroll
     for (int i = 0; i < 5; ++i)
         ys[i] = fma(h, fma(A61, k1[i], fma(A62, k2[i], fma(A63, k3[i], fma(A64, k4[i], A65 * k5[i])))),
                     y[i]);
-    rhs<false, false>(st, rc, ys, k6, nullptr);
+    eval_rhs<SPLIT, false>(st, sf, rc, ys, k6, dg);
     // error partial sums before stage 7 so that k3..k6 are dead across it
     double ep[5];
 #pragma unroll
@@ -287,7 +375,7 @@ __device__ __forceinline__ void dp45_step(const Spacetime& st, const RayConst& r
         yn[i] = fma(h, fma(B1, k1[i], fma(B3, k3[i], fma(B4, k4[i], fma(B5, k5[i], B6 * k6[i])))), y[i]);
         ep[i] = fma(E1, k1[i], fma(E3, k3[i], fma(E4, k4[i], fma(E5, k5[i], E6 * k6[i]))));
     }
-    rhs<true, false>(st, rc, yn, kn, dg);
+    eval_rhs<SPLIT, true>(st, sf, rc, yn, kn, dg);
 #pragma unroll
     for (int i = 0; i < 5; ++i) err[i] = h * fma(E7, kn[i], ep[i]);
 }

@@ -15,8 +15,10 @@ constexpr size_t WS_FB_COUNT = 192;   // uint32 fallback list length
 constexpr size_t WS_PARAMS = 256;     // device copy of Params (read by the kernels' cold paths)
 constexpr size_t WS_PARAMS_MAX = 1792;
 constexpr size_t WS_RC = WS_PARAMS + WS_PARAMS_MAX;  // double[n_rays] disk crossing radius per ray
-// then, for KT_MIXED only, uint32[n_rays] ray ids for the FP64 re-run
+// then, for KT_MIXED only: uint32[n_rays] ray ids for the FP64 re-run and
+// uint8[n_rays] re-run flags
 inline size_t ws_fb_list_offset(size_t n_rays) { return (WS_RC + 8 * n_rays + 255) & ~size_t(255); }
+inline size_t ws_need_offset(size_t n_rays) { return (ws_fb_list_offset(n_rays) + 4 * n_rays + 255) & ~size_t(255); }
 constexpr int ACC_EVALS = 0, ACC_EVALS_FP32 = 1;
 
 struct Outputs {
@@ -59,6 +61,7 @@ struct Params {
     uint32_t* fb_list;
     uint32_t* fb_count;
     double* rc_buf;
+    uint8_t* need_fb;   // KT_MIXED: 1 where the ray must be re-run in FP64
     Params* ws_params;  // where ws_init leaves the device copy of this struct
     // launch
     int32_t persistent, batch;
@@ -72,6 +75,7 @@ static_assert(sizeof(Params) <= WS_PARAMS_MAX, "Params must fit its workspace sl
 struct Hot {
     double M, a, a2, two_a2;
     double rtol, atol, r_cap, r_esc, r_src, r_in, r_out;
+    double h_budget, r_switch;  // KT_MIXED
     int32_t disk_on, src_on;
     int32_t max_steps, max_evals;
     const Params* cold;  // the workspace copy of Params
@@ -79,7 +83,9 @@ struct Hot {
 
 // Host-side launchers (kt_trace.hip).
 int launch_ws_init(const Params& p, void* stream);  // also copies p into the workspace
-int launch_trace(const Params& p, int grid, int block, void* stream);
+int launch_trace(const Params& p, int grid, int block, void* stream);  // pass of p.precision
+int launch_fallback_list(const Params& p, void* stream);  // compact need_fb, switch the copy to from_list
+int launch_trace_fallback(const Params& p, int grid, int block, void* stream);  // FP64 re-run from the list
 int launch_reset_ticket(const Params& p, void* stream);
 int launch_ring(const Params& p, void* stream);
 int launch_disk_obs(const Params& p, void* stream);

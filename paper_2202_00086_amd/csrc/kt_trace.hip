@@ -89,6 +89,7 @@ enum : int {
     F_SKIPDISK = 1 << 5,  // disk crossing of the re-taken step already handled
     F_SRCDONE = 1 << 6,   // source sphere crossed
     F_EVSRC = 1 << 7,     // event being located: 0 disk plane, 1 source sphere
+    F_USED32 = 1 << 24,   // mixed pass: some step used the FP32 mass part
 };
 constexpr int NCROSS_SHIFT = 8;   // 8 bits: equatorial crossings outside the disk
 constexpr int EVIT_SHIFT = 16;    // 8 bits: trial steps of the current event
@@ -140,11 +141,13 @@ __device__ __forceinline__ double error_msq(const double er[5], const double sc[
     return 0.2 * fma(e0, e0, fma(e1, e1, fma(e2, e2, fma(e3, e3, e4 * e4))));
 }
 
-template <int METHOD>
+template <int METHOD, int PREC>
 __global__ void __launch_bounds__(BLOCK_MAX) __attribute__((amdgpu_waves_per_eu(KT_WAVES_PER_EU)))
 trace_kernel(const Hot hp) {
     constexpr int EVALS_PER_STEP = (METHOD == KT_DP45) ? 6 : 4;
     constexpr bool S_TIME = (METHOD == KT_RK4_S);
+    constexpr bool MIXED = (PREC == KT_MIXED) && (METHOD == KT_DP45);
+    const Spacetime32 sf{static_cast<float>(hp.M), static_cast<float>(hp.a), static_cast<float>(hp.a2)};
     __shared__ double cold[N_COLD][BLOCK_MAX];
     const int tid = threadIdx.x;
 #define COLD(f) cold[f][tid]
@@ -173,7 +176,7 @@ trace_kernel(const Hot hp) {
     double y[5], k1[5];
     double E = 0.0, L = 0.0, h = 0.0;
     int nsteps = 0, nevals = 0;
-    unsigned long long evals_acc = 0;
+    unsigned long long evals_acc = 0, evals32_acc = 0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) y[i] = k1[i] = 0.0;
 
@@ -239,7 +242,19 @@ trace_kernel(const Hot hp) {
             const double hs = locating ? COLD(C_EVC) : h;
             double yn[5], kn[5], er[5];
             Diag dg;
-            take_step<METHOD>(st, rc, y, k1, hs, yn, kn, er, &dg);
+            if constexpr (MIXED) {
+                // the FP32 mass part only when every stepping lane of the wave
+                // is beyond r_switch (a wave-uniform branch)
+                if (__all(y[0] >= hp.r_switch)) {
+                    dp45_step<true>(st, rc, y, k1, hs, yn, kn, er, &dg, &sf);
+                    fl |= F_USED32;
+                    evals32_acc += EVALS_PER_STEP;
+                } else {
+                    dp45_step<false>(st, rc, y, k1, hs, yn, kn, er, &dg);
+                }
+            } else {
+                take_step<METHOD>(st, rc, y, k1, hs, yn, kn, er, &dg);
+            }
             nevals += EVALS_PER_STEP;
             if (locating) {
                 // Illinois regula falsi on the event function
@@ -418,15 +433,63 @@ trace_kernel(const Hot hp) {
             if (o.used_fp64) o.used_fp64[ray] = static_cast<uint8_t>(P.from_list ? 1 : 0);
             if (o.n_steps) o.n_steps[ray] = nsteps;
             if (o.n_evals) o.n_evals[ray] = nevals;
+            if constexpr (MIXED) {
+                const double mr = COLD(C_MAXREL);
+                P.need_fb[ray] = ((fl & F_USED32) && !(mr <= hp.h_budget)) ? 1 : 0;
+            }
             evals_acc += static_cast<unsigned long long>(nevals);
             ray = -1;
         }
     }
 #undef COLD
 
-    // one atomic per wave for the evaluation counter
+    // one atomic per wave for each evaluation counter
     for (int off = 32; off > 0; off >>= 1) evals_acc += __shfl_down(evals_acc, off);
     if (lane == 0 && evals_acc != 0ull) atomicAdd(P.acc + ACC_EVALS, evals_acc);
+    if constexpr (MIXED) {
+        for (int off = 32; off > 0; off >>= 1) evals32_acc += __shfl_down(evals32_acc, off);
+        if (lane == 0 && evals32_acc != 0ull) atomicAdd(P.acc + ACC_EVALS_FP32, evals32_acc);
+    }
+}
+
+// Compact the re-run flags into the fallback list (order does not matter:
+// every ray is independent) and count them.
+__global__ void fallback_list_kernel(const uint8_t* __restrict__ need, int64_t n, uint32_t* __restrict__ list,
+                                     uint32_t* count) {
+    __shared__ uint32_t block_base;
+    __shared__ uint32_t wave_counts[BLOCK_MAX / 64];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const uint32_t lane = __lane_id();
+    for (int64_t base = static_cast<int64_t>(blockIdx.x) * blockDim.x; base < n;
+         base += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t k = base + tid;
+        const bool want = k < n && need[k];
+        const unsigned long long m = __ballot(want);
+        const uint32_t rank = static_cast<uint32_t>(__popcll(m & ((1ull << lane) - 1ull)));
+        if (lane == 0) wave_counts[wave] = static_cast<uint32_t>(__popcll(m));
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t tot = 0;
+            for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) {
+                const uint32_t c = wave_counts[w];
+                wave_counts[w] = tot;
+                tot += c;
+            }
+            block_base = tot ? atomicAdd(count, tot) : 0u;
+        }
+        __syncthreads();
+        if (want) list[block_base + wave_counts[wave] + rank] = static_cast<uint32_t>(k);
+        __syncthreads();
+    }
+}
+
+// Switch the workspace copy of the parameters to the list-driven FP64 pass.
+__global__ void to_fallback_kernel(Params* wp) {
+    if (threadIdx.x == 0) {
+        *wp->ticket = 0u;
+        wp->from_list = 1;
+        wp->precision = KT_FP64;
+    }
 }
 
 // Keplerian redshift and observed intensity of every disk pixel from the
@@ -573,6 +636,8 @@ static Hot make_hot(const Params& p) {
     hp.r_src = p.r_src;
     hp.r_in = p.r_in;
     hp.r_out = p.r_out;
+    hp.h_budget = p.h_budget;
+    hp.r_switch = p.r_switch;
     hp.disk_on = p.disk_on;
     hp.src_on = p.src_on;
     hp.max_steps = static_cast<int32_t>(p.max_steps);
@@ -583,20 +648,41 @@ static Hot make_hot(const Params& p) {
 
 int launch_trace(const Params& p, int grid, int block, void* stream) {
     const Hot hp = make_hot(p);
-    if (p.method == KT_DP45)
-        hipLaunchKernelGGL(trace_kernel<KT_DP45>, dim3(grid), dim3(block), 0,
-                           static_cast<hipStream_t>(stream), hp);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p.method == KT_DP45 && p.precision == KT_MIXED)
+        hipLaunchKernelGGL((trace_kernel<KT_DP45, KT_MIXED>), dim3(grid), dim3(block), 0, s, hp);
+    else if (p.method == KT_DP45)
+        hipLaunchKernelGGL((trace_kernel<KT_DP45, KT_FP64>), dim3(grid), dim3(block), 0, s, hp);
     else
-        hipLaunchKernelGGL(trace_kernel<KT_RK4_S>, dim3(grid), dim3(block), 0,
-                           static_cast<hipStream_t>(stream), hp);
+        hipLaunchKernelGGL((trace_kernel<KT_RK4_S, KT_FP64>), dim3(grid), dim3(block), 0, s, hp);
+    return check_launch();
+}
+
+int launch_fallback_list(const Params& p, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(fallback_list_kernel, dim3(small_grid(p.n_rays, 256)), dim3(256), 0, s, p.need_fb,
+                       static_cast<int64_t>(p.n_rays), p.fb_list, p.fb_count);
+    if (check_launch()) return -1;
+    hipLaunchKernelGGL(to_fallback_kernel, dim3(1), dim3(64), 0, s, p.ws_params);
+    return check_launch();
+}
+
+int launch_trace_fallback(const Params& p, int grid, int block, void* stream) {
+    const Hot hp = make_hot(p);
+    hipLaunchKernelGGL((trace_kernel<KT_DP45, KT_FP64>), dim3(grid), dim3(block), 0,
+                       static_cast<hipStream_t>(stream), hp);
     return check_launch();
 }
 
 int trace_max_blocks_per_cu(const Params& p, int block) {
     int nb = 0;
-    hipError_t e = (p.method == KT_DP45)
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<KT_DP45>, block, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<KT_RK4_S>, block, 0);
+    hipError_t e;
+    if (p.method == KT_DP45 && p.precision == KT_MIXED)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<KT_DP45, KT_MIXED>, block, 0);
+    else if (p.method == KT_DP45)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<KT_DP45, KT_FP64>, block, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<KT_RK4_S, KT_FP64>, block, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 

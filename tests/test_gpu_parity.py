@@ -209,3 +209,66 @@ def test_full_size_kerr_ring_sampled(K):
     assert st.evals == g["n_evals"].astype(np.int64).sum()
     assert (g["fate"] <= K.DISK).all()
     assert np.nanmax(g["max_rel_h"]) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Mixed precision: FP32 mass part of the RHS beyond r_switch, FP64 re-run of
+# every ray over the |H|_rel budget.
+# ---------------------------------------------------------------------------
+
+_BITWISE_KEYS = ("fate", "max_abs_h", "max_rel_h", "psi", "deflection", "theta_f", "phi_f", "n_cross",
+                 "n_steps", "r_hit", "g", "intensity", "ring")
+
+
+def test_mixed_zero_budget_equals_fp64(K):
+    """h_budget = 0 sends every ray that used the FP32 part back to the FP64
+    pass; rays that never used it ran the FP64 code already.  So every
+    output equals the plain FP64 render bit for bit."""
+    params = dict(W.kerr_ring(0.9, n=96), disk_on=1, r_in=2.320883, r_out=30.0)
+    _announce("mixed budget 0")
+    ref = gpu_render(K, params)
+    g = gpu_render(K, dict(params, precision=K.MIXED, h_budget=0.0, r_switch=300.0))
+    for key in _BITWISE_KEYS:
+        np.testing.assert_array_equal(g[key].view(np.uint8), ref[key].view(np.uint8), err_msg=key)
+    st = g["stats"]
+    assert st.evals_fp32 > 0
+    assert st.fallback_rays == int(g["used_fp64"].sum()) > 0
+    assert st.evals > ref["stats"].evals
+
+
+def test_mixed_without_fallback_error_is_bounded(K):
+    """No re-run (budget = inf): the FP32 mass part's error, stated against
+    the FP64 oracle.  Fates keep the FP64 parity rule; located quantities
+    agree to 1e-6."""
+    params = W.kerr_ring(0.9, n=64)
+    _announce("mixed no fallback")
+    g = gpu_render(K, dict(params, precision=K.MIXED, h_budget=1e300, r_switch=300.0))
+    o = ora_render(params)
+    assert g["stats"].fallback_rays == 0 and (g["used_fp64"] == 0).all()
+    assert g["stats"].evals_fp32 > 0.05 * g["stats"].evals
+    P.check_fates(g["fate"], o["fate"], 64, 64)
+    m = P.value_mask(g, o, 64, 64)
+    e = P.rel_err(g["deflection"][m], o["deflection"][m])
+    e = e[np.isfinite(e)]
+    print(f"[mixed no fallback] deflection rel err max {e.max():.2e} p99 {np.percentile(e, 99):.2e}; "
+          f"max |H|_rel {np.nanmax(g['max_rel_h']):.2e}", flush=True)
+    assert e.max() < 1e-6
+
+
+def test_mixed_default_budget(K):
+    """Budget 1e-10: every ray ends within the budget, and FP64 parity holds
+    for every output under the FP64 rules."""
+    params = W.kerr_ring(0.9, n=96)
+    _announce("mixed budget 1e-10")
+    g = gpu_render(K, dict(params, precision=K.MIXED, h_budget=1e-10, r_switch=300.0))
+    o = ora_render(params)
+    assert np.nanmax(g["max_rel_h"]) <= 1e-10
+    P.check_fates(g["fate"], o["fate"], 96, 96)
+    m = P.value_mask(g, o, 96, 96)
+    kept = m & (g["used_fp64"] == 0)
+    if kept.any():
+        e = P.rel_err(g["deflection"][kept], o["deflection"][kept])
+        e = e[np.isfinite(e)]
+        print(f"[mixed 1e-10] fallback {g['used_fp64'].mean():.3f}; kept-mixed deflection rel err "
+              f"max {e.max() if e.size else 0:.2e}", flush=True)
+    P.check_values(g, o, "deflection", m & (g["used_fp64"] == 1), rtol=1e-8)
