@@ -60,6 +60,15 @@ __device__ __forceinline__ void sincos_fast(double x, double* s_out, double* c_o
     *c_out = ((q + 1) & 2) ? -c0 : c0;
 }
 
+// sqrt(q) for q >= 0 from the hardware reciprocal-square-root estimate and
+// two Newton steps on 1/sqrt (within an ulp or two); 0 for q = 0.
+__device__ __forceinline__ double sqrt_fast(double q) {
+    double y = __builtin_amdgcn_rsq(q);
+    y = y * fma(-0.5 * q * y, y, 1.5);
+    y = y * fma(-0.5 * q * y, y, 1.5);
+    return q > 0.0 ? q * y : 0.0;
+}
+
 // atan t for |t| <= 1: two half-angle reductions, atan t = 2 atan(t / (1 +
 // sqrt(1 + t^2))), bring |t| below tan(pi/16) = 0.199, where the Taylor
 // series through t^23 is exact to < 1e-18.
@@ -87,6 +96,47 @@ __device__ __forceinline__ double atan2_upper(double y, double x) {
     if (x >= y) return atan_unit(y / x);
     if (x >= -y) return HALF_PI - atan_unit(x / y);
     return PI + atan_unit(y / x);
+}
+
+// sin and cos of the polar angle theta.  theta is folded to t in [-pi, pi]
+// by t = theta - 2 pi rint(theta / 2 pi) (t = theta exactly on [0, pi), the
+// range of every ray that does not pass over the polar axis); then with
+// u = |t| - pi/2 in [-pi/2, pi/2]: sin theta = copysign(cos u, t) and
+// cos theta = -sin u, from the Taylor series of cos u through u^20 and sin u
+// through u^21 (truncation below 3e-17).  No quadrant selects.
+__device__ __forceinline__ void sincos_theta(double th, double* s_out, double* c_out) {
+    constexpr double INV_TWO_PI = 0.15915494309189533577;
+    constexpr double TWO_PI_HI = 6.2831853071795862320e+00;  // 2 pi rounded to double
+    constexpr double TWO_PI_LO = 2.4492935982947064e-16;     // 2 pi - TWO_PI_HI
+    constexpr double PIO2_HI = 1.5707963267948965580e+00;
+    constexpr double PIO2_LO = 6.1232339957367658e-17;
+    const double n = __builtin_rint(th * INV_TWO_PI);
+    double t = fma(-n, TWO_PI_HI, th);
+    t = fma(-n, TWO_PI_LO, t);
+    const double u = (fabs(t) - PIO2_HI) - PIO2_LO;
+    const double u2 = u * u;
+    double pc = 1.0 / 2432902008176640000.0;        //  1/20!
+    pc = fma(pc, u2, -1.0 / 6402373705728000.0);    // -1/18!
+    pc = fma(pc, u2, 1.0 / 20922789888000.0);       //  1/16!
+    pc = fma(pc, u2, -1.0 / 87178291200.0);         // -1/14!
+    pc = fma(pc, u2, 1.0 / 479001600.0);            //  1/12!
+    pc = fma(pc, u2, -1.0 / 3628800.0);             // -1/10!
+    pc = fma(pc, u2, 1.0 / 40320.0);                //  1/8!
+    pc = fma(pc, u2, -1.0 / 720.0);                 // -1/6!
+    pc = fma(pc, u2, 1.0 / 24.0);                   //  1/4!
+    pc = fma(pc, u2, -0.5);                         // -1/2!
+    *s_out = __builtin_copysign(fma(pc, u2, 1.0), t);  // sin theta = +-cos u
+    double ps = -1.0 / 51090942171709440000.0;      // -1/21!  (signs of -sin u)
+    ps = fma(ps, u2, 1.0 / 121645100408832000.0);   //  1/19!
+    ps = fma(ps, u2, -1.0 / 355687428096000.0);     // -1/17!
+    ps = fma(ps, u2, 1.0 / 1307674368000.0);        //  1/15!
+    ps = fma(ps, u2, -1.0 / 6227020800.0);          // -1/13!
+    ps = fma(ps, u2, 1.0 / 39916800.0);             //  1/11!
+    ps = fma(ps, u2, -1.0 / 362880.0);              // -1/9!
+    ps = fma(ps, u2, 1.0 / 5040.0);                 //  1/7!
+    ps = fma(ps, u2, -1.0 / 120.0);                 // -1/5!
+    ps = fma(ps, u2, 1.0 / 6.0);                    //  1/3!
+    *c_out = fma(ps * u2, u, -u);                   // cos theta = -sin u
 }
 
 // sin and cos of a small angle, |x| <= 1/2, from their Taylor series (sin
@@ -182,7 +232,7 @@ __device__ __forceinline__ void rhs(const Spacetime& st, const RayConst& rc, con
                                     double dz[5], Diag* dg) {
     const double r = z[0], pr = z[3], pth = z[4];
     double s, c;
-    sincos_fast(z[1], &s, &c);
+    sincos_theta(z[1], &s, &c);
     const double r2 = r * r;
     const double rho2 = r2 + st.a2;
     const double Sig = fma(st.a2 * c, c, r2);
@@ -253,7 +303,7 @@ __device__ __forceinline__ void rhs_split(const Spacetime& st, const Spacetime32
                                           const double z[5], double dz[5], Diag* dg) {
     const double r = z[0], pr = z[3], pth = z[4];
     double s, c;
-    sincos_fast(z[1], &s, &c);
+    sincos_theta(z[1], &s, &c);
     const double r2 = r * r;
     const double rho2 = r2 + st.a2;
     const double Sig = fma(st.a2 * c, c, r2);

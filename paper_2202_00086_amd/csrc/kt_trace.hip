@@ -51,7 +51,7 @@ __device__ __forceinline__ double arc_angle_short(double s1, double c1, double s
     const double dx = fma(s2, cd, -s1);
     const double dy = s2 * sd;
     const double dz = c2 - c1;
-    const double h = 0.5 * sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
+    const double h = 0.5 * sqrt_fast(fma(dx, dx, fma(dy, dy, dz * dz)));
     return h <= 0.0625 ? 2.0 * asin_small(h) : -1.0;
 }
 

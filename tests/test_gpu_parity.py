@@ -272,3 +272,22 @@ def test_mixed_default_budget(K):
         print(f"[mixed 1e-10] fallback {g['used_fp64'].mean():.3f}; kept-mixed deflection rel err "
               f"max {e.max() if e.size else 0:.2e}", flush=True)
     P.check_values(g, o, "deflection", m & (g["used_fp64"] == 1), rtol=1e-8)
+
+
+def test_polar_rays_wind_through_the_axis(K):
+    """A one-column image (x = 0, so L = 0): these rays cross the polar axis
+    and theta leaves [0, pi]; the kernel must switch to the range-reduced
+    sin/cos for those steps."""
+    for a in (0.0, 0.9):
+        params = dict(W.kerr_ring(a, n=8), nx=1, ny=41, fov_x=5.0)
+        _announce("polar column", a)
+        g = gpu_render(K, params)
+        o = ora_render(params)
+        np.testing.assert_array_equal(g["fate"], o["fate"])
+        m = np.isfinite(o["deflection"])
+        e = P.rel_err(g["deflection"][m], o["deflection"][m])
+        assert e.max() < 1e-8, e.max()
+        # the rays really do leave [0, pi]
+        s = O.Setup(**params)
+        tr, _ = O.trace_one(s, 0.0, O.pixel_xy(s, 0, 30)[1])
+        assert tr[:, 2].min() < 0.0 or tr[:, 2].max() > math.pi
