@@ -228,11 +228,9 @@ struct Diag {
 // S_TIME scales the field by d(lambda)/ds = Delta/r.
 // ---------------------------------------------------------------------------
 template <bool WANT_DIAG, bool S_TIME>
-__device__ __forceinline__ void rhs(const Spacetime& st, const RayConst& rc, const double z[5],
-                                    double dz[5], Diag* dg) {
+__device__ __forceinline__ void rhs_sc(const Spacetime& st, const RayConst& rc, const double z[5], double s,
+                                       double c, double dz[5], Diag* dg) {
     const double r = z[0], pr = z[3], pth = z[4];
-    double s, c;
-    sincos_theta(z[1], &s, &c);
     const double r2 = r * r;
     const double rho2 = r2 + st.a2;
     const double Sig = fma(st.a2 * c, c, r2);
@@ -285,6 +283,42 @@ __device__ __forceinline__ void rhs(const Spacetime& st, const RayConst& rc, con
     }
 }
 
+// The RHS at z with sin/cos of theta computed from theta itself.
+template <bool WANT_DIAG, bool S_TIME>
+__device__ __forceinline__ void rhs(const Spacetime& st, const RayConst& rc, const double z[5],
+                                    double dz[5], Diag* dg) {
+    double s, c;
+    sincos_theta(z[1], &s, &c);
+    rhs_sc<WANT_DIAG, S_TIME>(st, rc, z, s, c, dz, dg);
+}
+
+// sin and cos of theta0 + d from those of theta0 and the Taylor series of
+// sin d through d^13 and cos d through d^14: exact to rounding for
+// |d| <= 0.6, which covers the angle change between a step's start and any of
+// its stages (per-step changes stay below ~0.02 rad at the tolerances used);
+// the truncation grows smoothly beyond (1e-12 at |d| = 1) for the wild stages
+// of steps that get rejected.
+__device__ __forceinline__ void sincos_shift(double s0, double c0, double d, double* s_out, double* c_out) {
+    const double d2 = d * d;
+    double ps = -1.0 / 6227020800.0;       // -1/13!
+    ps = fma(ps, d2, 1.0 / 39916800.0);    //  1/11!
+    ps = fma(ps, d2, -1.0 / 362880.0);     // -1/9!
+    ps = fma(ps, d2, 1.0 / 5040.0);        //  1/7!
+    ps = fma(ps, d2, -1.0 / 120.0);        // -1/5!
+    ps = fma(ps, d2, 1.0 / 6.0);           //  1/3!
+    const double sd = fma(-ps * d2, d, d); // sin d
+    double pc = 1.0 / 87178291200.0;       //  1/14!
+    pc = fma(pc, d2, -1.0 / 479001600.0);  // -1/12!
+    pc = fma(pc, d2, 1.0 / 3628800.0);     //  1/10!
+    pc = fma(pc, d2, -1.0 / 40320.0);      // -1/8!
+    pc = fma(pc, d2, 1.0 / 720.0);         //  1/6!
+    pc = fma(pc, d2, -1.0 / 24.0);         // -1/4!
+    pc = fma(pc, d2, 0.5);                 //  1/2!
+    const double cdm1 = -pc * d2;          // cos d - 1
+    *s_out = fma(s0, cdm1, fma(c0, sd, s0));
+    *c_out = fma(c0, cdm1, fma(-s0, sd, c0));
+}
+
 // ---------------------------------------------------------------------------
 // Split form for the mixed-precision policy: H = H0 + HM with
 //   H0 = 1/2 [-E^2 + (rho2 p_r^2 + p_th^2)/Sigma + L^2/(rho2 sin^2)]   (M = 0 part)
@@ -300,10 +334,8 @@ struct Spacetime32 {
 
 template <bool WANT_DIAG>
 __device__ __forceinline__ void rhs_split(const Spacetime& st, const Spacetime32& sf, const RayConst& rc,
-                                          const double z[5], double dz[5], Diag* dg) {
+                                          const double z[5], double s, double c, double dz[5], Diag* dg) {
     const double r = z[0], pr = z[3], pth = z[4];
-    double s, c;
-    sincos_theta(z[1], &s, &c);
     const double r2 = r * r;
     const double rho2 = r2 + st.a2;
     const double Sig = fma(st.a2 * c, c, r2);
@@ -363,13 +395,23 @@ __device__ __forceinline__ void rhs_split(const Spacetime& st, const Spacetime32
 }
 
 // The right-hand side of the stepper: Carter form in FP64, or the split form.
+// at stage state z.  Inner stages take sin/cos of theta from those (s0, c0)
+// at the step's start angle th0; the last stage (D: the step's end, whose
+// sin/cos seed the next step) computes them from theta itself, so the
+// shifts never accumulate.
 template <bool SPLIT, bool D>
 __device__ __forceinline__ void eval_rhs(const Spacetime& st, const Spacetime32* sf, const RayConst& rc,
-                                         const double* z, double* out, Diag* dg) {
-    if constexpr (SPLIT)
-        rhs_split<D>(st, *sf, rc, z, out, dg);
+                                         const double* z, double th0, double s0, double c0, double* out,
+                                         Diag* dg) {
+    double s, c;
+    if constexpr (D)
+        sincos_theta(z[1], &s, &c);
     else
-        rhs<D, false>(st, rc, z, out, dg);
+        sincos_shift(s0, c0, z[1] - th0, &s, &c);
+    if constexpr (SPLIT)
+        rhs_split<D>(st, *sf, rc, z, s, c, out, dg);
+    else
+        rhs_sc<D, false>(st, rc, z, s, c, out, dg);
 }
 
 // ---------------------------------------------------------------------------
@@ -394,30 +436,32 @@ constexpr double E1 = 71.0 / 57600, E3 = -71.0 / 16695, E4 = 71.0 / 1920,
 // One DP5(4) step of size h from y with k1 = f(y).  Writes the 5th-order
 // solution yn, kn = f(yn) with its diagnostics, and the error vector err.
 // Six RHS evaluations.
+// (s0, c0) are sin and cos of y[1].
 template <bool SPLIT = false>
 __device__ __forceinline__ void dp45_step(const Spacetime& st, const RayConst& rc, const double y[5],
-                                          const double k1[5], double h, double yn[5], double kn[5],
-                                          double err[5], Diag* dg, const Spacetime32* sf = nullptr) {
+                                          const double k1[5], double s0, double c0, double h, double yn[5],
+                                          double kn[5], double err[5], Diag* dg,
+                                          const Spacetime32* sf = nullptr) {
     using namespace dp;
     double k2[5], k3[5], k4[5], k5[5], k6[5], ys[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) ys[i] = fma(h, A21 * k1[i], y[i]);
-    eval_rhs<SPLIT, false>(st, sf, rc, ys, k2, dg);
+    eval_rhs<SPLIT, false>(st, sf, rc, ys, y[1], s0, c0, k2, dg);
 #pragma unroll
     for (int i = 0; i < 5; ++i) ys[i] = fma(h, fma(A31, k1[i], A32 * k2[i]), y[i]);
-    eval_rhs<SPLIT, false>(st, sf, rc, ys, k3, dg);
+    eval_rhs<SPLIT, false>(st, sf, rc, ys, y[1], s0, c0, k3, dg);
 #pragma unroll
     for (int i = 0; i < 5; ++i) ys[i] = fma(h, fma(A41, k1[i], fma(A42, k2[i], A43 * k3[i])), y[i]);
-    eval_rhs<SPLIT, false>(st, sf, rc, ys, k4, dg);
+    eval_rhs<SPLIT, false>(st, sf, rc, ys, y[1], s0, c0, k4, dg);
 #pragma unroll
     for (int i = 0; i < 5; ++i)
         ys[i] = fma(h, fma(A51, k1[i], fma(A52, k2[i], fma(A53, k3[i], A54 * k4[i]))), y[i]);
-    eval_rhs<SPLIT, false>(st, sf, rc, ys, k5, dg);
+    eval_rhs<SPLIT, false>(st, sf, rc, ys, y[1], s0, c0, k5, dg);
 #pragma unroll
     for (int i = 0; i < 5; ++i)
         ys[i] = fma(h, fma(A61, k1[i], fma(A62, k2[i], fma(A63, k3[i], fma(A64, k4[i], A65 * k5[i])))),
                     y[i]);
-    eval_rhs<SPLIT, false>(st, sf, rc, ys, k6, dg);
+    eval_rhs<SPLIT, false>(st, sf, rc, ys, y[1], s0, c0, k6, dg);
     // error partial sums before stage 7 so that k3..k6 are dead across it
     double ep[5];
 #pragma unroll
@@ -425,7 +469,7 @@ __device__ __forceinline__ void dp45_step(const Spacetime& st, const RayConst& r
         yn[i] = fma(h, fma(B1, k1[i], fma(B3, k3[i], fma(B4, k4[i], fma(B5, k5[i], B6 * k6[i])))), y[i]);
         ep[i] = fma(E1, k1[i], fma(E3, k3[i], fma(E4, k4[i], fma(E5, k5[i], E6 * k6[i]))));
     }
-    eval_rhs<SPLIT, true>(st, sf, rc, yn, kn, dg);
+    eval_rhs<SPLIT, true>(st, sf, rc, yn, y[1], s0, c0, kn, dg);
 #pragma unroll
     for (int i = 0; i < 5; ++i) err[i] = h * fma(E7, kn[i], ep[i]);
 }

@@ -106,10 +106,10 @@ constexpr int BLOCK_MAX = 256;
 
 template <int METHOD>
 __device__ __forceinline__ void take_step(const Spacetime& st, const RayConst& rc, const double y[5],
-                                          const double k1[5], double h, double yn[5], double kn[5],
-                                          double er[5], Diag* dg) {
+                                          const double k1[5], double s0, double c0, double h, double yn[5],
+                                          double kn[5], double er[5], Diag* dg) {
     if constexpr (METHOD == KT_DP45) {
-        dp45_step(st, rc, y, k1, h, yn, kn, er, dg);
+        dp45_step(st, rc, y, k1, s0, c0, h, yn, kn, er, dg);
     } else {
         rk4s_step(st, rc, y, k1, h, yn, kn, dg);
 #pragma unroll
@@ -242,18 +242,20 @@ trace_kernel(const Hot hp) {
             const double hs = locating ? COLD(C_EVC) : h;
             double yn[5], kn[5], er[5];
             Diag dg;
+            // sin/cos of theta at the step start (from the last evaluation there)
+            const double s0 = COLD(C_CS), c0 = COLD(C_CC);
             if constexpr (MIXED) {
                 // the FP32 mass part only when every stepping lane of the wave
                 // is beyond r_switch (a wave-uniform branch)
                 if (__all(y[0] >= hp.r_switch)) {
-                    dp45_step<true>(st, rc, y, k1, hs, yn, kn, er, &dg, &sf);
+                    dp45_step<true>(st, rc, y, k1, s0, c0, hs, yn, kn, er, &dg, &sf);
                     fl |= F_USED32;
                     evals32_acc += EVALS_PER_STEP;
                 } else {
-                    dp45_step<false>(st, rc, y, k1, hs, yn, kn, er, &dg);
+                    dp45_step<false>(st, rc, y, k1, s0, c0, hs, yn, kn, er, &dg);
                 }
             } else {
-                take_step<METHOD>(st, rc, y, k1, hs, yn, kn, er, &dg);
+                take_step<METHOD>(st, rc, y, k1, s0, c0, hs, yn, kn, er, &dg);
             }
             nevals += EVALS_PER_STEP;
             if (locating) {
@@ -275,7 +277,7 @@ trace_kernel(const Hot hp) {
                             fl = (fl & ~(0xff << NCROSS_SHIFT)) | (nc << NCROSS_SHIFT) | F_SKIPDISK;
                         }
                     } else {
-                        defl = COLD(C_PSI) + arc_angle(COLD(C_CS), COLD(C_CC), dg.s, dg.c, yn[2] - y[2]);
+                        defl = COLD(C_PSI) + arc_angle(s0, c0, dg.s, dg.c, yn[2] - y[2]);
                         double sp, cp;
                         sincos_fast(yn[2], &sp, &cp);
                         const double nx = dg.s * cp, ny = dg.s * sp, nz = dg.c;
@@ -384,9 +386,9 @@ trace_kernel(const Hot hp) {
                                     COLD(C_EVC) = h - fb * h / (fb - fa);
                                     locate = true;
                                 } else {
-                                    const double s1 = COLD(C_CS), c1 = COLD(C_CC), dphi = yn[2] - y[2];
-                                    double arc = arc_angle_short(s1, c1, dg.s, dg.c, dphi);
-                                    if (arc < 0.0) arc = arc_angle(s1, c1, dg.s, dg.c, dphi);
+                                    const double dphi = yn[2] - y[2];
+                                    double arc = arc_angle_short(s0, c0, dg.s, dg.c, dphi);
+                                    if (arc < 0.0) arc = arc_angle(s0, c0, dg.s, dg.c, dphi);
                                     COLD(C_PSI) += arc;
                                 }
                             }
