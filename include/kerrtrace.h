@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define KT_VERSION_NUMBER 100
+#define KT_VERSION_NUMBER 110
 
 /* return codes */
 #define KT_OK 0
@@ -105,7 +105,7 @@ typedef struct kt_integrator {
 typedef struct kt_launch {
     int32_t persistent;     /* 1: persistent waves refill lanes from a global ticket;
                                0: one ray per lane, no refill */
-    int32_t block;          /* threads per workgroup: 64, 128, 256 or 512 */
+    int32_t block;          /* threads per workgroup: 64, 128 or 256 */
     int32_t blocks_per_cu;  /* persistent grid = CUs * blocks_per_cu; 0 = occupancy */
     int32_t batch;          /* ray ids taken per ticket fetch, 1..4096 */
 } kt_launch;
@@ -150,9 +150,12 @@ int kt_render(const kt_camera *camera, const kt_spacetime *spacetime, const kt_d
               const kt_source *source, const kt_integrator *integ, const kt_outputs *out,
               void *workspace, size_t workspace_bytes, void *hip_stream);
 
-/* kt_render with an explicit launch shape (NULL = defaults).  Per-ray
-   arithmetic does not depend on the launch shape: outputs are bit-identical
-   for every valid shape. */
+/* kt_render with an explicit launch shape (NULL = defaults).  With KT_FP64
+   the per-ray arithmetic does not depend on the launch shape: outputs are
+   bit-identical for every valid shape.  With KT_MIXED the FP32 part runs
+   only while every stepping lane of a wave is beyond r_switch, so which
+   rays use it depends on how rays share waves; every result still meets
+   h_budget or comes from the FP64 re-run. */
 int kt_render_ex(const kt_camera *camera, const kt_spacetime *spacetime, const kt_disk *disk,
                  const kt_source *source, const kt_integrator *integ, const kt_outputs *out,
                  void *workspace, size_t workspace_bytes, void *hip_stream,
@@ -160,6 +163,40 @@ int kt_render_ex(const kt_camera *camera, const kt_spacetime *spacetime, const k
 
 /* Workspace size in bytes for this camera and integrator (0 on bad input). */
 size_t kt_workspace_bytes(const kt_camera *camera, const kt_integrator *integ);
+
+/* One image of a batch: its own camera, spacetime, disk and source.  Disk
+   and source are disabled with enabled = 0. */
+typedef struct kt_image {
+    kt_camera camera;
+    kt_spacetime spacetime;
+    kt_disk disk;
+    kt_source source;
+} kt_image;
+
+#define KT_MAX_IMAGES 4096
+
+/* Render n_images images of any sizes, spins, inclinations and distances in
+   one persistent launch (the rays of all images share one ticket, so short
+   and long images balance each other out).  The images' outputs are
+   concatenated in table order: image k occupies entries
+   [first_k, first_k + nx_k*ny_k) of every output array, first_k being the
+   sum of nx*ny over the images before it; the total must be < 2^31.
+   n_images lies in [1, KT_MAX_IMAGES].  integ is shared by all images
+   (r_escape = 0 selects 1.1 r_obs per image).  Requesting ring needs every
+   image's source enabled.  workspace: at least
+   kt_workspace_bytes_batch(n_images, images, integ) bytes, 256-byte aligned.
+   With KT_FP64 each image's outputs are bit-identical to a kt_render_ex of
+   that image alone with the same integrator; launch may be NULL (defaults).
+   The table is read during the call only.
+   Returns KT_OK, KT_EINVAL (naming the offending image), KT_ENOMEM or
+   KT_EDEVICE. */
+int kt_render_batch(int32_t n_images, const kt_image *images, const kt_integrator *integ,
+                    const kt_outputs *out, void *workspace, size_t workspace_bytes,
+                    void *hip_stream, const kt_launch *launch);
+
+/* Workspace size in bytes for kt_render_batch (0 on bad input). */
+size_t kt_workspace_bytes_batch(int32_t n_images, const kt_image *images,
+                                const kt_integrator *integ);
 
 /* Initial state of every pixel (Sect. 2.3), for checking the camera alone:
    state is a device array of 7*nx*ny doubles laid out SoA as

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "kerrtrace.h"
 #include "kt_internal.h"
@@ -65,7 +66,7 @@ int validate_common(const kt_camera* cam, const kt_spacetime* st) {
 
 // Per-image camera constants at (r_obs, incl) from the Kerr metric
 // (eq:Kerr) and the observer tetrad (eq:matrix, second eq:momentums).
-void camera_constants(const kt_camera* cam, const kt_spacetime* st, kt::Params& p) {
+void camera_constants(const kt_camera* cam, const kt_spacetime* st, kt::Image& im) {
     const double M = st->M, a = st->a, r0 = cam->r_obs;
     const double s = std::sin(cam->incl), c = std::cos(cam->incl);
     const double Sig = r0 * r0 + a * a * c * c;
@@ -74,73 +75,26 @@ void camera_constants(const kt_camera* cam, const kt_spacetime* st, kt::Params& 
     const double g_phph = s * s * (r0 * r0 + a * a + 2.0 * M * a * a * r0 * s * s / Sig);
     // g_tph^2 - g_tt g_phph = Delta sin^2 for Kerr, so A_t = sqrt(g_phph / (Delta sin^2))
     const double At = std::sqrt(g_phph / (Del * s * s));
-    p.E0 = 1.0 / At;
-    p.cE = g_tph / (r0 * std::sqrt(g_phph));
-    p.cL = -std::sqrt(g_phph) / r0;
-    p.cth = std::sqrt(Sig) / r0;
-    p.g_rr = Sig / Del;
-    p.r0 = r0;
-    p.incl = cam->incl;
-    p.inv_r0 = 1.0 / r0;
-    p.fov_x = cam->fov_x;
-    p.fov_y = cam->fov_y;
-    p.dx = 2.0 * cam->fov_x / cam->nx;
-    p.dy = 2.0 * cam->fov_y / cam->ny;
-    p.nx = cam->nx;
-    p.ny = cam->ny;
-    p.n_rays = cam->nx * cam->ny;
-    p.M = M;
-    p.a = a;
-    p.a2 = a * a;
-    p.two_a2 = 2.0 * a * a;
+    im.E0 = 1.0 / At;
+    im.cE = g_tph / (r0 * std::sqrt(g_phph));
+    im.cL = -std::sqrt(g_phph) / r0;
+    im.cth = std::sqrt(Sig) / r0;
+    im.g_rr = Sig / Del;
+    im.r0 = r0;
+    im.incl = cam->incl;
+    im.fov_x = cam->fov_x;
+    im.fov_y = cam->fov_y;
+    im.dx = 2.0 * cam->fov_x / cam->nx;
+    im.dy = 2.0 * cam->fov_y / cam->ny;
+    im.nx = cam->nx;
+    im.ny = cam->ny;
+    im.M = M;
+    im.a = a;
+    im.a2 = a * a;
+    im.two_a2 = 2.0 * a * a;
 }
 
-size_t ws_bytes(const kt_camera* cam, const kt_integrator* integ) {
-    size_t n = static_cast<size_t>(cam->nx) * static_cast<size_t>(cam->ny);
-    size_t b = kt::ws_fb_list_offset(n);
-    if (integ->precision == KT_MIXED) b = kt::ws_need_offset(n) + n;
-    return (b + 255) & ~static_cast<size_t>(255);
-}
-
-}  // namespace
-
-extern "C" {
-
-const char* kt_last_error(void) { return g_err; }
-
-int kt_version(void) { return KT_VERSION_NUMBER; }
-
-size_t kt_workspace_bytes(const kt_camera* camera, const kt_integrator* integ) {
-    if (!camera || !integ || camera->nx < 1 || camera->ny < 1) return 0;
-    return ws_bytes(camera, integ);
-}
-
-int kt_init_rays(const kt_camera* camera, const kt_spacetime* spacetime, double* state,
-                 uint8_t* invalid, void* hip_stream) {
-    g_err[0] = 0;
-    int rc = validate_common(camera, spacetime);
-    if (rc) return rc;
-    if (!state || !invalid) return fail(KT_EINVAL, "state and invalid must not be NULL");
-    if (!(camera->r_obs > horizon(spacetime->M, spacetime->a)))
-        return fail(KT_EINVAL, "r_obs must lie outside the horizon");
-    kt::Params p;
-    std::memset(&p, 0, sizeof p);
-    camera_constants(camera, spacetime, p);
-    if (kt::launch_init_rays(p, state, invalid, hip_stream))
-        return fail(KT_EDEVICE, "init kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
-    return KT_OK;
-}
-
-int kt_render_ex(const kt_camera* camera, const kt_spacetime* spacetime, const kt_disk* disk,
-                 const kt_source* source, const kt_integrator* integ, const kt_outputs* out,
-                 void* workspace, size_t workspace_bytes, void* hip_stream, const kt_launch* launch) {
-    g_err[0] = 0;
-    int rc = validate_common(camera, spacetime);
-    if (rc) return rc;
-    if (!integ || !out) return fail(KT_EINVAL, "integ and out must not be NULL");
-    if (!out->fate) return fail(KT_EINVAL, "out->fate must not be NULL");
-    const double M = spacetime->M, a = spacetime->a;
-    const double r_plus = horizon(M, a);
+int validate_integ(const kt_integrator* integ) {
     if (integ->method != KT_RK4_S && integ->method != KT_DP45)
         return fail(KT_EINVAL, "unknown integrator method %d", integ->method);
     if (integ->precision != KT_FP64 && integ->precision != KT_MIXED)
@@ -160,10 +114,23 @@ int kt_render_ex(const kt_camera* camera, const kt_spacetime* spacetime, const k
     if (!(integ->capture_buffer >= 0.0)) return fail(KT_EINVAL, "capture_buffer must be >= 0");
     if (integ->max_steps < 1 || integ->max_steps > 100000000)
         return fail(KT_EINVAL, "max_steps must lie in [1, 1e8]");
+    return KT_OK;
+}
+
+// Validate one image and fill its table entry (everything but `first`).
+int make_image(const kt_camera* camera, const kt_spacetime* spacetime, const kt_disk* disk,
+               const kt_source* source, const kt_integrator* integ, bool want_ring, kt::Image& im) {
+    int rc = validate_common(camera, spacetime);
+    if (rc) return rc;
+    std::memset(&im, 0, sizeof im);
+    camera_constants(camera, spacetime, im);
+    const double r_plus = horizon(spacetime->M, spacetime->a);
     const double r_cap = r_plus + integ->capture_buffer;
     if (!(camera->r_obs > r_cap)) return fail(KT_EINVAL, "r_obs must exceed r_+ + capture_buffer");
     const double r_esc = integ->r_escape == 0.0 ? 1.1 * camera->r_obs : integ->r_escape;
     if (!(r_esc > camera->r_obs)) return fail(KT_EINVAL, "r_escape must exceed r_obs");
+    im.r_cap = r_cap;
+    im.r_esc = r_esc;
 
     const bool disk_on = disk && disk->enabled;
     if (disk_on) {
@@ -171,15 +138,36 @@ int kt_render_ex(const kt_camera* camera, const kt_spacetime* spacetime, const k
             return fail(KT_EINVAL, "non-finite disk parameter");
         if (!(disk->r_in > r_plus && disk->r_out > disk->r_in))
             return fail(KT_EINVAL, "disk needs r_+ < r_in < r_out");
+        im.disk_on = 1;
+        im.r_in = disk->r_in;
+        im.r_out = disk->r_out;
+        im.emis_q = disk->emis_index;
     }
     const bool src_on = source && source->enabled;
     if (src_on) {
         if (!std::isfinite(source->r_src) || !(source->r_src > r_cap))
             return fail(KT_EINVAL, "r_src must be finite and outside r_+ + capture_buffer");
+        im.src_on = 1;
+        im.r_src = source->r_src;
+        im.src_tol = 1e-12 * source->r_src;
+        // the source sits at (theta, phi) = (pi - incl, pi)
+        const double ts = M_PI - camera->incl;
+        im.src_n[0] = std::sin(ts) * std::cos(M_PI);
+        im.src_n[1] = std::sin(ts) * std::sin(M_PI);
+        im.src_n[2] = std::cos(ts);
     }
-    if (out->ring && !(src_on && out->deflection))
-        return fail(KT_EINVAL, "ring needs an enabled source and a deflection output");
+    if (want_ring && !src_on) return fail(KT_EINVAL, "ring needs an enabled source and a deflection output");
+    return KT_OK;
+}
 
+bool is_mixed(const kt_integrator* integ) { return integ->precision == KT_MIXED; }
+
+// The launch sequence shared by single and batch renders.  `table` holds the
+// validated images with their `first` offsets; for one image it travels in
+// Params and the device table is the workspace copy of img0.
+int render_images(const std::vector<kt::Image>& table, int64_t n_rays, const kt_integrator* integ,
+                  const kt_outputs* out, void* workspace, size_t workspace_bytes, void* hip_stream,
+                  const kt_launch* launch) {
     kt_launch ln{1, 256, 0, 32};
     if (launch) ln = *launch;
     if (ln.block != 64 && ln.block != 128 && ln.block != 256)
@@ -188,18 +176,17 @@ int kt_render_ex(const kt_camera* camera, const kt_spacetime* spacetime, const k
     if (ln.blocks_per_cu < 0 || ln.blocks_per_cu > 64)
         return fail(KT_EINVAL, "launch blocks_per_cu must lie in [0, 64]");
 
-    const size_t need = ws_bytes(camera, integ);
+    const int32_t n_images = static_cast<int32_t>(table.size());
+    const bool batch = n_images > 1;
+    const kt::WsLayout w = kt::ws_layout(static_cast<size_t>(n_rays), table.size(), batch, is_mixed(integ));
     if (!workspace) return fail(KT_EINVAL, "workspace must not be NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
         return fail(KT_EINVAL, "workspace must be 256-byte aligned");
-    if (workspace_bytes < need)
-        return fail(KT_ENOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
+    if (workspace_bytes < w.total)
+        return fail(KT_ENOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes, w.total);
 
     kt::Params p;
     std::memset(&p, 0, sizeof p);
-    camera_constants(camera, spacetime, p);
-    p.r_cap = r_cap;
-    p.r_esc = r_esc;
     p.method = integ->method;
     p.precision = integ->precision;
     p.h_fixed = integ->h_fixed;
@@ -210,22 +197,9 @@ int kt_render_ex(const kt_camera* camera, const kt_spacetime* spacetime, const k
     p.max_evals = 16 * integ->max_steps;
     p.h_budget = integ->h_budget;
     p.r_switch = integ->r_switch;
-    p.disk_on = disk_on ? 1 : 0;
-    if (disk_on) {
-        p.r_in = disk->r_in;
-        p.r_out = disk->r_out;
-        p.emis_q = disk->emis_index;
-    }
-    p.src_on = src_on ? 1 : 0;
-    if (src_on) {
-        p.r_src = source->r_src;
-        p.src_tol = 1e-12 * source->r_src;
-        // the source sits at (theta, phi) = (pi - incl, pi)
-        const double ts = M_PI - camera->incl;
-        p.src_n[0] = std::sin(ts) * std::cos(M_PI);
-        p.src_n[1] = std::sin(ts) * std::sin(M_PI);
-        p.src_n[2] = std::cos(ts);
-    }
+    p.n_rays = n_rays;
+    p.n_images = n_images;
+    p.img0 = table[0];
     p.out.fate = out->fate;
     p.out.r_hit = out->r_hit;
     p.out.g = out->g;
@@ -246,24 +220,28 @@ int kt_render_ex(const kt_camera* camera, const kt_spacetime* spacetime, const k
     p.ticket = reinterpret_cast<uint32_t*>(ws + kt::WS_TICKET);
     p.acc = reinterpret_cast<unsigned long long*>(ws + kt::WS_ACC);
     p.fb_count = reinterpret_cast<uint32_t*>(ws + kt::WS_FB_COUNT);
-    p.rc_buf = reinterpret_cast<double*>(ws + kt::WS_RC);
     p.ws_params = reinterpret_cast<kt::Params*>(ws + kt::WS_PARAMS);
-    p.need_fb = reinterpret_cast<uint8_t*>(ws + kt::ws_need_offset(static_cast<size_t>(p.n_rays)));
-    p.fb_list = reinterpret_cast<uint32_t*>(ws + kt::ws_fb_list_offset(static_cast<size_t>(p.n_rays)));
+    p.images = batch ? reinterpret_cast<const kt::Image*>(ws + w.images) : &p.ws_params->img0;
+    p.rc_buf = reinterpret_cast<double*>(ws + w.rc);
+    p.fb_list = reinterpret_cast<uint32_t*>(ws + w.fb_list);
+    p.need_fb = reinterpret_cast<uint8_t*>(ws + w.need);
     p.persistent = ln.persistent ? 1 : 0;
     p.batch = ln.batch;
     p.from_list = 0;
 
+    if (batch && kt::launch_upload_images(table.data(), n_images, reinterpret_cast<kt::Image*>(ws + w.images),
+                                          hip_stream))
+        return fail(KT_EDEVICE, "image table upload failed: %s", hipGetErrorString(hipGetLastError()));
     if (kt::launch_ws_init(p, hip_stream))
         return fail(KT_EDEVICE, "workspace init launch failed: %s", hipGetErrorString(hipGetLastError()));
+    const int64_t lane_grid = (n_rays + ln.block - 1) / ln.block;
     int grid;
     if (p.persistent) {
         const int per_cu = ln.blocks_per_cu > 0 ? ln.blocks_per_cu : kt::trace_max_blocks_per_cu(p, ln.block);
         grid = device_cus() * per_cu;
-        const int64_t needed = (static_cast<int64_t>(p.n_rays) + ln.block - 1) / ln.block;
-        if (grid > needed) grid = static_cast<int>(needed);
+        if (grid > lane_grid) grid = static_cast<int>(lane_grid);
     } else {
-        grid = static_cast<int>((static_cast<int64_t>(p.n_rays) + ln.block - 1) / ln.block);
+        grid = static_cast<int>(lane_grid);
     }
     if (grid < 1) grid = 1;
     if (kt::launch_trace(p, grid, ln.block, hip_stream))
@@ -273,8 +251,7 @@ int kt_render_ex(const kt_camera* camera, const kt_spacetime* spacetime, const k
         // list whose length stays on the device
         if (kt::launch_fallback_list(p, hip_stream))
             return fail(KT_EDEVICE, "fallback list launch failed: %s", hipGetErrorString(hipGetLastError()));
-        int grid2 = ln.persistent ? grid
-                                  : static_cast<int>((static_cast<int64_t>(p.n_rays) + ln.block - 1) / ln.block);
+        int grid2 = ln.persistent ? grid : static_cast<int>(lane_grid);
         if (grid2 < 1) grid2 = 1;
         if (kt::launch_trace_fallback(p, grid2, ln.block, hip_stream))
             return fail(KT_EDEVICE, "fallback trace launch failed: %s", hipGetErrorString(hipGetLastError()));
@@ -288,11 +265,113 @@ int kt_render_ex(const kt_camera* camera, const kt_spacetime* spacetime, const k
     return KT_OK;
 }
 
+int validate_outputs(const kt_outputs* out) {
+    if (!out->fate) return fail(KT_EINVAL, "out->fate must not be NULL");
+    if (out->ring && !out->deflection)
+        return fail(KT_EINVAL, "ring needs an enabled source and a deflection output");
+    return KT_OK;
+}
+
+// Table of a batch with `first` offsets; on error returns the code with the
+// image named in the message.
+int make_table(int32_t n_images, const kt_image* images, const kt_integrator* integ, bool want_ring,
+               std::vector<kt::Image>& table, int64_t* n_rays) {
+    if (n_images < 1 || n_images > KT_MAX_IMAGES)
+        return fail(KT_EINVAL, "n_images must lie in [1, %d] (got %d)", KT_MAX_IMAGES, n_images);
+    if (!images) return fail(KT_EINVAL, "images must not be NULL");
+    table.resize(static_cast<size_t>(n_images));
+    int64_t first = 0;
+    for (int32_t k = 0; k < n_images; ++k) {
+        const kt_image& in = images[k];
+        int rc = make_image(&in.camera, &in.spacetime, &in.disk, &in.source, integ, want_ring, table[k]);
+        if (rc) {
+            char msg[512];
+            std::snprintf(msg, sizeof msg, "image %d: %s", k, g_err);
+            std::snprintf(g_err, sizeof g_err, "%s", msg);
+            return rc;
+        }
+        table[k].first = first;
+        first += static_cast<int64_t>(in.camera.nx) * in.camera.ny;
+        if (first >= (int64_t{1} << 31)) return fail(KT_EINVAL, "total rays of the batch must be < 2^31");
+    }
+    *n_rays = first;
+    return KT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kt_last_error(void) { return g_err; }
+
+int kt_version(void) { return KT_VERSION_NUMBER; }
+
+size_t kt_workspace_bytes(const kt_camera* camera, const kt_integrator* integ) {
+    if (!camera || !integ || camera->nx < 1 || camera->ny < 1) return 0;
+    const size_t n = static_cast<size_t>(camera->nx) * static_cast<size_t>(camera->ny);
+    return kt::ws_layout(n, 1, false, is_mixed(integ)).total;
+}
+
+size_t kt_workspace_bytes_batch(int32_t n_images, const kt_image* images, const kt_integrator* integ) {
+    if (!images || !integ || n_images < 1 || n_images > KT_MAX_IMAGES) return 0;
+    size_t n = 0;
+    for (int32_t k = 0; k < n_images; ++k) {
+        if (images[k].camera.nx < 1 || images[k].camera.ny < 1) return 0;
+        n += static_cast<size_t>(images[k].camera.nx) * static_cast<size_t>(images[k].camera.ny);
+    }
+    return kt::ws_layout(n, static_cast<size_t>(n_images), n_images > 1, is_mixed(integ)).total;
+}
+
+int kt_init_rays(const kt_camera* camera, const kt_spacetime* spacetime, double* state,
+                 uint8_t* invalid, void* hip_stream) {
+    g_err[0] = 0;
+    int rc = validate_common(camera, spacetime);
+    if (rc) return rc;
+    if (!state || !invalid) return fail(KT_EINVAL, "state and invalid must not be NULL");
+    if (!(camera->r_obs > horizon(spacetime->M, spacetime->a)))
+        return fail(KT_EINVAL, "r_obs must lie outside the horizon");
+    kt::Params p;
+    std::memset(&p, 0, sizeof p);
+    camera_constants(camera, spacetime, p.img0);
+    p.n_rays = static_cast<int64_t>(camera->nx) * camera->ny;
+    if (kt::launch_init_rays(p, state, invalid, hip_stream))
+        return fail(KT_EDEVICE, "init kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+    return KT_OK;
+}
+
+int kt_render_ex(const kt_camera* camera, const kt_spacetime* spacetime, const kt_disk* disk,
+                 const kt_source* source, const kt_integrator* integ, const kt_outputs* out,
+                 void* workspace, size_t workspace_bytes, void* hip_stream, const kt_launch* launch) {
+    g_err[0] = 0;
+    int rc = validate_common(camera, spacetime);
+    if (rc) return rc;
+    if (!integ || !out) return fail(KT_EINVAL, "integ and out must not be NULL");
+    if ((rc = validate_integ(integ)) || (rc = validate_outputs(out))) return rc;
+    std::vector<kt::Image> table(1);
+    if ((rc = make_image(camera, spacetime, disk, source, integ, out->ring != nullptr, table[0]))) return rc;
+    table[0].first = 0;
+    const int64_t n = static_cast<int64_t>(camera->nx) * camera->ny;
+    return render_images(table, n, integ, out, workspace, workspace_bytes, hip_stream, launch);
+}
+
 int kt_render(const kt_camera* camera, const kt_spacetime* spacetime, const kt_disk* disk,
               const kt_source* source, const kt_integrator* integ, const kt_outputs* out,
               void* workspace, size_t workspace_bytes, void* hip_stream) {
     return kt_render_ex(camera, spacetime, disk, source, integ, out, workspace, workspace_bytes,
                         hip_stream, nullptr);
+}
+
+int kt_render_batch(int32_t n_images, const kt_image* images, const kt_integrator* integ,
+                    const kt_outputs* out, void* workspace, size_t workspace_bytes, void* hip_stream,
+                    const kt_launch* launch) {
+    g_err[0] = 0;
+    if (!integ || !out) return fail(KT_EINVAL, "integ and out must not be NULL");
+    int rc;
+    if ((rc = validate_integ(integ)) || (rc = validate_outputs(out))) return rc;
+    std::vector<kt::Image> table;
+    int64_t n = 0;
+    if ((rc = make_table(n_images, images, integ, out->ring != nullptr, table, &n))) return rc;
+    return render_images(table, n, integ, out, workspace, workspace_bytes, hip_stream, launch);
 }
 
 }  // extern "C"

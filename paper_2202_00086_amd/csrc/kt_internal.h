@@ -1,4 +1,4 @@
-// kt_internal.h -- parameter block shared by the host runtime and the kernels.
+// kt_internal.h -- parameter blocks shared by the host runtime and the kernels.
 #pragma once
 
 #include <stddef.h>
@@ -8,18 +8,7 @@
 
 namespace kt {
 
-// Workspace layout (bytes from the start of the caller's buffer).
-constexpr size_t WS_TICKET = 0;       // uint32 ray ticket
-constexpr size_t WS_ACC = 64;         // uint64[16]: evals, evals_fp32, -, fate histogram at 8..15
-constexpr size_t WS_FB_COUNT = 192;   // uint32 fallback list length
-constexpr size_t WS_PARAMS = 256;     // device copy of Params (read by the kernels' cold paths)
-constexpr size_t WS_PARAMS_MAX = 1792;
-constexpr size_t WS_RC = WS_PARAMS + WS_PARAMS_MAX;  // double[n_rays] disk crossing radius per ray
-// then, for KT_MIXED only: uint32[n_rays] ray ids for the FP64 re-run and
-// uint8[n_rays] re-run flags
-inline size_t ws_fb_list_offset(size_t n_rays) { return (WS_RC + 8 * n_rays + 255) & ~size_t(255); }
-inline size_t ws_need_offset(size_t n_rays) { return (ws_fb_list_offset(n_rays) + 4 * n_rays + 255) & ~size_t(255); }
-constexpr int ACC_EVALS = 0, ACC_EVALS_FP32 = 1;
+constexpr int ACC_EVALS = 0, ACC_EVALS_FP32 = 1;  // acc[8..15]: fate histogram
 
 struct Outputs {
     uint8_t* fate;
@@ -29,24 +18,21 @@ struct Outputs {
     kt_stats* stats;
 };
 
-// Everything a trace kernel needs, passed by value.
-struct Params {
-    // spacetime
+// Everything that belongs to one image: spacetime, camera constants, disk,
+// source, and where its rays sit in the batch.
+struct Image {
+    // spacetime (eq:Kerr) and the end radii
     double M, a, a2, two_a2;
     double r_cap, r_esc;
     // camera and per-image camera constants (Sect. 2.3)
-    double r0, incl, inv_r0, fov_x, fov_y, dx, dy;
+    double r0, incl, fov_x, fov_y, dx, dy;
     double E0;      // 1 / A_t
     double cE;      // g_tphi / (r0 sqrt(g_phph)):  E = E0 + x cE
     double cL;      // -sqrt(g_phph) / r0:          L = x cL
     double cth;     // sqrt(g_thth) / r0:           p_theta = y cth
     double g_rr;    // g_rr at the camera:          p_r = -sqrt(g_rr (1 - (y/r0)^2 - (x/r0)^2))
-    int32_t nx, ny, n_rays;
-    // integrator
-    int32_t method, precision;
-    double h_fixed, rtol, atol, h_init;
-    int64_t max_steps, max_evals;
-    double h_budget, r_switch;
+    int32_t nx, ny;
+    int64_t first;  // ray id of pixel 0 (outputs of this image start here)
     // disk (Sect. 5)
     int32_t disk_on;
     double r_in, r_out, emis_q;
@@ -54,6 +40,20 @@ struct Params {
     int32_t src_on;
     double r_src, src_tol;
     double src_n[3];  // unit vector towards the source
+};
+
+// Everything a render needs, copied into the workspace by ws_init.
+struct Params {
+    // integrator (shared by all images)
+    int32_t method, precision;
+    double h_fixed, rtol, atol, h_init;
+    int64_t max_steps, max_evals;
+    double h_budget, r_switch;
+    // images: a single render uses a one-entry table (img0)
+    int64_t n_rays;
+    int32_t n_images;
+    const Image* images;  // device table
+    Image img0;
     // outputs and workspace
     Outputs out;
     uint32_t* ticket;
@@ -68,21 +68,49 @@ struct Params {
     int32_t from_list;  // take ray ids from fb_list[0 .. *fb_count)
 };
 
+// Workspace layout (byte offsets from the start of the caller's buffer).
+constexpr size_t WS_TICKET = 0;       // uint32 ray ticket
+constexpr size_t WS_ACC = 64;         // uint64[16]
+constexpr size_t WS_FB_COUNT = 192;   // uint32 fallback list length
+constexpr size_t WS_PARAMS = 256;     // device copy of Params
+constexpr size_t WS_PARAMS_MAX = 1792;
 static_assert(sizeof(Params) <= WS_PARAMS_MAX, "Params must fit its workspace slot");
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct WsLayout {
+    size_t images;   // Image[n_images] (batch renders)
+    size_t rc;       // double[n_rays] disk crossing radius per ray
+    size_t fb_list;  // uint32[n_rays] (KT_MIXED)
+    size_t need;     // uint8[n_rays] (KT_MIXED)
+    size_t total;
+};
+
+inline WsLayout ws_layout(size_t n_rays, size_t n_images, bool batch, bool mixed) {
+    WsLayout w;
+    w.images = WS_PARAMS + WS_PARAMS_MAX;
+    w.rc = align256(w.images + (batch ? n_images * sizeof(Image) : 0));
+    w.fb_list = align256(w.rc + 8 * n_rays);
+    w.need = align256(w.fb_list + (mixed ? 4 * n_rays : 0));
+    w.total = align256(w.need + (mixed ? n_rays : 0));
+    return w;
+}
 
 // The values the trace kernel's inner loop reads every step, passed by value
 // so they sit in scalar registers; everything else is read through `cold`.
+// For batch renders the per-image ones become per-lane values.
 struct Hot {
     double M, a, a2, two_a2;
     double rtol, atol, r_cap, r_esc, r_src, r_in, r_out;
     double h_budget, r_switch;  // KT_MIXED
     int32_t disk_on, src_on;
     int32_t max_steps, max_evals;
-    const Params* cold;  // the workspace copy of Params
+    const Params* cold;         // the workspace copy of Params
 };
 
 // Host-side launchers (kt_trace.hip).
 int launch_ws_init(const Params& p, void* stream);  // also copies p into the workspace
+int launch_upload_images(const Image* host, int32_t n, Image* dev, void* stream);
 int launch_trace(const Params& p, int grid, int block, void* stream);  // pass of p.precision
 int launch_fallback_list(const Params& p, void* stream);  // compact need_fb, switch the copy to from_list
 int launch_trace_fallback(const Params& p, int grid, int block, void* stream);  // FP64 re-run from the list

@@ -55,28 +55,65 @@ __device__ __forceinline__ double arc_angle_short(double s1, double c1, double s
     return h <= 0.0625 ? 2.0 * asin_small(h) : -1.0;
 }
 
-// Initial state of pixel `ray` (second eq:momentums with p_r ingoing).
-// Returns false when x^2 + y^2 >= r0^2 (no real p_r).
-__device__ __forceinline__ bool camera_state(const Params& p, int32_t ray, double z[5], double* E,
+// Initial state of pixel `pix` of image `im` (second eq:momentums with p_r
+// ingoing).  Returns false when x^2 + y^2 >= r0^2 (no real p_r).
+__device__ __forceinline__ bool camera_state(const Image& im, int32_t pix, double z[5], double* E,
                                              double* L) {
     // separate roundings, no FMA: the pixel centre is the same double the
     // plain expression -fov + (i + 1/2) dx gives on any IEEE machine
 #pragma clang fp contract(off)
-    const int32_t j = ray / p.nx;
-    const int32_t i = ray - j * p.nx;
-    const double x = -p.fov_x + (static_cast<double>(i) + 0.5) * p.dx;
-    const double y = -p.fov_y + (static_cast<double>(j) + 0.5) * p.dy;
-    const double Pth = y / p.r0;   // observer-frame P^theta with P^t = 1
-    const double Pph = -x / p.r0;  // observer-frame P^phi
+    const int32_t j = pix / im.nx;
+    const int32_t i = pix - j * im.nx;
+    const double x = -im.fov_x + (static_cast<double>(i) + 0.5) * im.dx;
+    const double y = -im.fov_y + (static_cast<double>(j) + 0.5) * im.dy;
+    const double Pth = y / im.r0;   // observer-frame P^theta with P^t = 1
+    const double Pph = -x / im.r0;  // observer-frame P^phi
     const double rad = 1.0 - Pth * Pth - Pph * Pph;
-    *E = p.E0 + x * p.cE;
-    *L = x * p.cL;
-    z[0] = p.r0;
-    z[1] = p.incl;
+    *E = im.E0 + x * im.cE;
+    *L = x * im.cL;
+    z[0] = im.r0;
+    z[1] = im.incl;
     z[2] = 0.0;
-    z[3] = rad > 0.0 ? -sqrt(p.g_rr * rad) : 0.0;
-    z[4] = y * p.cth;
+    z[3] = rad > 0.0 ? -sqrt(im.g_rr * rad) : 0.0;
+    z[4] = y * im.cth;
     return rad > 0.0;
+}
+
+// Index of the image that ray id `ray` belongs to (binary search over the
+// images' first ray ids).
+__device__ __forceinline__ int find_image(const Params& P, int64_t ray) {
+    int lo = 0, hi = P.n_images - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P.images[mid].first <= ray)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// The per-image values the step loop needs.  For a single image they come
+// from kernel arguments (wave-uniform); for a batch they are loaded per ray.
+struct LaneImg {
+    Spacetime st;
+    double r_cap, r_esc, r_src, r_in, r_out;
+    int32_t disk_on, src_on;
+    int32_t k;  // image index
+};
+
+__device__ __forceinline__ LaneImg lane_img(const Image& im, int k) {
+    LaneImg li;
+    li.st = Spacetime{im.M, im.a, im.a2, im.two_a2};
+    li.r_cap = im.r_cap;
+    li.r_esc = im.r_esc;
+    li.r_src = im.r_src;
+    li.r_in = im.r_in;
+    li.r_out = im.r_out;
+    li.disk_on = im.disk_on;
+    li.src_on = im.src_on;
+    li.k = k;
+    return li;
 }
 
 // Lane flags, packed in one int.
@@ -141,20 +178,28 @@ __device__ __forceinline__ double error_msq(const double er[5], const double sc[
     return 0.2 * fma(e0, e0, fma(e1, e1, fma(e2, e2, fma(e3, e3, e4 * e4))));
 }
 
-template <int METHOD, int PREC>
+template <int METHOD, int PREC, bool BATCH>
 __global__ void __launch_bounds__(BLOCK_MAX) __attribute__((amdgpu_waves_per_eu(KT_WAVES_PER_EU)))
 trace_kernel(const Hot hp) {
     constexpr int EVALS_PER_STEP = (METHOD == KT_DP45) ? 6 : 4;
     constexpr bool S_TIME = (METHOD == KT_RK4_S);
     constexpr bool MIXED = (PREC == KT_MIXED) && (METHOD == KT_DP45);
-    const Spacetime32 sf{static_cast<float>(hp.M), static_cast<float>(hp.a), static_cast<float>(hp.a2)};
     __shared__ double cold[N_COLD][BLOCK_MAX];
     const int tid = threadIdx.x;
 #define COLD(f) cold[f][tid]
     // cold parameters are read from the workspace copy where needed
     const Params& P = *hp.cold;
 
-    const Spacetime st{hp.M, hp.a, hp.a2, hp.two_a2};
+    LaneImg li;
+    li.st = Spacetime{hp.M, hp.a, hp.a2, hp.two_a2};
+    li.r_cap = hp.r_cap;
+    li.r_esc = hp.r_esc;
+    li.r_src = hp.r_src;
+    li.r_in = hp.r_in;
+    li.r_out = hp.r_out;
+    li.disk_on = hp.disk_on;
+    li.src_on = hp.src_on;
+    li.k = 0;
     const uint32_t lane = __lane_id();
     const uint32_t n_total = P.from_list ? *P.fb_count : static_cast<uint32_t>(P.n_rays);
 
@@ -202,7 +247,14 @@ trace_kernel(const Hot hp) {
             if (ray < 0 && rank < avail) {
                 const uint32_t slot = q_next + rank;
                 ray = P.from_list ? static_cast<int32_t>(P.fb_list[slot]) : static_cast<int32_t>(slot);
-                fl = camera_state(P, ray, y, &E, &L) ? (F_VALID | F_FRESH) : 0;
+                if constexpr (BATCH) {
+                    const int k = find_image(P, ray);
+                    const Image& im = P.images[k];
+                    li = lane_img(im, k);
+                    fl = camera_state(im, ray - static_cast<int32_t>(im.first), y, &E, &L) ? (F_VALID | F_FRESH) : 0;
+                } else {
+                    fl = camera_state(P.img0, ray, y, &E, &L) ? (F_VALID | F_FRESH) : 0;
+                }
                 h = (METHOD == KT_DP45) ? P.h_init : P.h_fixed;
                 nsteps = 0;
                 nevals = 0;
@@ -214,6 +266,7 @@ trace_kernel(const Hot hp) {
         if (ray < 0) continue;
 
         // ---- one step per busy lane ----------------------------------------
+        const Spacetime st = li.st;
         const RayConst rc = make_ray_const(st, E, L);
         const double NaN = __builtin_nan("");
         int fate = -1;  // >= 0 once the ray ends
@@ -245,6 +298,7 @@ trace_kernel(const Hot hp) {
             // sin/cos of theta at the step start (from the last evaluation there)
             const double s0 = COLD(C_CS), c0 = COLD(C_CC);
             if constexpr (MIXED) {
+                const Spacetime32 sf{static_cast<float>(st.M), static_cast<float>(st.a), static_cast<float>(st.a2)};
                 // the FP32 mass part only when every stepping lane of the wave
                 // is beyond r_switch (a wave-uniform branch)
                 if (__all(y[0] >= hp.r_switch)) {
@@ -261,13 +315,13 @@ trace_kernel(const Hot hp) {
             if (locating) {
                 // Illinois regula falsi on the event function
                 const bool src = (fl & F_EVSRC) != 0;
-                const double fc = src ? yn[0] - hp.r_src : yn[1] - HALF_PI;
-                const double tol = src ? P.src_tol : 1e-14;
+                const double fc = src ? yn[0] - li.r_src : yn[1] - HALF_PI;
+                const double tol = src ? (BATCH ? P.images[li.k].src_tol : P.img0.src_tol) : 1e-14;
                 const int it = ((fl >> EVIT_SHIFT) & 0xff) + 1;
                 fl = (fl & ~(0xff << EVIT_SHIFT)) | (it << EVIT_SHIFT);
                 if (fabs(fc) <= tol || it >= 64) {
                     if (!src) {
-                        if (yn[0] >= hp.r_in && yn[0] <= hp.r_out) {
+                        if (yn[0] >= li.r_in && yn[0] <= li.r_out) {
                             fate = KT_FATE_DISK;
                             r_c = yn[0];
                             thf = yn[1];
@@ -280,12 +334,13 @@ trace_kernel(const Hot hp) {
                         defl = COLD(C_PSI) + arc_angle(s0, c0, dg.s, dg.c, yn[2] - y[2]);
                         double sp, cp;
                         sincos_fast(yn[2], &sp, &cp);
+                        const double* sn = BATCH ? P.images[li.k].src_n : P.img0.src_n;
                         const double nx = dg.s * cp, ny = dg.s * sp, nz = dg.c;
-                        const double cx = ny * P.src_n[2] - nz * P.src_n[1];
-                        const double cy = nz * P.src_n[0] - nx * P.src_n[2];
-                        const double cz = nx * P.src_n[1] - ny * P.src_n[0];
+                        const double cx = ny * sn[2] - nz * sn[1];
+                        const double cy = nz * sn[0] - nx * sn[2];
+                        const double cz = nx * sn[1] - ny * sn[0];
                         psi = atan2_upper(sqrt(fma(cx, cx, fma(cy, cy, cz * cz))),
-                                          fma(nx, P.src_n[0], fma(ny, P.src_n[1], nz * P.src_n[2])));
+                                          fma(nx, sn[0], fma(ny, sn[1], nz * sn[2])));
                         COLD(C_PSI) = defl;  // parked until the ray ends
                         COLD(C_SRCPSI) = psi;
                         fl |= F_SRCDONE;
@@ -347,7 +402,7 @@ trace_kernel(const Hot hp) {
                     fl &= ~F_RETAKE;
                     bool locate = false;
                     // thin disk: sign change of theta - pi/2 over the step
-                    if (hp.disk_on && !(fl & F_SKIPDISK)) {
+                    if (li.disk_on && !(fl & F_SKIPDISK)) {
                         const double ga = y[1] - HALF_PI, gb = yn[1] - HALF_PI;
                         if (ga * gb < 0.0) {
                             fl = (fl & ~(F_EVSRC | (0xff << EVIT_SHIFT))) | F_LOCATE;
@@ -358,7 +413,7 @@ trace_kernel(const Hot hp) {
                             COLD(C_EVC) = h - gb * h / (gb - ga);
                             locate = true;
                         } else if (gb == 0.0) {
-                            if (yn[0] >= hp.r_in && yn[0] <= hp.r_out) {
+                            if (yn[0] >= li.r_in && yn[0] <= li.r_out) {
                                 fate = KT_FATE_DISK;
                                 r_c = yn[0];
                                 thf = yn[1];
@@ -370,14 +425,14 @@ trace_kernel(const Hot hp) {
                         }
                     }
                     if (!locate && fate < 0) {
-                        if (yn[0] < hp.r_cap) {
+                        if (yn[0] < li.r_cap) {
                             fate = KT_FATE_CAPTURED;
                             thf = yn[1];
                             phf = yn[2];
                         } else {
-                            if (hp.src_on && !(fl & F_SRCDONE)) {
-                                if (y[0] < hp.r_src && yn[0] >= hp.r_src) {
-                                    const double fa = y[0] - hp.r_src, fb = yn[0] - hp.r_src;
+                            if (li.src_on && !(fl & F_SRCDONE)) {
+                                if (y[0] < li.r_src && yn[0] >= li.r_src) {
+                                    const double fa = y[0] - li.r_src, fb = yn[0] - li.r_src;
                                     fl = (fl & ~(0xff << EVIT_SHIFT)) | F_EVSRC | F_LOCATE;
                                     COLD(C_EVA) = 0.0;
                                     COLD(C_EVFA) = fa;
@@ -393,7 +448,7 @@ trace_kernel(const Hot hp) {
                                 }
                             }
                             if (!locate) {
-                                if (yn[0] > hp.r_esc) {
+                                if (yn[0] > li.r_esc) {
                                     fate = KT_FATE_ESCAPED;
                                     thf = yn[1];
                                     phf = yn[2];
@@ -497,26 +552,28 @@ __global__ void to_fallback_kernel(Params* wp) {
 // Keplerian redshift and observed intensity of every disk pixel from the
 // crossing radius the trace kernel parked in rc_buf (eq:redshift read as
 // g = 1 / (u^t (E - Omega L)); I_obs = g^3 I_em with I_em = (M/r)^q).
-__global__ void disk_obs_kernel(const Params p) {
+__global__ void disk_obs_kernel(const Params* pp) {
+    const Params& p = *pp;
     const int64_t n = p.n_rays;
     const double NaN = __builtin_nan("");
     for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < n;
          k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         double r_hit = NaN, g = NaN, inten = 0.0;
         if (p.out.fate[k] == KT_FATE_DISK) {
+            const Image& im = p.images[find_image(p, k)];
             double z[5], E, L;
-            camera_state(p, static_cast<int32_t>(k), z, &E, &L);
+            camera_state(im, static_cast<int32_t>(k - im.first), z, &E, &L);
             const double rc = p.rc_buf[k];
-            const double sM = sqrt(p.M);
-            const double Om = sM / fma(rc, sqrt(rc), p.a * sM);
+            const double sM = sqrt(im.M);
+            const double Om = sM / fma(rc, sqrt(rc), im.a * sM);
             const double inv_rc = 1.0 / rc;
-            const double gtt = -(1.0 - 2.0 * p.M * inv_rc);
-            const double gtp = -2.0 * p.M * p.a * inv_rc;
-            const double gpp = rc * rc + p.a2 + 2.0 * p.M * p.a2 * inv_rc;
+            const double gtt = -(1.0 - 2.0 * im.M * inv_rc);
+            const double gtp = -2.0 * im.M * im.a * inv_rc;
+            const double gpp = rc * rc + im.a2 + 2.0 * im.M * im.a2 * inv_rc;
             const double norm = -gtt - 2.0 * Om * gtp - Om * Om * gpp;  // (u^t)^-2
             r_hit = rc;
             g = sqrt(norm) / (E - Om * L);
-            inten = g * g * g * pow(p.M * inv_rc, p.emis_q);
+            inten = g * g * g * pow(im.M * inv_rc, im.emis_q);
         }
         if (p.out.r_hit) p.out.r_hit[k] = r_hit;
         if (p.out.g) p.out.g[k] = g;
@@ -538,6 +595,20 @@ __global__ void ws_init_kernel(const Params p) {
     if (t < 16) p.acc[t] = 0ull;
 }
 
+// Copy a chunk of the image table into device memory (the table travels in
+// kernel arguments, so nothing on the host has to outlive the call).
+constexpr int UPLOAD_CHUNK = 12;
+struct ImageChunk {
+    Image im[UPLOAD_CHUNK];
+    int32_t n, base;
+};
+static_assert(sizeof(ImageChunk) <= 3900, "image chunk must fit the kernel-argument limit");
+
+__global__ void upload_images_kernel(const ImageChunk c, Image* dev) {
+    const int t = threadIdx.x;
+    if (t < c.n) dev[c.base + t] = c.im[t];
+}
+
 __global__ void reset_ticket_kernel(uint32_t* ticket) {
     if (threadIdx.x == 0) *ticket = 0u;
 }
@@ -548,19 +619,26 @@ __device__ __forceinline__ double odd_pi_count(double v) {
     return floor((v + PI) / (2.0 * PI));
 }
 
-__global__ void ring_kernel(const double* __restrict__ defl, uint8_t* __restrict__ ring, int32_t nx,
-                            int32_t ny) {
-    const int64_t n = static_cast<int64_t>(nx) * ny;
+// Ring flags, within each image: an odd multiple of pi between a pixel's
+// deflection and its +i or +j neighbour's.
+__global__ void ring_kernel(const Params* pp) {
+    const Params& P = *pp;
+    const double* __restrict__ defl = P.out.deflection;
+    uint8_t* __restrict__ ring = P.out.ring;
+    const int64_t n = P.n_rays;
     for (int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; p < n;
          p += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int32_t j = static_cast<int32_t>(p / nx);
-        const int32_t i = static_cast<int32_t>(p - static_cast<int64_t>(j) * nx);
+        const Image& im = P.images[find_image(P, p)];
+        const int64_t pix = p - im.first;
+        const int32_t nx = im.nx;
+        const int32_t j = static_cast<int32_t>(pix / nx);
+        const int32_t i = static_cast<int32_t>(pix - static_cast<int64_t>(j) * nx);
         const double d = defl[p];
         uint8_t flag = 0;
         if (isfinite(d)) {
             const double k = odd_pi_count(d);
             if (i + 1 < nx && isfinite(defl[p + 1]) && odd_pi_count(defl[p + 1]) != k) flag = 1;
-            if (j + 1 < ny && isfinite(defl[p + nx]) && odd_pi_count(defl[p + nx]) != k) flag = 1;
+            if (j + 1 < im.ny && isfinite(defl[p + nx]) && odd_pi_count(defl[p + nx]) != k) flag = 1;
         }
         ring[p] = flag;
     }
@@ -589,12 +667,11 @@ __global__ void stats_kernel(const unsigned long long* acc, const uint32_t* fb_c
     }
 }
 
-__global__ void init_rays_kernel(const Params p, double* state, uint8_t* invalid) {
-    const int64_t n = p.n_rays;
+__global__ void init_rays_kernel(const Image im, int64_t n, double* state, uint8_t* invalid) {
     for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < n;
          k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         double z[5], E, L;
-        const bool ok = camera_state(p, static_cast<int32_t>(k), z, &E, &L);
+        const bool ok = camera_state(im, static_cast<int32_t>(k), z, &E, &L);
         for (int c = 0; c < 5; ++c) state[c * n + k] = z[c];
         state[5 * n + k] = E;
         state[6 * n + k] = L;
@@ -625,38 +702,59 @@ int launch_reset_ticket(const Params& p, void* stream) {
     return check_launch();
 }
 
+int launch_upload_images(const Image* host, int32_t n, Image* dev, void* stream) {
+    for (int32_t base = 0; base < n; base += UPLOAD_CHUNK) {
+        ImageChunk c;
+        c.n = n - base < UPLOAD_CHUNK ? n - base : UPLOAD_CHUNK;
+        c.base = base;
+        for (int t = 0; t < c.n; ++t) c.im[t] = host[base + t];
+        hipLaunchKernelGGL(upload_images_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), c, dev);
+        if (check_launch()) return -1;
+    }
+    return 0;
+}
+
 static Hot make_hot(const Params& p) {
+    const Image& im = p.img0;  // batch renders take the per-image values from the table
     Hot hp;
-    hp.M = p.M;
-    hp.a = p.a;
-    hp.a2 = p.a2;
-    hp.two_a2 = p.two_a2;
+    hp.M = im.M;
+    hp.a = im.a;
+    hp.a2 = im.a2;
+    hp.two_a2 = im.two_a2;
     hp.rtol = p.rtol;
     hp.atol = p.atol;
-    hp.r_cap = p.r_cap;
-    hp.r_esc = p.r_esc;
-    hp.r_src = p.r_src;
-    hp.r_in = p.r_in;
-    hp.r_out = p.r_out;
+    hp.r_cap = im.r_cap;
+    hp.r_esc = im.r_esc;
+    hp.r_src = im.r_src;
+    hp.r_in = im.r_in;
+    hp.r_out = im.r_out;
     hp.h_budget = p.h_budget;
     hp.r_switch = p.r_switch;
-    hp.disk_on = p.disk_on;
-    hp.src_on = p.src_on;
+    hp.disk_on = im.disk_on;
+    hp.src_on = im.src_on;
     hp.max_steps = static_cast<int32_t>(p.max_steps);
     hp.max_evals = static_cast<int32_t>(p.max_evals);
     hp.cold = p.ws_params;
     return hp;
 }
 
+template <int METHOD, int PREC>
+static void launch_variant(const Params& p, const Hot& hp, int grid, int block, hipStream_t s) {
+    if (p.n_images > 1)
+        hipLaunchKernelGGL((trace_kernel<METHOD, PREC, true>), dim3(grid), dim3(block), 0, s, hp);
+    else
+        hipLaunchKernelGGL((trace_kernel<METHOD, PREC, false>), dim3(grid), dim3(block), 0, s, hp);
+}
+
 int launch_trace(const Params& p, int grid, int block, void* stream) {
     const Hot hp = make_hot(p);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (p.method == KT_DP45 && p.precision == KT_MIXED)
-        hipLaunchKernelGGL((trace_kernel<KT_DP45, KT_MIXED>), dim3(grid), dim3(block), 0, s, hp);
+        launch_variant<KT_DP45, KT_MIXED>(p, hp, grid, block, s);
     else if (p.method == KT_DP45)
-        hipLaunchKernelGGL((trace_kernel<KT_DP45, KT_FP64>), dim3(grid), dim3(block), 0, s, hp);
+        launch_variant<KT_DP45, KT_FP64>(p, hp, grid, block, s);
     else
-        hipLaunchKernelGGL((trace_kernel<KT_RK4_S, KT_FP64>), dim3(grid), dim3(block), 0, s, hp);
+        launch_variant<KT_RK4_S, KT_FP64>(p, hp, grid, block, s);
     return check_launch();
 }
 
@@ -671,33 +769,38 @@ int launch_fallback_list(const Params& p, void* stream) {
 
 int launch_trace_fallback(const Params& p, int grid, int block, void* stream) {
     const Hot hp = make_hot(p);
-    hipLaunchKernelGGL((trace_kernel<KT_DP45, KT_FP64>), dim3(grid), dim3(block), 0,
-                       static_cast<hipStream_t>(stream), hp);
+    launch_variant<KT_DP45, KT_FP64>(p, hp, grid, block, static_cast<hipStream_t>(stream));
     return check_launch();
+}
+
+template <int METHOD, int PREC>
+static hipError_t occupancy_variant(const Params& p, int* nb, int block) {
+    if (p.n_images > 1)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, trace_kernel<METHOD, PREC, true>, block, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, trace_kernel<METHOD, PREC, false>, block, 0);
 }
 
 int trace_max_blocks_per_cu(const Params& p, int block) {
     int nb = 0;
     hipError_t e;
     if (p.method == KT_DP45 && p.precision == KT_MIXED)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<KT_DP45, KT_MIXED>, block, 0);
+        e = occupancy_variant<KT_DP45, KT_MIXED>(p, &nb, block);
     else if (p.method == KT_DP45)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<KT_DP45, KT_FP64>, block, 0);
+        e = occupancy_variant<KT_DP45, KT_FP64>(p, &nb, block);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<KT_RK4_S, KT_FP64>, block, 0);
+        e = occupancy_variant<KT_RK4_S, KT_FP64>(p, &nb, block);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 int launch_disk_obs(const Params& p, void* stream) {
     hipLaunchKernelGGL(disk_obs_kernel, dim3(small_grid(p.n_rays, 256)), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), p);
+                       static_cast<hipStream_t>(stream), p.ws_params);
     return check_launch();
 }
 
 int launch_ring(const Params& p, void* stream) {
-    const int64_t n = p.n_rays;
-    hipLaunchKernelGGL(ring_kernel, dim3(small_grid(n, 256)), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), p.out.deflection, p.out.ring, p.nx, p.ny);
+    hipLaunchKernelGGL(ring_kernel, dim3(small_grid(p.n_rays, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), p.ws_params);
     return check_launch();
 }
 
@@ -713,7 +816,7 @@ int launch_stats(const Params& p, void* stream) {
 
 int launch_init_rays(const Params& p, double* state, uint8_t* invalid, void* stream) {
     hipLaunchKernelGGL(init_rays_kernel, dim3(small_grid(p.n_rays, 256)), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), p, state, invalid);
+                       static_cast<hipStream_t>(stream), p.img0, static_cast<int64_t>(p.n_rays), state, invalid);
     return check_launch();
 }
 

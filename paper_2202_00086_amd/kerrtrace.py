@@ -1,8 +1,8 @@
 """Python binding of libkerrtrace.so (the C ABI in include/kerrtrace.h).
 
-The functions kt_render, kt_render_ex, kt_workspace_bytes, kt_init_rays,
-kt_last_error and kt_version mirror the C entry points one to one and only
-marshal arguments: every step of the ray tracing runs in the HIP kernels of
+The functions kt_render, kt_render_ex, kt_render_batch, kt_workspace_bytes,
+kt_workspace_bytes_batch, kt_init_rays, kt_last_error and kt_version mirror
+the C entry points one to one and only marshal arguments: every step of the ray tracing runs in the HIP kernels of
 the library.  PyTorch supplies device memory and the HIP stream.
 
 render() is a convenience wrapper that allocates the output tensors and the
@@ -47,6 +47,14 @@ class kt_source(C.Structure):
     _fields_ = [("enabled", C.c_int32), ("r_src", C.c_double)]
 
 
+class kt_image(C.Structure):
+    _fields_ = [("camera", kt_camera), ("spacetime", kt_spacetime), ("disk", kt_disk),
+                ("source", kt_source)]
+
+
+MAX_IMAGES = 4096
+
+
 class kt_integrator(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("h_fixed", C.c_double),
                 ("rtol", C.c_double), ("atol", C.c_double), ("h_init", C.c_double),
@@ -78,8 +86,13 @@ _lib.kt_render.argtypes = [_P(kt_camera), _P(kt_spacetime), _P(kt_disk), _P(kt_s
 _lib.kt_render.restype = C.c_int
 _lib.kt_render_ex.argtypes = _lib.kt_render.argtypes + [_P(kt_launch)]
 _lib.kt_render_ex.restype = C.c_int
+_lib.kt_render_batch.argtypes = [C.c_int32, _P(kt_image), _P(kt_integrator), _P(kt_outputs), C.c_void_p,
+                                 C.c_size_t, C.c_void_p, _P(kt_launch)]
+_lib.kt_render_batch.restype = C.c_int
 _lib.kt_workspace_bytes.argtypes = [_P(kt_camera), _P(kt_integrator)]
 _lib.kt_workspace_bytes.restype = C.c_size_t
+_lib.kt_workspace_bytes_batch.argtypes = [C.c_int32, _P(kt_image), _P(kt_integrator)]
+_lib.kt_workspace_bytes_batch.restype = C.c_size_t
 _lib.kt_init_rays.argtypes = [_P(kt_camera), _P(kt_spacetime), C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.kt_init_rays.restype = C.c_int
 _lib.kt_last_error.argtypes = []
@@ -87,8 +100,8 @@ _lib.kt_last_error.restype = C.c_char_p
 _lib.kt_version.argtypes = []
 _lib.kt_version.restype = C.c_int
 
-EXPORTED = ("kt_render", "kt_render_ex", "kt_workspace_bytes", "kt_init_rays", "kt_last_error",
-            "kt_version")
+EXPORTED = ("kt_render", "kt_render_ex", "kt_render_batch", "kt_workspace_bytes",
+            "kt_workspace_bytes_batch", "kt_init_rays", "kt_last_error", "kt_version")
 
 
 class KtError(RuntimeError):
@@ -123,6 +136,17 @@ def kt_render_ex(camera, spacetime, disk, source, integ, outputs, workspace_ptr,
     return _lib.kt_render_ex(C.byref(camera), C.byref(spacetime), _ref(disk), _ref(source),
                              C.byref(integ), C.byref(outputs), workspace_ptr, workspace_bytes,
                              stream_ptr, _ref(launch))
+
+
+def kt_workspace_bytes_batch(images, integ):
+    """images: a ctypes array of kt_image."""
+    return _lib.kt_workspace_bytes_batch(len(images), images, C.byref(integ))
+
+
+def kt_render_batch(images, integ, outputs, workspace_ptr, workspace_bytes, stream_ptr, launch=None):
+    """images: a ctypes array of kt_image."""
+    return _lib.kt_render_batch(len(images), images, C.byref(integ), C.byref(outputs), workspace_ptr,
+                                workspace_bytes, stream_ptr, _ref(launch))
 
 
 def kt_init_rays(camera, spacetime, state_ptr, invalid_ptr, stream_ptr):
@@ -210,6 +234,68 @@ class Renderer:
         if rc != KT_OK:
             raise KtError(rc, kt_last_error())
         return self.out
+
+
+_IMAGE_KEYS = ("M", "a", "r_obs", "incl", "fov_x", "fov_y", "nx", "ny", "disk_on", "r_in", "r_out",
+               "emis_q", "src_on", "r_src")
+
+
+def split_params(params):
+    """(per-image keyword parameters, integrator keyword parameters)."""
+    img = {k: v for k, v in params.items() if k in _IMAGE_KEYS}
+    integ = {k: v for k, v in params.items() if k not in _IMAGE_KEYS}
+    return img, integ
+
+
+def image_table(images):
+    """ctypes array of kt_image from a list of per-image keyword dicts."""
+    arr = (kt_image * len(images))()
+    for k, im in enumerate(images):
+        cam, st, disk, src, _ = make_structs(**im)
+        arr[k] = kt_image(cam, st, disk, src)
+    return arr
+
+
+class BatchRenderer:
+    """Owns outputs and workspace for a batch of images; render() enqueues
+    all of them as one launch on the current torch stream.  `images` is a
+    list of per-image keyword dicts (camera, spacetime, disk, source keys);
+    `integ` holds the shared integrator keywords.  Outputs are concatenated;
+    views(name) splits one of them per image."""
+
+    def __init__(self, images, device="cuda:0", want=OUTPUT_FIELDS, stats=True, launch=None, **integ):
+        import torch
+        self.device = torch.device(device)
+        self.images = [dict(im) for im in images]
+        self.table = image_table(self.images)
+        *_, self.integ = make_structs(**integ)
+        self.sizes = [im.camera.nx * im.camera.ny for im in self.table]
+        self.first = [sum(self.sizes[:k]) for k in range(len(self.sizes))]
+        self.n = sum(self.sizes)
+        self.want = tuple(want)
+        if "ring" in self.want and not all(im.source.enabled for im in self.table):
+            self.want = tuple(w for w in self.want if w != "ring")
+        self.out = alloc_outputs(self.n, self.device, self.want, stats)
+        self.ws_bytes = kt_workspace_bytes_batch(self.table, self.integ)
+        if self.ws_bytes == 0:
+            raise KtError(KT_EINVAL, "kt_workspace_bytes_batch returned 0")
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.c_out = outputs_struct(self.out)
+        self.launch = launch
+
+    def render(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        rc = kt_render_batch(self.table, self.integ, self.c_out, self.ws.data_ptr(), self.ws_bytes,
+                             C.c_void_p(stream.cuda_stream), self.launch)
+        if rc != KT_OK:
+            raise KtError(rc, kt_last_error())
+        return self.out
+
+    def views(self, name):
+        t = self.out[name]
+        return [t[f:f + n] for f, n in zip(self.first, self.sizes)]
 
 
 def render(device="cuda:0", want=OUTPUT_FIELDS, launch=None, **params):

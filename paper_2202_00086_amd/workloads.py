@@ -12,8 +12,14 @@ the CPU oracle (oracle.Setup) accept these keyword names.
                             point source at r_src = 1000M behind the hole.
   schwarzschild_disk_2048   a = 0, 2048x2048, i = 80 deg, r_obs = 1000M,
                             +-35M, thin Keplerian disk 6M..30M, I_em ~ r^-2.
+  heterogeneous_batch       256 seeded Kerr disk images: sides 64..1024 in
+                            steps of 64, a ~ U[0, 0.998], i ~ U[5, 85] deg,
+                            r_obs log-uniform in [100, 1e4]M, +-35M, disk
+                            from the prograde ISCO to 30M, I_em ~ r^-2.
 """
 import math
+
+import numpy as np
 
 
 def schwarzschild_shadow_64():
@@ -41,6 +47,47 @@ def kerr_disk(a=0.9, incl_deg=60.0, n=256, r_in=None, r_obs=1000.0, fov=35.0, rt
                 emis_q=2.0)
 
 
-def oracle_setup(params):
-    """oracle.Setup keyword arguments from a workload dict."""
-    return {k: v for k, v in params.items()}
+def isco(a, M=1.0):
+    """Radius of the innermost stable circular orbit of Kerr for orbits
+    moving in +phi (prograde for a > 0, retrograde for a < 0), from the
+    closed form of Bardeen, Press & Teukolsky (1972).  A workload input: the
+    disk's inner edge."""
+    chi = abs(a) / M
+    z1 = 1.0 + (1.0 - chi * chi) ** (1.0 / 3.0) * ((1.0 + chi) ** (1.0 / 3.0) + (1.0 - chi) ** (1.0 / 3.0))
+    z2 = math.sqrt(3.0 * chi * chi + z1 * z1)
+    root = math.sqrt((3.0 - z1) * (3.0 + z1 + 2.0 * z2))
+    return M * (3.0 + z2 - root if a >= 0.0 else 3.0 + z2 + root)
+
+
+# keys that describe one image; everything else is the shared integrator
+IMAGE_KEYS = ("M", "a", "r_obs", "incl", "fov_x", "fov_y", "nx", "ny", "disk_on", "r_in", "r_out",
+              "emis_q", "src_on", "r_src")
+
+
+def heterogeneous_batch(n_images=256, seed=20220201, side_unit=64, side_steps=16, fov=35.0, rtol=1e-12):
+    """(images, integ): `images` is a list of per-image dicts (IMAGE_KEYS),
+    `integ` the shared integrator dict.  Sides are side_unit * (1 + k) with k
+    uniform in [0, side_steps); nx and ny are drawn independently.  The
+    escape radius is 1.1 r_obs of each image (r_escape = 0 in `integ`)."""
+    rng = np.random.default_rng(seed)
+    images = []
+    for _ in range(n_images):
+        nx = int(side_unit * (1 + rng.integers(0, side_steps)))
+        ny = int(side_unit * (1 + rng.integers(0, side_steps)))
+        a = float(rng.uniform(0.0, 0.998))
+        incl = math.radians(float(rng.uniform(5.0, 85.0)))
+        r_obs = float(10.0 ** rng.uniform(2.0, 4.0))
+        images.append(dict(M=1.0, a=a, r_obs=r_obs, incl=incl, fov_x=fov, fov_y=fov, nx=nx, ny=ny,
+                           disk_on=1, r_in=isco(a), r_out=30.0, emis_q=2.0))
+    integ = dict(method=1, rtol=rtol, atol=rtol, h_init=1.0, cap_buffer=0.01, r_escape=0.0,
+                 max_steps=1_000_000)
+    return images, integ
+
+
+def image_params(image, integ):
+    """Single-image parameters of one batch entry (escape at 1.1 r_obs when
+    the shared r_escape is 0)."""
+    p = dict(integ, **image)
+    if p.get("r_escape", 0.0) == 0.0:
+        p["r_escape"] = 1.1 * image["r_obs"]
+    return p

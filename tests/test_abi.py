@@ -31,8 +31,8 @@ def _declared_functions():
 
 def test_header_declares_expected_entry_points():
     assert _declared_functions() == sorted(
-        ["kt_render", "kt_render_ex", "kt_workspace_bytes", "kt_init_rays", "kt_last_error",
-         "kt_version"])
+        ["kt_render", "kt_render_ex", "kt_render_batch", "kt_workspace_bytes",
+         "kt_workspace_bytes_batch", "kt_init_rays", "kt_last_error", "kt_version"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared_functions():
         assert hasattr(lib, name), name
     assert set(K.EXPORTED) == set(_declared_functions())
-    assert K.kt_version() == 100
+    assert K.kt_version() == 110
 
 
 def test_struct_layouts_match_header():
@@ -55,6 +55,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(K.kt_launch) == 16
     assert C.sizeof(K.kt_stats) == 12 * 8
     assert C.sizeof(K.kt_outputs) == 16 * 8
+    assert C.sizeof(K.kt_image) == 40 + 16 + 32 + 16
 
 
 def _args(**kw):
@@ -143,3 +144,77 @@ def test_launch_shape_validated():
 def test_workspace_bytes_zero_on_bad_camera():
     K, cam, st, disk, src, integ = _args(nx=0)
     assert K.kt_workspace_bytes(cam, integ) == 0
+
+
+def _batch(images, **integ_kw):
+    from paper_2202_00086_amd import kerrtrace as K
+    table = K.image_table(images)
+    *_, integ = K.make_structs(**integ_kw)
+    return K, table, integ
+
+
+GOOD_IMAGE = dict(a=0.5, nx=8, ny=6, incl=1.0)
+
+
+@no_gpu_only
+@pytest.mark.parametrize("k, kw", [(0, dict(a=1.2)), (1, dict(nx=0)), (2, dict(disk_on=1, r_in=1.0)),
+                                   (1, dict(src_on=1, r_src=1.0)), (2, dict(incl=0.0))])
+def test_batch_validation_names_the_image(k, kw):
+    images = [dict(GOOD_IMAGE) for _ in range(3)]
+    images[k].update(kw)
+    K, table, integ = _batch(images)
+    out = K.kt_outputs()
+    out.fate = 0x1000
+    rc = K.kt_render_batch(table, integ, out, C.c_void_p(0x100000), 1 << 30, None)
+    assert rc == K.KT_EINVAL
+    assert K.kt_last_error().startswith(f"image {k}:"), K.kt_last_error()
+
+
+@no_gpu_only
+def test_batch_rejects_bad_counts_and_shared_arguments():
+    from paper_2202_00086_amd import kerrtrace as K
+    K_, table, integ = _batch([GOOD_IMAGE])
+    out = K.kt_outputs()
+    out.fate = 0x1000
+    ws = C.c_void_p(0x100000)
+    lib = K._lib
+    assert lib.kt_render_batch(0, table, C.byref(integ), C.byref(out), ws, 1 << 30, None, None) == K.KT_EINVAL
+    assert lib.kt_render_batch(K.MAX_IMAGES + 1, table, C.byref(integ), C.byref(out), ws, 1 << 30, None,
+                               None) == K.KT_EINVAL
+    assert lib.kt_render_batch(1, None, C.byref(integ), C.byref(out), ws, 1 << 30, None, None) == K.KT_EINVAL
+    _, table, bad_integ = _batch([GOOD_IMAGE], rtol=0.0)
+    assert K.kt_render_batch(table, bad_integ, out, ws, 1 << 30, None) == K.KT_EINVAL
+    # ring with an image whose source is off
+    _, table, integ = _batch([dict(GOOD_IMAGE, src_on=1), GOOD_IMAGE])
+    out.ring = 0x2000
+    out.deflection = 0x3000
+    assert K.kt_render_batch(table, integ, out, ws, 1 << 30, None) == K.KT_EINVAL
+    assert "image 1" in K.kt_last_error()
+
+
+@no_gpu_only
+def test_batch_total_rays_limit():
+    K, table, integ = _batch([dict(GOOD_IMAGE, nx=40000, ny=40000), dict(GOOD_IMAGE, nx=40000, ny=20000)])
+    out = K.kt_outputs()
+    out.fate = 0x1000
+    assert K.kt_render_batch(table, integ, out, C.c_void_p(0x100000), 1 << 40, None) == K.KT_EINVAL
+    assert "2^31" in K.kt_last_error()
+
+
+@no_gpu_only
+def test_batch_workspace_size():
+    """The batch workspace holds the image table on top of the per-ray
+    buffers, and a smaller one is refused."""
+    images = [dict(GOOD_IMAGE, nx=10 + k, ny=7) for k in range(5)]
+    K, table, integ = _batch(images)
+    need = K.kt_workspace_bytes_batch(table, integ)
+    n = sum((10 + k) * 7 for k in range(5))
+    cam, _, _, _, integ1 = K.make_structs(nx=n, ny=1)
+    assert need > K.kt_workspace_bytes(cam, integ1)
+    out = K.kt_outputs()
+    out.fate = 0x1000
+    assert K.kt_render_batch(table, integ, out, C.c_void_p(0x100000), need - 1, None) == K.KT_ENOMEM
+    # mixed precision needs the fallback list and flags too
+    _, table, integ_m = _batch(images, precision=K.MIXED)
+    assert K.kt_workspace_bytes_batch(table, integ_m) >= need + 5 * n
+    assert K.kt_workspace_bytes_batch((K.kt_image * 0)(), integ) == 0

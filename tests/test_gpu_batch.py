@@ -1,0 +1,191 @@
+"""Batched heterogeneous renders (kt_render_batch) on the GPU.
+
+Per-ray arithmetic is the same in a batch as in a single render, so every
+image of an FP64 batch must equal its own kt_render bit for bit: this checks
+the image lookup, the per-image constants, the concatenated outputs and the
+per-image ring post-pass.  The full 256-image workload is then checked on a
+sample of pixels against the oracle traced one by one.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2202_00086_amd import workloads as W
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+_BITWISE = ("fate", "r_hit", "g", "intensity", "max_abs_h", "max_rel_h", "psi", "deflection", "theta_f",
+            "phi_f", "n_cross", "ring", "n_steps", "n_evals", "used_fp64")
+
+
+def _announce(*what):
+    print("[gpu-case]", *what, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2202_00086_amd import kerrtrace
+    return kerrtrace
+
+
+def _host(K, out):
+    res = {k: v.cpu().numpy() for k, v in out.items() if k != "stats"}
+    res["stats"] = K.read_stats(out)
+    return res
+
+
+def batch_render(K, images, integ, launch=None, want=None):
+    import torch
+    kw = {} if want is None else {"want": want}
+    br = K.BatchRenderer(images, device="cuda:0", launch=launch, **kw, **integ)
+    br.render()
+    torch.cuda.synchronize()
+    return br, _host(K, br.out)
+
+
+def single_render(K, params):
+    import torch
+    r = K.Renderer(device="cuda:0", **params)
+    r.render()
+    torch.cuda.synchronize()
+    return _host(K, r.out)
+
+
+def _compare_with_singles(K, br, g, images, integ):
+    evals = 0
+    fates = np.zeros(8, np.int64)
+    for k, im in enumerate(images):
+        s = single_render(K, W.image_params(im, integ))
+        f, n = br.first[k], br.sizes[k]
+        for key in _BITWISE:
+            if key in g and key in s:
+                np.testing.assert_array_equal(g[key][f:f + n].view(np.uint8), s[key].view(np.uint8),
+                                              err_msg=f"image {k} {key}")
+        evals += s["stats"].evals
+        fates += np.array(s["stats"].fate_count[:8])
+    st = g["stats"]
+    assert st.rays == br.n
+    assert st.evals == evals
+    assert list(st.fate_count[:8]) == fates.tolist()
+
+
+def test_batch_equals_single_renders(K):
+    """Twelve seeded Kerr disk images, sides 8..64, spins, inclinations and
+    distances all different, in one launch."""
+    images, integ = W.heterogeneous_batch(n_images=12, seed=7, side_unit=8, side_steps=8)
+    _announce("batch vs single, 12 disk images", [(i["nx"], i["ny"]) for i in images])
+    br, g = batch_render(K, images, integ)
+    assert (g["fate"] <= K.DISK).all() and (g["fate"] == K.DISK).any()
+    _compare_with_singles(K, br, g, images, integ)
+
+
+def test_batch_with_source_and_ring_equals_single_renders(K):
+    """Source on in every image: deflection, psi and the ring flags (whose
+    neighbours must stay inside each image) match the single renders; the
+    1x1 and one-row images sit between larger ones."""
+    base = W.kerr_ring(0.9, n=8)
+    integ = {k: v for k, v in base.items() if k not in W.IMAGE_KEYS}
+    mk = lambda a, nx, ny, incl: {**{k: v for k, v in base.items() if k in W.IMAGE_KEYS},
+                                  "a": a, "nx": nx, "ny": ny, "incl": incl}
+    images = [mk(0.5, 40, 33, 1.0), mk(0.0, 1, 1, 1.2), mk(0.998, 57, 1, 0.6), mk(0.9, 48, 48, 1.0472),
+              mk(0.3, 17, 29, 1.5)]
+    _announce("batch vs single, 5 ring images")
+    br, g = batch_render(K, images, integ)
+    assert g["ring"].any()
+    _compare_with_singles(K, br, g, images, integ)
+
+
+def test_batch_launch_shapes_are_bit_identical(K):
+    images, integ = W.heterogeneous_batch(n_images=6, seed=11, side_unit=16, side_steps=4)
+    _announce("batch launch shapes")
+    _, ref = batch_render(K, images, integ)
+    for ln in [K.kt_launch(1, 128, 0, 1), K.kt_launch(1, 64, 1, 8), K.kt_launch(0, 256, 0, 32),
+               K.kt_launch(1, 256, 3, 4096)]:
+        _announce("  launch", ln.persistent, ln.block, ln.blocks_per_cu, ln.batch)
+        _, g = batch_render(K, images, integ, launch=ln)
+        for key in _BITWISE:
+            if key in g:
+                np.testing.assert_array_equal(g[key].view(np.uint8), ref[key].view(np.uint8), err_msg=key)
+
+
+def test_batch_mixed_precision(K):
+    """Mixed batch at |H|_rel budget 1e-10: every ray meets the budget, rays
+    re-run in FP64 equal the FP64 batch bit for bit, and the others keep the
+    FP64 fate rule and agree on the disk observables to 1e-6."""
+    images, integ = W.heterogeneous_batch(n_images=10, seed=5, side_unit=12, side_steps=6)
+    _announce("batch mixed 1e-10")
+    br, ref = batch_render(K, images, integ)
+    _, g = batch_render(K, images, dict(integ, precision=K.MIXED, h_budget=1e-10, r_switch=300.0))
+    assert np.nanmax(g["max_rel_h"]) <= 1e-10
+    fb = g["used_fp64"] == 1
+    assert g["stats"].fallback_rays == int(fb.sum())
+    for key in ("fate", "r_hit", "g", "intensity", "max_rel_h", "n_steps"):
+        np.testing.assert_array_equal(g[key][fb].view(np.uint8), ref[key][fb].view(np.uint8), err_msg=key)
+    for k in range(len(images)):
+        f, n = br.first[k], br.sizes[k]
+        nx, ny = images[k]["nx"], images[k]["ny"]
+        P.check_fates(g["fate"][f:f + n], ref["fate"][f:f + n], nx, ny, frac=2e-3, min_allowed=2)
+    same = (g["fate"] == ref["fate"]) & (g["fate"] == K.DISK) & (g["n_cross"] == ref["n_cross"])
+    for key in ("r_hit", "g"):
+        e = P.rel_err(g[key][same], ref[key][same])
+        assert e.max() < 1e-6, (key, e.max())
+
+
+def _neighbourhoods(rng, im, per_image):
+    """Sample pixel ids of one image and their clamped 3x3 neighbourhoods."""
+    nx, ny = im["nx"], im["ny"]
+    pix = np.sort(rng.choice(nx * ny, size=min(per_image, nx * ny), replace=False))
+    j, i = np.divmod(pix, nx)
+    nb = []
+    for dj in (-1, 0, 1):
+        for di in (-1, 0, 1):
+            nb.append(np.clip(j + dj, 0, ny - 1) * nx + np.clip(i + di, 0, nx - 1))
+    return pix.astype(np.int32), np.stack(nb, 1)
+
+
+def test_full_heterogeneous_batch_sampled(K):
+    """The 256-image workload in the default launch configuration: per image a
+    fixed sample of pixels against the oracle, stats over all 69M rays."""
+    import torch
+    images, integ = W.heterogeneous_batch()
+    want = ("fate", "r_hit", "g", "intensity", "max_rel_h", "n_cross", "n_evals")
+    _announce("heterogeneous batch 256 images sampled")
+    br = K.BatchRenderer(images, device="cuda:0", want=want, **integ)
+    br.render()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2202)
+    checked = disk = 0
+    for k, im in enumerate(images):
+        pix, nb = _neighbourhoods(rng, im, 6)
+        f = br.first[k]
+        idx = torch.from_numpy(np.concatenate([pix, nb.ravel()]).astype(np.int64) + f).to("cuda:0")
+        gv = {key: br.out[key].index_select(0, idx).cpu().numpy() for key in want}
+        ns = pix.size
+        o = O.trace_pixels(O.Setup(**W.image_params(im, integ)), pix)
+        nbf = gv["fate"][ns:].reshape(ns, 9)
+        near = (nbf != nbf[:, 4:5]).any(1)
+        same = gv["fate"][:ns] == o["fate"]
+        assert (same | near).all(), (k, pix[~(same | near)])
+        ok = same & ~near & (o["fate"] == K.DISK) & (gv["n_cross"][:ns] == o["n_cross"]) & (o["n_cross"] <= 1)
+        for key in ("r_hit", "g", "intensity"):
+            if ok.any():
+                e = P.rel_err(gv[key][:ns][ok], o[key][ok])
+                assert e.max() < 1e-8, (k, key, e.max())
+        checked += ns
+        disk += int(ok.sum())
+    print(f"[batch sampled] {checked} pixels, {disk} disk values compared", flush=True)
+    assert disk > 100
+    st = K.read_stats(br.out)
+    assert st.rays == br.n == sum(i["nx"] * i["ny"] for i in images)
+    assert sum(st.fate_count) == br.n
+    assert st.evals == int(br.out["n_evals"].to(torch.int64).sum().item())
+    h = br.out["max_rel_h"]
+    h_max = float(h[~torch.isnan(h)].max().item())
+    print(f"[batch sampled] max |H|_rel over the batch {h_max:.3e}", flush=True)
+    assert h_max < 1e-8
