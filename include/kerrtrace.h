@@ -198,6 +198,26 @@ int kt_render_batch(int32_t n_images, const kt_image *images, const kt_integrato
 size_t kt_workspace_bytes_batch(int32_t n_images, const kt_image *images,
                                 const kt_integrator *integ);
 
+#define KT_AUTOTUNE_DEFAULT_COUNT 20
+
+/* Launch-shape autotuner.  Renders the batch (the probe workload: pass a
+   representative subset of a large batch to keep this short) once untimed
+   and then `repeats` times with every candidate shape, timing each with HIP
+   events on hip_stream, and writes the fastest candidate to *best.  Waves
+   per SIMD are chosen through blocks_per_cu (blocks_per_cu * block / 256
+   waves per SIMD).  candidates == NULL with n_candidates == 0 selects the
+   built-in set of KT_AUTOTUNE_DEFAULT_COUNT shapes: persistent, block
+   {128, 256} x 1 or 2 waves per SIMD x ticket batch {4, 8, 16, 32, 64}.
+   times_ms (may be NULL) receives the mean milliseconds per render of each
+   candidate, in order.  Synchronises hip_stream; the outputs hold the last
+   render's results.  repeats lies in [1, 100].  Other arguments as for
+   kt_render_batch (n_images = 1 tunes a single image).
+   Returns KT_OK, KT_EINVAL, KT_ENOMEM or KT_EDEVICE. */
+int kt_autotune_batch(int32_t n_images, const kt_image *images, const kt_integrator *integ,
+                      const kt_outputs *out, void *workspace, size_t workspace_bytes,
+                      void *hip_stream, const kt_launch *candidates, int32_t n_candidates,
+                      int32_t repeats, kt_launch *best, float *times_ms);
+
 /* Initial state of every pixel (Sect. 2.3), for checking the camera alone:
    state is a device array of 7*nx*ny doubles laid out SoA as
    [r | theta | phi | p_r | p_theta | E | L], each block nx*ny long;

@@ -374,4 +374,67 @@ int kt_render_batch(int32_t n_images, const kt_image* images, const kt_integrato
     return render_images(table, n, integ, out, workspace, workspace_bytes, hip_stream, launch);
 }
 
+int kt_autotune_batch(int32_t n_images, const kt_image* images, const kt_integrator* integ,
+                      const kt_outputs* out, void* workspace, size_t workspace_bytes, void* hip_stream,
+                      const kt_launch* candidates, int32_t n_candidates, int32_t repeats, kt_launch* best,
+                      float* times_ms) {
+    g_err[0] = 0;
+    if (!integ || !out || !best) return fail(KT_EINVAL, "integ, out and best must not be NULL");
+    if (repeats < 1 || repeats > 100) return fail(KT_EINVAL, "repeats must lie in [1, 100]");
+    if ((candidates == nullptr) != (n_candidates == 0) || n_candidates < 0 || n_candidates > 4096)
+        return fail(KT_EINVAL, "give candidates with 1..4096 entries, or NULL with n_candidates = 0");
+    int rc;
+    if ((rc = validate_integ(integ)) || (rc = validate_outputs(out))) return rc;
+    std::vector<kt::Image> table;
+    int64_t n = 0;
+    if ((rc = make_table(n_images, images, integ, out->ring != nullptr, table, &n))) return rc;
+
+    std::vector<kt_launch> cand;
+    if (candidates) {
+        cand.assign(candidates, candidates + n_candidates);
+    } else {
+        for (int block : {128, 256})
+            for (int waves : {1, 2})
+                for (int batch : {4, 8, 16, 32, 64}) cand.push_back(kt_launch{1, block, waves * 256 / block, batch});
+    }
+    // the untimed first render also validates every shape before any timing
+    for (const kt_launch& ln : cand)
+        if ((ln.block != 64 && ln.block != 128 && ln.block != 256) || ln.batch < 1 || ln.batch > 4096 ||
+            ln.blocks_per_cu < 0 || ln.blocks_per_cu > 64)
+            return fail(KT_EINVAL, "candidate launch shape out of range (block %d, blocks_per_cu %d, batch %d)",
+                        ln.block, ln.blocks_per_cu, ln.batch);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(KT_EDEVICE, "hipEventCreate failed");
+    }
+    int best_i = -1;
+    float best_ms = 0.0f;
+    rc = render_images(table, n, integ, out, workspace, workspace_bytes, hip_stream, &cand[0]);
+    for (size_t i = 0; rc == KT_OK && i < cand.size(); ++i) {
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(KT_EDEVICE, "hipEventRecord failed"); break; }
+        for (int r = 0; r < repeats && rc == KT_OK; ++r)
+            rc = render_images(table, n, integ, out, workspace, workspace_bytes, hip_stream, &cand[i]);
+        if (rc) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(KT_EDEVICE, "event timing failed: %s", hipGetErrorString(hipGetLastError()));
+            break;
+        }
+        ms /= static_cast<float>(repeats);
+        if (times_ms) times_ms[i] = ms;
+        if (best_i < 0 || ms < best_ms) {
+            best_i = static_cast<int>(i);
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *best = cand[static_cast<size_t>(best_i)];
+    return KT_OK;
+}
+
 }  // extern "C"

@@ -1,6 +1,7 @@
 """Python binding of libkerrtrace.so (the C ABI in include/kerrtrace.h).
 
-The functions kt_render, kt_render_ex, kt_render_batch, kt_workspace_bytes,
+The functions kt_render, kt_render_ex, kt_render_batch, kt_autotune_batch,
+kt_workspace_bytes,
 kt_workspace_bytes_batch, kt_init_rays, kt_last_error and kt_version mirror
 the C entry points one to one and only marshal arguments: every step of the ray tracing runs in the HIP kernels of
 the library.  PyTorch supplies device memory and the HIP stream.
@@ -89,6 +90,10 @@ _lib.kt_render_ex.restype = C.c_int
 _lib.kt_render_batch.argtypes = [C.c_int32, _P(kt_image), _P(kt_integrator), _P(kt_outputs), C.c_void_p,
                                  C.c_size_t, C.c_void_p, _P(kt_launch)]
 _lib.kt_render_batch.restype = C.c_int
+_lib.kt_autotune_batch.argtypes = [C.c_int32, _P(kt_image), _P(kt_integrator), _P(kt_outputs), C.c_void_p,
+                                   C.c_size_t, C.c_void_p, _P(kt_launch), C.c_int32, C.c_int32,
+                                   _P(kt_launch), _P(C.c_float)]
+_lib.kt_autotune_batch.restype = C.c_int
 _lib.kt_workspace_bytes.argtypes = [_P(kt_camera), _P(kt_integrator)]
 _lib.kt_workspace_bytes.restype = C.c_size_t
 _lib.kt_workspace_bytes_batch.argtypes = [C.c_int32, _P(kt_image), _P(kt_integrator)]
@@ -100,8 +105,9 @@ _lib.kt_last_error.restype = C.c_char_p
 _lib.kt_version.argtypes = []
 _lib.kt_version.restype = C.c_int
 
-EXPORTED = ("kt_render", "kt_render_ex", "kt_render_batch", "kt_workspace_bytes",
+EXPORTED = ("kt_render", "kt_render_ex", "kt_render_batch", "kt_autotune_batch", "kt_workspace_bytes",
             "kt_workspace_bytes_batch", "kt_init_rays", "kt_last_error", "kt_version")
+AUTOTUNE_DEFAULT_COUNT = 20
 
 
 class KtError(RuntimeError):
@@ -147,6 +153,18 @@ def kt_render_batch(images, integ, outputs, workspace_ptr, workspace_bytes, stre
     """images: a ctypes array of kt_image."""
     return _lib.kt_render_batch(len(images), images, C.byref(integ), C.byref(outputs), workspace_ptr,
                                 workspace_bytes, stream_ptr, _ref(launch))
+
+
+def kt_autotune_batch(images, integ, outputs, workspace_ptr, workspace_bytes, stream_ptr, candidates=None,
+                      repeats=2):
+    """Returns (rc, best kt_launch, list of mean ms per candidate)."""
+    n_c = 0 if candidates is None else len(candidates)
+    arr = None if candidates is None else (kt_launch * n_c)(*candidates)
+    times = (C.c_float * (n_c or AUTOTUNE_DEFAULT_COUNT))()
+    best = kt_launch()
+    rc = _lib.kt_autotune_batch(len(images), images, C.byref(integ), C.byref(outputs), workspace_ptr,
+                                workspace_bytes, stream_ptr, arr, n_c, repeats, C.byref(best), times)
+    return rc, best, list(times)
 
 
 def kt_init_rays(camera, spacetime, state_ptr, invalid_ptr, stream_ptr):
@@ -292,6 +310,20 @@ class BatchRenderer:
         if rc != KT_OK:
             raise KtError(rc, kt_last_error())
         return self.out
+
+    def autotune(self, candidates=None, repeats=2, stream=None):
+        """Pick the fastest launch shape on this batch (kt_autotune_batch),
+        keep it for later renders and return (best, times_ms)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        rc, best, times = kt_autotune_batch(self.table, self.integ, self.c_out, self.ws.data_ptr(),
+                                            self.ws_bytes, C.c_void_p(stream.cuda_stream), candidates,
+                                            repeats)
+        if rc != KT_OK:
+            raise KtError(rc, kt_last_error())
+        self.launch = best
+        return best, times
 
     def views(self, name):
         t = self.out[name]

@@ -31,7 +31,7 @@ def _declared_functions():
 
 def test_header_declares_expected_entry_points():
     assert _declared_functions() == sorted(
-        ["kt_render", "kt_render_ex", "kt_render_batch", "kt_workspace_bytes",
+        ["kt_render", "kt_render_ex", "kt_render_batch", "kt_autotune_batch", "kt_workspace_bytes",
          "kt_workspace_bytes_batch", "kt_init_rays", "kt_last_error", "kt_version"])
 
 
@@ -218,3 +218,27 @@ def test_batch_workspace_size():
     _, table, integ_m = _batch(images, precision=K.MIXED)
     assert K.kt_workspace_bytes_batch(table, integ_m) >= need + 5 * n
     assert K.kt_workspace_bytes_batch((K.kt_image * 0)(), integ) == 0
+
+
+@no_gpu_only
+def test_autotune_validation():
+    from paper_2202_00086_amd import kerrtrace as K
+    _, table, integ = _batch([GOOD_IMAGE])
+    out = K.kt_outputs()
+    out.fate = 0x1000
+    ws = C.c_void_p(0x100000)
+    lib = K._lib
+    best = K.kt_launch()
+    one = (K.kt_launch * 1)(K.kt_launch(1, 256, 0, 32))
+    bad = (K.kt_launch * 1)(K.kt_launch(1, 96, 0, 32))
+
+    def call(cands, n, repeats, best_ref):
+        return lib.kt_autotune_batch(1, table, C.byref(integ), C.byref(out), ws, 1 << 30, None, cands, n,
+                                     repeats, best_ref, None)
+    assert call(None, 0, 0, C.byref(best)) == K.KT_EINVAL          # repeats
+    assert call(None, 0, 101, C.byref(best)) == K.KT_EINVAL
+    assert call(None, 3, 2, C.byref(best)) == K.KT_EINVAL          # NULL list with a count
+    assert call(one, 0, 2, C.byref(best)) == K.KT_EINVAL           # list without a count
+    assert call(one, 1, 2, None) == K.KT_EINVAL                    # no place for the result
+    assert call(bad, 1, 2, C.byref(best)) == K.KT_EINVAL           # shape out of range
+    assert "candidate" in K.kt_last_error()

@@ -189,3 +189,25 @@ def test_full_heterogeneous_batch_sampled(K):
     h_max = float(h[~torch.isnan(h)].max().item())
     print(f"[batch sampled] max |H|_rel over the batch {h_max:.3e}", flush=True)
     assert h_max < 1e-8
+
+
+def test_autotune_picks_the_fastest_candidate(K):
+    """The built-in candidate set on a small batch: every candidate timed,
+    the fastest returned, and the outputs left by the tuner equal a plain
+    render (FP64 results do not depend on the launch shape)."""
+    images, integ = W.heterogeneous_batch(n_images=6, seed=11, side_unit=16, side_steps=4)
+    _announce("autotune default set")
+    br, ref = batch_render(K, images, integ)
+    best, times = br.autotune(repeats=1)
+    assert len(times) == K.AUTOTUNE_DEFAULT_COUNT and min(times) > 0.0
+    shapes = [(b, w * 256 // b, q) for b in (128, 256) for w in (1, 2) for q in (4, 8, 16, 32, 64)]
+    assert (best.block, best.blocks_per_cu, best.batch) == shapes[int(np.argmin(times))]
+    after = _host(K, br.out)
+    for key in _BITWISE:
+        if key in ref:
+            np.testing.assert_array_equal(after[key].view(np.uint8), ref[key].view(np.uint8), err_msg=key)
+    _announce("autotune explicit candidates")
+    cands = [K.kt_launch(1, 64, 2, 1), K.kt_launch(0, 128, 0, 32)]
+    best, times = br.autotune(candidates=cands, repeats=2)
+    assert len(times) == 2 and min(times) > 0.0
+    assert (best.persistent, best.block) == [(1, 64), (0, 128)][int(np.argmin(times))]
