@@ -20,6 +20,8 @@
  *     second eq:momentums (Sect. 2.3), with p_r taken ingoing;
  *   - the Dormand-Prince 5(4) embedded pair (cited in Sect. 3.1; FSAL, six
  *     evaluations per step) and classic RK4;
+ *   - the schemes Sect. 3.1 compares it with: Runge-Kutta-Fehlberg 4(5),
+ *     Cash-Karp 5(4) and Bulirsch-Stoer extrapolation;
  *   - the constraint monitor Error = |H_num| (Sect. 3.1);
  *   - termination at r < r_H + delta_r (captured) and r > r_cs (escaped),
  *     Sect. 4.1, and on a thin equatorial disk (Sect. 5);
@@ -201,6 +203,7 @@ void ko_pixel_xy(const ko_setup *s, int32_t i, int32_t j, double *x, double *y)
 /* ------------------------------------------------------------------------ */
 
 #define NMAX 5
+#define BS_K 5 /* Bulirsch-Stoer columns: order 2 BS_K */
 
 typedef void (*field_fn)(const double *y, double *dy, const void *ctx);
 
@@ -247,6 +250,112 @@ static void dp45_step(field_fn f, const void *ctx, int n, const double *y, const
     }
 }
 
+/* Six-stage embedded pairs without FSAL: stage rows A, the weights of the
+   propagated solution and of the embedded one.  The error estimate is the
+   difference of the two solutions. */
+typedef struct {
+    double A[6][5];
+    double b_prop[6], b_emb[6];
+} erk6_tableau;
+
+/* Fehlberg (1969), RK4(5): the 4th-order solution is propagated and the
+   5th-order one estimates its error. */
+static const erk6_tableau RKF45 = {
+    {{0, 0, 0, 0, 0},
+     {1.0 / 4, 0, 0, 0, 0},
+     {3.0 / 32, 9.0 / 32, 0, 0, 0},
+     {1932.0 / 2197, -7200.0 / 2197, 7296.0 / 2197, 0, 0},
+     {439.0 / 216, -8.0, 3680.0 / 513, -845.0 / 4104, 0},
+     {-8.0 / 27, 2.0, -3544.0 / 2565, 1859.0 / 4104, -11.0 / 40}},
+    {25.0 / 216, 0, 1408.0 / 2565, 2197.0 / 4104, -1.0 / 5, 0},
+    {16.0 / 135, 0, 6656.0 / 12825, 28561.0 / 56430, -9.0 / 50, 2.0 / 55},
+};
+
+/* Cash & Karp (1990), RK5(4): the 5th-order solution is propagated (local
+   extrapolation) and the embedded 4th-order one estimates the error. */
+static const erk6_tableau CK45 = {
+    {{0, 0, 0, 0, 0},
+     {1.0 / 5, 0, 0, 0, 0},
+     {3.0 / 40, 9.0 / 40, 0, 0, 0},
+     {3.0 / 10, -9.0 / 10, 6.0 / 5, 0, 0},
+     {-11.0 / 54, 5.0 / 2, -70.0 / 27, 35.0 / 27, 0},
+     {1631.0 / 55296, 175.0 / 512, 575.0 / 13824, 44275.0 / 110592, 253.0 / 4096}},
+    {37.0 / 378, 0, 250.0 / 621, 125.0 / 594, 0, 512.0 / 1771},
+    {2825.0 / 27648, 0, 18575.0 / 48384, 13525.0 / 55296, 277.0 / 14336, 1.0 / 4},
+};
+
+/* One step of a six-stage pair from y with k1 = f(y) given: the propagated
+   solution yn, kn = f(yn) (the next step's k1) and e = yn - y_embedded.
+   Six new evaluations. */
+static void erk6_step(const erk6_tableau *t, field_fn f, const void *ctx, int n, const double *y,
+                      const double *k1, double h, double *yn, double *kn, double *e)
+{
+    double k[6][NMAX];
+    double ys[NMAX];
+    memcpy(k[0], k1, sizeof(double) * n);
+    for (int st = 1; st < 6; ++st) {
+        for (int i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < st; ++j) acc += t->A[st][j] * k[j][i];
+            ys[i] = y[i] + h * acc;
+        }
+        f(ys, k[st], ctx);
+    }
+    for (int i = 0; i < n; ++i) {
+        double acc = 0.0, diff = 0.0;
+        for (int j = 0; j < 6; ++j) {
+            acc += t->b_prop[j] * k[j][i];
+            diff += (t->b_prop[j] - t->b_emb[j]) * k[j][i];
+        }
+        yn[i] = y[i] + h * acc;
+        e[i] = h * diff;
+    }
+    f(yn, kn, ctx);
+}
+
+/* Bulirsch-Stoer step: Gragg's modified midpoint rule over [0, h] with
+   n_k = 2k substeps (k = 1..BS_K), each chain started from y, then
+   Aitken-Neville polynomial extrapolation of the chain ends to zero substep
+   size in the variable (h/n_k)^2 (the midpoint rule's error expansion is
+   even in the substep for even n_k).  The step returns the last diagonal
+   entry T[K][K] (order 2K) and e = T[K][K] - T[K][K-1].  Evaluations:
+   n_k - 1 per chain (k1 = f(y) starts every chain) plus f at the result
+   for the next step: BS_K^2 + 1. */
+static void bs_step(field_fn f, const void *ctx, int n, const double *y, const double *k1, double h,
+                    double *yn, double *kn, double *e)
+{
+    double T[BS_K][BS_K][NMAX];
+    for (int k = 0; k < BS_K; ++k) {
+        const int ns = 2 * (k + 1);
+        const double hs = h / ns;
+        double zp[NMAX], zc[NMAX], fz[NMAX];
+        for (int i = 0; i < n; ++i) {
+            zp[i] = y[i];
+            zc[i] = y[i] + hs * k1[i];
+        }
+        for (int m = 1; m < ns; ++m) {
+            f(zc, fz, ctx);
+            for (int i = 0; i < n; ++i) {
+                const double znext = zp[i] + 2.0 * hs * fz[i];
+                zp[i] = zc[i];
+                zc[i] = znext;
+            }
+        }
+        for (int i = 0; i < n; ++i) T[k][0][i] = zc[i];
+        for (int j = 1; j <= k; ++j) {
+            const double nk = ns, nkj = 2 * (k - j + 1);
+            const double ratio = (nk * nk) / (nkj * nkj);
+            for (int i = 0; i < n; ++i)
+                T[k][j][i] = T[k][j - 1][i] + (T[k][j - 1][i] - T[k - 1][j - 1][i]) / (ratio - 1.0);
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        yn[i] = T[BS_K - 1][BS_K - 1][i];
+        e[i] = T[BS_K - 1][BS_K - 1][i] - T[BS_K - 1][BS_K - 2][i];
+    }
+    f(yn, kn, ctx);
+}
+
 /* Classic RK4 step of size h from y with k1 = f(y) given.  Writes y_new and
    f(y_new).  Four new evaluations. */
 static void rk4_step(field_fn f, const void *ctx, int n, const double *y, const double *k1,
@@ -263,6 +372,37 @@ static void rk4_step(field_fn f, const void *ctx, int n, const double *y, const 
     f(yn, kn, ctx);
 }
 
+/* One step of any method; returns the number of new evaluations.  RK4
+   gives a zero error vector. */
+static int step_any(int32_t method, field_fn f, const void *ctx, int n, const double *y,
+                    const double *k1, double h, double *yn, double *kn, double *e)
+{
+    switch (method) {
+    case KO_DP45:
+        dp45_step(f, ctx, n, y, k1, h, yn, kn, e);
+        return 6;
+    case KO_RKF45:
+        erk6_step(&RKF45, f, ctx, n, y, k1, h, yn, kn, e);
+        return 6;
+    case KO_CK45:
+        erk6_step(&CK45, f, ctx, n, y, k1, h, yn, kn, e);
+        return 6;
+    case KO_BS:
+        bs_step(f, ctx, n, y, k1, h, yn, kn, e);
+        return BS_K * BS_K + 1;
+    default:
+        rk4_step(f, ctx, n, y, k1, h, yn, kn);
+        for (int i = 0; i < n; ++i) e[i] = 0.0;
+        return 4;
+    }
+}
+
+/* Exponent of the step-size controller: 1 / (order of the error estimate + 1). */
+static double controller_exponent(int32_t method)
+{
+    return method == KO_BS ? 1.0 / (2 * BS_K - 1) : 1.0 / 5;
+}
+
 static void harmonic_field(const double *y, double *dy, const void *ctx)
 {
     (void)ctx;
@@ -270,23 +410,52 @@ static void harmonic_field(const double *y, double *dy, const void *ctx)
     dy[1] = -y[0];
 }
 
+static void riccati_field(const double *y, double *dy, const void *ctx)
+{
+    (void)ctx;
+    dy[0] = y[0] * y[0];
+}
+
 void ko_harmonic_fixed(int32_t method, double T, int64_t n, double out[2])
 {
-    double y[2] = {0.0, 1.0}, k[2], yn[2], kn[2], e[2];
-    double h = T / (double)n;
-    harmonic_field(y, k, NULL);
+    double y0[2] = {0.0, 1.0};
+    ko_fixed_steps(method, 0, T, n, y0, out);
+}
+
+void ko_fixed_steps(int32_t method, int32_t problem, double T, int64_t n, const double *y0,
+                    double *out)
+{
+    field_fn f = problem == 0 ? harmonic_field : riccati_field;
+    const int dim = problem == 0 ? 2 : 1;
+    double y[2], k[2], yn[2], kn[2], e[2];
+    memcpy(y, y0, sizeof(double) * dim);
+    const double h = T / (double)n;
+    f(y, k, NULL);
     for (int64_t s = 0; s < n; ++s) {
-        if (method == KO_DP45)
-            dp45_step(harmonic_field, NULL, 2, y, k, h, yn, kn, e);
-        else
-            rk4_step(harmonic_field, NULL, 2, y, k, h, yn, kn);
-        y[0] = yn[0];
-        y[1] = yn[1];
-        k[0] = kn[0];
-        k[1] = kn[1];
+        step_any(method, f, NULL, dim, y, k, h, yn, kn, e);
+        memcpy(y, yn, sizeof(double) * dim);
+        memcpy(k, kn, sizeof(double) * dim);
     }
-    out[0] = y[0];
-    out[1] = y[1];
+    memcpy(out, y, sizeof(double) * dim);
+}
+
+int ko_one_step(int32_t method, int32_t problem, double h, const double *y0, double *yn, double *e)
+{
+    field_fn f = problem == 0 ? harmonic_field : riccati_field;
+    const int dim = problem == 0 ? 2 : 1;
+    double k[2], kn[2];
+    f(y0, k, NULL);
+    return step_any(method, f, NULL, dim, y0, k, h, yn, kn, e);
+}
+
+void ko_tableau(int32_t method, double A[36], double b_prop[6], double b_emb[6])
+{
+    const erk6_tableau *t = method == KO_RKF45 ? &RKF45 : &CK45;
+    for (int i = 0; i < 6; ++i) {
+        for (int j = 0; j < 6; ++j) A[6 * i + j] = j < 5 ? t->A[i][j] : 0.0;
+        b_prop[i] = t->b_prop[i];
+        b_emb[i] = t->b_emb[i];
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -321,13 +490,7 @@ typedef struct {
 static int take_step(tracer *t, const double *z, const double *k1, double h, double *zn,
                      double *kn, double *e)
 {
-    if (t->s->method == KO_DP45) {
-        dp45_step(ray_field, &t->ctx, 5, z, k1, h, zn, kn, e);
-        return 6;
-    }
-    rk4_step(ray_field, &t->ctx, 5, z, k1, h, zn, kn);
-    for (int i = 0; i < 5; ++i) e[i] = 0.0;
-    return 4;
+    return step_any(t->s->method, ray_field, &t->ctx, 5, z, k1, h, zn, kn, e);
 }
 
 /* Locate the root of z(h')[comp] - target for h' in (0, h] with the Illinois
@@ -417,7 +580,8 @@ static int64_t trace_ray(const ko_setup *s, double x, double y, const ko_out *o,
     {
         const double E = init[5], L = init[6];
         const double r_cap = ko_horizon(s->M, s->a) + s->cap_buffer;
-        const int dp = (s->method == KO_DP45);
+        const int dp = (s->method != KO_RK4_S); /* adaptive */
+        const double expo = controller_exponent(s->method);
         double k1[5], zn[5], kn[5], e[5];
         double lam = 0.0;
         double h = dp ? s->h_init : s->h_fixed;
@@ -459,7 +623,7 @@ static int64_t trace_ray(const ko_setup *s, double x, double y, const ko_out *o,
                     break;
                 }
                 if (err > 1.0) {
-                    h *= fmax(0.2, 0.9 * pow(err, -0.2));
+                    h *= fmax(0.2, 0.9 * pow(err, -expo));
                     rejected = 1;
                     if (h < 1e-12 * fmax(1.0, fabs(lam))) {
                         fate = KO_STEPFAIL;
@@ -467,7 +631,7 @@ static int64_t trace_ray(const ko_setup *s, double x, double y, const ko_out *o,
                     }
                     continue;
                 }
-                double fac = err < 1e-10 ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * pow(err, -0.2)));
+                double fac = err < 1e-10 ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * pow(err, -expo)));
                 if (rejected) fac = fmin(fac, 1.0);
                 rejected = 0;
                 h_next = h * fac;

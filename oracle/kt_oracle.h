@@ -35,6 +35,9 @@ extern "C" {
 /* integrators */
 #define KO_RK4_S 0 /* classic RK4, fixed step in s with d(lambda)/ds = Delta/r */
 #define KO_DP45 1  /* Dormand-Prince 5(4), adaptive, FSAL */
+#define KO_RKF45 2 /* Runge-Kutta-Fehlberg 4(5), adaptive, 4th order propagated */
+#define KO_CK45 3  /* Cash-Karp 5(4), adaptive, 5th order propagated */
+#define KO_BS 4    /* Bulirsch-Stoer: modified midpoint n = 2,4,..,10, extrapolated (order 10) */
 
 typedef struct {
     /* spacetime */
@@ -46,8 +49,8 @@ typedef struct {
     /* integrator */
     int32_t method;
     double h_fixed;      /* RK4_S step in s */
-    double rtol, atol;   /* DP45 tolerances */
-    double h_init;       /* DP45 first trial step in lambda */
+    double rtol, atol;   /* tolerances of the adaptive methods */
+    double h_init;       /* first trial step in lambda of the adaptive methods */
     double cap_buffer;   /* delta_r: captured when r < r_+ + cap_buffer */
     double r_escape;     /* escaped when r > r_escape */
     int64_t max_steps;   /* accepted-step cap */
@@ -127,6 +130,21 @@ double ko_horizon(double M, double a);
    fixed steps of the given method's underlying tableau (DP5 propagates the
    5th-order solution).  Returns the final (y, y') in out[2]. */
 void ko_harmonic_fixed(int32_t method, double T, int64_t n, double out[2]);
+
+/* n fixed steps of size T/n of any method on a test problem: problem 0 is
+   y'' = -y as (y, y'), problem 1 is the scalar y' = y^2.  y0 and out hold 2
+   resp. 1 values. */
+void ko_fixed_steps(int32_t method, int32_t problem, double T, int64_t n, const double *y0,
+                    double *out);
+
+/* One step of size h of any method on a test problem (as above): the
+   propagated solution and the embedded error estimate.  Returns the number
+   of evaluations the step took beyond f(y0). */
+int ko_one_step(int32_t method, int32_t problem, double h, const double *y0, double *yn, double *e);
+
+/* The Butcher tableau of KO_RKF45 or KO_CK45: A row-major 6x6, the weights
+   of the propagated and of the embedded solution. */
+void ko_tableau(int32_t method, double A[36], double b_prop[6], double b_emb[6]);
 
 #ifdef __cplusplus
 }

@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("KT_ORACLE_LIB") or os.path.join(HERE, "libkt_oracle.so")
 
 ESCAPED, CAPTURED, DISK, MAXSTEPS, STEPFAIL, INVALID = range(6)
-RK4_S, DP45 = 0, 1
+RK4_S, DP45, RKF45, CK45, BS = 0, 1, 2, 3, 4
+BS_COLUMNS = 5
 
 
 class _Setup(C.Structure):
@@ -116,6 +117,10 @@ def lib():
         L.ko_horizon.argtypes = [C.c_double, C.c_double]
         L.ko_horizon.restype = C.c_double
         L.ko_harmonic_fixed.argtypes = [C.c_int32, C.c_double, C.c_int64, dp]
+        L.ko_fixed_steps.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_int64, dp, dp]
+        L.ko_one_step.argtypes = [C.c_int32, C.c_int32, C.c_double, dp, dp, dp]
+        L.ko_one_step.restype = C.c_int
+        L.ko_tableau.argtypes = [C.c_int32, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -229,3 +234,26 @@ def harmonic_fixed(method, T, n):
     out = np.zeros(2)
     lib().ko_harmonic_fixed(method, T, n, _dptr(out))
     return out
+
+
+def fixed_steps(method, problem, T, n, y0):
+    """n fixed steps on test problem 0 (y'' = -y as (y, y')) or 1 (y' = y^2)."""
+    y0 = np.ascontiguousarray(y0, dtype=np.float64)
+    out = np.zeros(y0.size)
+    lib().ko_fixed_steps(method, problem, T, n, _dptr(y0), _dptr(out))
+    return out
+
+
+def one_step(method, problem, h, y0):
+    """(y_new, error estimate, evaluations) of one step on a test problem."""
+    y0 = np.ascontiguousarray(y0, dtype=np.float64)
+    yn, e = np.zeros(y0.size), np.zeros(y0.size)
+    nev = lib().ko_one_step(method, problem, h, _dptr(y0), _dptr(yn), _dptr(e))
+    return yn, e, nev
+
+
+def tableau(method):
+    """(A[6, 6], b_propagated[6], b_embedded[6]) of RKF45 or CK45."""
+    A, bp, be = np.zeros(36), np.zeros(6), np.zeros(6)
+    lib().ko_tableau(method, _dptr(A), _dptr(bp), _dptr(be))
+    return A.reshape(6, 6), bp, be
