@@ -55,6 +55,10 @@ extern "C" {
 /* integrators */
 #define KT_RK4_S 0  /* classic RK4, fixed step h_fixed in s, d(lambda)/ds = Delta/r */
 #define KT_DP45 1   /* Dormand-Prince 5(4), adaptive, FSAL (Sect. 3.1) */
+#define KT_RKF45 2  /* Runge-Kutta-Fehlberg 4(5), adaptive, 4th order propagated (Sect. 3.1) */
+#define KT_CK45 3   /* Cash-Karp 5(4), adaptive, 5th order propagated (Sect. 3.1) */
+#define KT_BS 4     /* Bulirsch-Stoer: modified midpoint with 2, 4, .., 10 substeps,
+                       Aitken-Neville extrapolation (order 10), adaptive (Sect. 3.1) */
 
 /* arithmetic of the RHS */
 #define KT_FP64 0
@@ -89,11 +93,11 @@ typedef struct kt_source {
 } kt_source;
 
 typedef struct kt_integrator {
-    int32_t method;         /* KT_RK4_S or KT_DP45 */
+    int32_t method;         /* KT_RK4_S, KT_DP45, KT_RKF45, KT_CK45 or KT_BS */
     int32_t precision;      /* KT_FP64 or KT_MIXED */
     double h_fixed;         /* RK4_S step in s, > 0 */
-    double rtol, atol;      /* DP45 tolerances, > 0 */
-    double h_init;          /* DP45 first trial step in lambda, > 0 */
+    double rtol, atol;      /* tolerances of the adaptive methods, > 0 */
+    double h_init;          /* first trial step in lambda of the adaptive methods, > 0 */
     double capture_buffer;  /* delta_r of Sect. 4.1, >= 0 */
     double r_escape;        /* r_cs; 0 selects 1.1 r_obs */
     double h_budget;        /* MIXED: re-run in FP64 when max |H|_rel > h_budget */

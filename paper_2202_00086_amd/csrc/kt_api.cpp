@@ -95,7 +95,7 @@ void camera_constants(const kt_camera* cam, const kt_spacetime* st, kt::Image& i
 }
 
 int validate_integ(const kt_integrator* integ) {
-    if (integ->method != KT_RK4_S && integ->method != KT_DP45)
+    if (integ->method < KT_RK4_S || integ->method > KT_BS)
         return fail(KT_EINVAL, "unknown integrator method %d", integ->method);
     if (integ->precision != KT_FP64 && integ->precision != KT_MIXED)
         return fail(KT_EINVAL, "unknown precision %d", integ->precision);
@@ -109,7 +109,7 @@ int validate_integ(const kt_integrator* integ) {
         return fail(KT_EINVAL, "non-finite integrator parameter");
     if (integ->method == KT_RK4_S && !(integ->h_fixed > 0.0))
         return fail(KT_EINVAL, "h_fixed must be > 0");
-    if (integ->method == KT_DP45 && !(integ->rtol > 0.0 && integ->atol > 0.0 && integ->h_init > 0.0))
+    if (integ->method != KT_RK4_S && !(integ->rtol > 0.0 && integ->atol > 0.0 && integ->h_init > 0.0))
         return fail(KT_EINVAL, "rtol, atol and h_init must be > 0");
     if (!(integ->capture_buffer >= 0.0)) return fail(KT_EINVAL, "capture_buffer must be >= 0");
     if (integ->max_steps < 1 || integ->max_steps > 100000000)

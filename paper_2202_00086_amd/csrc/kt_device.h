@@ -474,6 +474,159 @@ __device__ __forceinline__ void dp45_step(const Spacetime& st, const RayConst& r
     for (int i = 0; i < 5; ++i) err[i] = h * fma(E7, kn[i], ep[i]);
 }
 
+// ---------------------------------------------------------------------------
+// Six-stage embedded pairs without FSAL, compared with DP5(4) in Sect. 3.1.
+// a(i, j): stage rows; b(j): weights of the propagated solution; e(j):
+// propagated minus embedded weights (the error estimate's weights).
+// ---------------------------------------------------------------------------
+// Fehlberg (1969) RK4(5): the 4th-order solution is propagated.
+struct Fehlberg45 {
+    static constexpr double a(int i, int j) {
+        constexpr double t[6][5] = {{0, 0, 0, 0, 0},
+                                    {1.0 / 4, 0, 0, 0, 0},
+                                    {3.0 / 32, 9.0 / 32, 0, 0, 0},
+                                    {1932.0 / 2197, -7200.0 / 2197, 7296.0 / 2197, 0, 0},
+                                    {439.0 / 216, -8.0, 3680.0 / 513, -845.0 / 4104, 0},
+                                    {-8.0 / 27, 2.0, -3544.0 / 2565, 1859.0 / 4104, -11.0 / 40}};
+        return t[i][j];
+    }
+    static constexpr double b(int j) {
+        constexpr double t[6] = {25.0 / 216, 0, 1408.0 / 2565, 2197.0 / 4104, -1.0 / 5, 0};
+        return t[j];
+    }
+    static constexpr double e(int j) {
+        constexpr double t[6] = {25.0 / 216 - 16.0 / 135, 0, 1408.0 / 2565 - 6656.0 / 12825,
+                                 2197.0 / 4104 - 28561.0 / 56430, -1.0 / 5 + 9.0 / 50, -2.0 / 55};
+        return t[j];
+    }
+};
+
+// Cash & Karp (1990) RK5(4): the 5th-order solution is propagated.
+struct CashKarp45 {
+    static constexpr double a(int i, int j) {
+        constexpr double t[6][5] = {{0, 0, 0, 0, 0},
+                                    {1.0 / 5, 0, 0, 0, 0},
+                                    {3.0 / 40, 9.0 / 40, 0, 0, 0},
+                                    {3.0 / 10, -9.0 / 10, 6.0 / 5, 0, 0},
+                                    {-11.0 / 54, 5.0 / 2, -70.0 / 27, 35.0 / 27, 0},
+                                    {1631.0 / 55296, 175.0 / 512, 575.0 / 13824, 44275.0 / 110592,
+                                     253.0 / 4096}};
+        return t[i][j];
+    }
+    static constexpr double b(int j) {
+        constexpr double t[6] = {37.0 / 378, 0, 250.0 / 621, 125.0 / 594, 0, 512.0 / 1771};
+        return t[j];
+    }
+    static constexpr double e(int j) {
+        constexpr double t[6] = {37.0 / 378 - 2825.0 / 27648, 0, 250.0 / 621 - 18575.0 / 48384,
+                                 125.0 / 594 - 13525.0 / 55296, -277.0 / 14336, 512.0 / 1771 - 1.0 / 4};
+        return t[j];
+    }
+};
+
+// One step of a six-stage pair of size h from y with k1 = f(y): the
+// propagated solution yn, kn = f(yn) with its diagnostics, and err = h sum
+// e_j k_j.  Inner stages take sin/cos of theta by angle addition from
+// (s0, c0); f(yn) computes them from theta.  Six RHS evaluations.
+template <class TAB>
+__device__ __forceinline__ void erk6_step(const Spacetime& st, const RayConst& rc, const double y[5],
+                                          const double k1[5], double s0, double c0, double h, double yn[5],
+                                          double kn[5], double err[5], Diag* dg) {
+    double k[6][5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) k[0][i] = k1[i];
+#pragma unroll
+    for (int stg = 1; stg < 6; ++stg) {
+        double ys[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            double acc = TAB::a(stg, 0) * k[0][i];
+#pragma unroll
+            for (int j = 1; j < stg; ++j)
+                if (TAB::a(stg, j) != 0.0) acc = fma(TAB::a(stg, j), k[j][i], acc);
+            ys[i] = fma(h, acc, y[i]);
+        }
+        eval_rhs<false, false>(st, nullptr, rc, ys, y[1], s0, c0, k[stg], dg);
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        double acc = 0.0, ea = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            if (TAB::b(j) != 0.0) acc = fma(TAB::b(j), k[j][i], acc);
+            if (TAB::e(j) != 0.0) ea = fma(TAB::e(j), k[j][i], ea);
+        }
+        yn[i] = fma(h, acc, y[i]);
+        err[i] = h * ea;
+    }
+    eval_rhs<false, true>(st, nullptr, rc, yn, y[1], s0, c0, kn, dg);
+}
+
+// ---------------------------------------------------------------------------
+// Bulirsch-Stoer extrapolation (the third scheme of Sect. 3.1).  For
+// k = 1..BS_COLUMNS the modified midpoint chain with n_k = 2k substeps
+// across [0, h] starts from y; its end is extrapolated to zero substep size
+// with the earlier chains' ends by Aitken-Neville in (h/n_k)^2, one tableau
+// row at a time kept in place.  The last diagonal entry (order 2K) is the
+// step's result; the error vector is its difference to the entry before it.
+// Chains span the whole step, so every evaluation takes sin/cos of theta
+// from theta itself.  K^2 + 1 RHS evaluations.
+// ---------------------------------------------------------------------------
+constexpr int BS_COLUMNS = 5;
+
+// 1 / ((n_k / n_(k-j))^2 - 1) with n = 2k, k = 1..BS_COLUMNS (as indices k, j
+// from 0): the Aitken-Neville weights.
+constexpr double bs_weight(int k, int j) {
+    return 1.0 / (static_cast<double>((k + 1) * (k + 1)) / static_cast<double>((k - j + 1) * (k - j + 1)) - 1.0);
+}
+
+__device__ __forceinline__ void bs_step(const Spacetime& st, const RayConst& rc, const double y[5],
+                                        const double k1[5], double h, double yn[5], double kn[5],
+                                        double err[5], Diag* dg) {
+    double T[BS_COLUMNS][5];  // row k of the tableau after chain k
+#pragma unroll
+    for (int k = 0; k < BS_COLUMNS; ++k) {
+        const int ns = 2 * (k + 1);
+        const double hs = h * (1.0 / ns);
+        const double h2 = 2.0 * hs;
+        double zp[5], zc[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            zp[i] = y[i];
+            zc[i] = fma(hs, k1[i], y[i]);
+        }
+#pragma unroll 1
+        for (int m = 1; m < ns; ++m) {
+            double fz[5];
+            rhs<false, false>(st, rc, zc, fz, nullptr);
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+                const double zn = fma(h2, fz[i], zp[i]);
+                zp[i] = zc[i];
+                zc[i] = zn;
+            }
+        }
+        // Aitken-Neville: T[k][j] = T[k][j-1] + (T[k][j-1] - T[k-1][j-1]) w(k, j)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            double carry = zc[i];
+#pragma unroll
+            for (int j = 1; j <= k; ++j) {
+                const double old = T[j - 1][i];
+                T[j - 1][i] = carry;
+                carry = fma(carry - old, bs_weight(k, j), carry);
+            }
+            T[k][i] = carry;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        yn[i] = T[BS_COLUMNS - 1][i];
+        err[i] = T[BS_COLUMNS - 1][i] - T[BS_COLUMNS - 2][i];
+    }
+    rhs<true, false>(st, rc, yn, kn, dg);
+}
+
 // One classic RK4 step of size h (in s) from y with k1 = F(y), F the field
 // scaled by Delta/r.  Writes yn and kn = F(yn) with diagnostics.  Four RHS
 // evaluations.

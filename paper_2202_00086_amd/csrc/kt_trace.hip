@@ -147,6 +147,12 @@ __device__ __forceinline__ void take_step(const Spacetime& st, const RayConst& r
                                           double kn[5], double er[5], Diag* dg) {
     if constexpr (METHOD == KT_DP45) {
         dp45_step(st, rc, y, k1, s0, c0, h, yn, kn, er, dg);
+    } else if constexpr (METHOD == KT_RKF45) {
+        erk6_step<Fehlberg45>(st, rc, y, k1, s0, c0, h, yn, kn, er, dg);
+    } else if constexpr (METHOD == KT_CK45) {
+        erk6_step<CashKarp45>(st, rc, y, k1, s0, c0, h, yn, kn, er, dg);
+    } else if constexpr (METHOD == KT_BS) {
+        bs_step(st, rc, y, k1, h, yn, kn, er, dg);
     } else {
         rk4s_step(st, rc, y, k1, h, yn, kn, dg);
 #pragma unroll
@@ -154,10 +160,24 @@ __device__ __forceinline__ void take_step(const Spacetime& st, const RayConst& r
     }
 }
 
-// Step-size factor err^(-1/5) * 0.9 from the mean-square error msq = err^2,
+// Evaluations per step and the step-size controller exponent 1/(q + 1), q
+// the order of the method's error estimate (4 for the Runge-Kutta pairs,
+// 2K - 2 for Bulirsch-Stoer with K columns).
+template <int METHOD>
+constexpr int evals_per_step() {
+    return METHOD == KT_RK4_S ? 4 : METHOD == KT_BS ? BS_COLUMNS * BS_COLUMNS + 1 : 6;
+}
+template <int METHOD>
+constexpr float controller_exponent() {
+    return METHOD == KT_BS ? 1.0f / (2 * BS_COLUMNS - 1) : 0.2f;
+}
+
+// Step-size factor 0.9 err^(-1/(q+1)) from the mean-square error msq = err^2,
 // evaluated in FP32: it only steers the step size.
+template <int METHOD>
 __device__ __forceinline__ float step_factor(double msq) {
-    return 0.9f * __builtin_amdgcn_exp2f(-0.1f * __builtin_amdgcn_logf(static_cast<float>(msq)));
+    constexpr float x = -0.5f * controller_exponent<METHOD>();
+    return 0.9f * __builtin_amdgcn_exp2f(x * __builtin_amdgcn_logf(static_cast<float>(msq)));
 }
 
 // Mean square of err_i / sc_i over the five components.  The five
@@ -181,7 +201,8 @@ __device__ __forceinline__ double error_msq(const double er[5], const double sc[
 template <int METHOD, int PREC, bool BATCH>
 __global__ void __launch_bounds__(BLOCK_MAX) __attribute__((amdgpu_waves_per_eu(KT_WAVES_PER_EU)))
 trace_kernel(const Hot hp) {
-    constexpr int EVALS_PER_STEP = (METHOD == KT_DP45) ? 6 : 4;
+    constexpr int EVALS_PER_STEP = evals_per_step<METHOD>();
+    constexpr bool ADAPTIVE = (METHOD != KT_RK4_S);
     constexpr bool S_TIME = (METHOD == KT_RK4_S);
     constexpr bool MIXED = (PREC == KT_MIXED) && (METHOD == KT_DP45);
     __shared__ double cold[N_COLD][BLOCK_MAX];
@@ -255,7 +276,7 @@ trace_kernel(const Hot hp) {
                 } else {
                     fl = camera_state(P.img0, ray, y, &E, &L) ? (F_VALID | F_FRESH) : 0;
                 }
-                h = (METHOD == KT_DP45) ? P.h_init : P.h_fixed;
+                h = ADAPTIVE ? P.h_init : P.h_fixed;
                 nsteps = 0;
                 nevals = 0;
             }
@@ -372,7 +393,7 @@ trace_kernel(const Hot hp) {
                 if (!finite) {
                     fate = KT_FATE_STEPFAIL;
                     accept = false;
-                } else if constexpr (METHOD == KT_DP45) {
+                } else if constexpr (ADAPTIVE) {
                     // mean square of err_i / (atol + rtol max(|y_i|, |yn_i|))
                     double sc[5];
 #pragma unroll
@@ -382,13 +403,13 @@ trace_kernel(const Hot hp) {
                         fate = KT_FATE_STEPFAIL;
                         accept = false;
                     } else if (msq > 1.0) {
-                        h *= static_cast<double>(fmaxf(0.2f, step_factor(msq)));
+                        h *= static_cast<double>(fmaxf(0.2f, step_factor<METHOD>(msq)));
                         fl |= F_REJECTED;
                         accept = false;
                         if (h < 1e-12 * fmax(1.0, fabs(COLD(C_LAM)))) fate = KT_FATE_STEPFAIL;
                     } else {
                         double fac = 5.0;
-                        if (msq >= 1e-20) fac = static_cast<double>(fminf(5.0f, fmaxf(0.2f, step_factor(msq))));
+                        if (msq >= 1e-20) fac = static_cast<double>(fminf(5.0f, fmaxf(0.2f, step_factor<METHOD>(msq))));
                         if (fl & F_REJECTED) fac = fmin(fac, 1.0);
                         h_next = h * fac;
                     }
@@ -749,12 +770,18 @@ static void launch_variant(const Params& p, const Hot& hp, int grid, int block, 
 int launch_trace(const Params& p, int grid, int block, void* stream) {
     const Hot hp = make_hot(p);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (p.method == KT_DP45 && p.precision == KT_MIXED)
-        launch_variant<KT_DP45, KT_MIXED>(p, hp, grid, block, s);
-    else if (p.method == KT_DP45)
-        launch_variant<KT_DP45, KT_FP64>(p, hp, grid, block, s);
-    else
-        launch_variant<KT_RK4_S, KT_FP64>(p, hp, grid, block, s);
+    switch (p.method) {
+    case KT_DP45:
+        if (p.precision == KT_MIXED)
+            launch_variant<KT_DP45, KT_MIXED>(p, hp, grid, block, s);
+        else
+            launch_variant<KT_DP45, KT_FP64>(p, hp, grid, block, s);
+        break;
+    case KT_RKF45: launch_variant<KT_RKF45, KT_FP64>(p, hp, grid, block, s); break;
+    case KT_CK45: launch_variant<KT_CK45, KT_FP64>(p, hp, grid, block, s); break;
+    case KT_BS: launch_variant<KT_BS, KT_FP64>(p, hp, grid, block, s); break;
+    default: launch_variant<KT_RK4_S, KT_FP64>(p, hp, grid, block, s); break;
+    }
     return check_launch();
 }
 
@@ -783,12 +810,16 @@ static hipError_t occupancy_variant(const Params& p, int* nb, int block) {
 int trace_max_blocks_per_cu(const Params& p, int block) {
     int nb = 0;
     hipError_t e;
-    if (p.method == KT_DP45 && p.precision == KT_MIXED)
-        e = occupancy_variant<KT_DP45, KT_MIXED>(p, &nb, block);
-    else if (p.method == KT_DP45)
-        e = occupancy_variant<KT_DP45, KT_FP64>(p, &nb, block);
-    else
-        e = occupancy_variant<KT_RK4_S, KT_FP64>(p, &nb, block);
+    switch (p.method) {
+    case KT_DP45:
+        e = p.precision == KT_MIXED ? occupancy_variant<KT_DP45, KT_MIXED>(p, &nb, block)
+                                    : occupancy_variant<KT_DP45, KT_FP64>(p, &nb, block);
+        break;
+    case KT_RKF45: e = occupancy_variant<KT_RKF45, KT_FP64>(p, &nb, block); break;
+    case KT_CK45: e = occupancy_variant<KT_CK45, KT_FP64>(p, &nb, block); break;
+    case KT_BS: e = occupancy_variant<KT_BS, KT_FP64>(p, &nb, block); break;
+    default: e = occupancy_variant<KT_RK4_S, KT_FP64>(p, &nb, block); break;
+    }
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 

@@ -1,0 +1,114 @@
+"""The comparison integrators of Sect. 3.1 on the GPU (RKF45, Cash-Karp
+5(4), Bulirsch-Stoer) against the oracle running the same schemes, element
+by element, plus bit-identity of their batch and launch-shape forms."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2202_00086_amd import workloads as W
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+SCHEMES = [("rkf45", 2), ("ck45", 3), ("bs", 4)]
+
+
+def _announce(*what):
+    print("[gpu-case]", *what, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2202_00086_amd import kerrtrace
+    return kerrtrace
+
+
+def gpu_render(K, params, launch=None):
+    import torch
+    r = K.Renderer(device="cuda:0", launch=launch, **params)
+    out = r.render()
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items() if k != "stats"}
+    res["stats"] = K.read_stats(out)
+    return res
+
+
+@pytest.mark.parametrize("name, method", SCHEMES)
+def test_scheme_kerr_ring_parity(K, name, method):
+    """a = 0.9 ring workload at 64x48 (ragged tail), rtol 1e-11."""
+    params = dict(W.kerr_ring(0.9, n=64, rtol=1e-11), ny=48, method=method)
+    _announce("scheme ring", name)
+    g = gpu_render(K, params)
+    o = O.trace_pixels(O.Setup(**params))
+    P.check_fates(g["fate"], o["fate"], 64, 48, min_allowed=2)
+    m = P.value_mask(g, o, 64, 48)
+    # The swept angle is a sum of arcs between accepted positions, so it
+    # depends on where the steps land.  The kernel's step factor is FP32
+    # (step ends differ at ~1e-7), so the tolerance is 10x the oracle's own
+    # change when its first step moves by 1e-7: ~4e-14 for the Runge-Kutta
+    # pairs (hundreds of short steps), up to ~1e-5 for Bulirsch-Stoer's few
+    # long ones.
+    o2 = O.trace_pixels(O.Setup(**dict(params, h_init=params["h_init"] * (1 + 1e-7))))
+    same = m & (o2["fate"] == o["fate"]) & np.isfinite(o["deflection"])
+    sens = {k: float(np.max(P.rel_err(o2[k][same & np.isfinite(o[k])], o[k][same & np.isfinite(o[k])])))
+            for k in ("deflection", "psi")}
+    tol = {k: max(1e-8, 10.0 * v) for k, v in sens.items()}
+    print(f"[{name}] step-placement sensitivity {sens}", flush=True)
+    assert tol["deflection"] < 1e-3
+    P.check_values(g, o, "deflection", m, rtol=tol["deflection"])
+    ok = m & np.isfinite(o["psi"]) & (o["psi"] > 1e-6)
+    P.check_values(g, o, "psi", ok, rtol=max(1e-7, tol["psi"]))
+    # every ray within the scheme's own level (the oracle's p99 at this
+    # tolerance is 2.5e-9, 3.4e-10 and 2.2e-11 for RKF45, CK45 and BS), and
+    # the distributions' percentiles agree
+    P.check_max_h(g, o, "max_rel_h", m, budget={2: 1e-8, 3: 2e-9, 4: 2e-10}[method])
+    per = {2: 6, 3: 6, 4: O.BS_COLUMNS ** 2 + 1}[method]
+    assert (g["n_evals"] >= per * g["n_steps"]).all()
+    assert g["stats"].evals == g["n_evals"].astype(np.int64).sum()
+
+
+@pytest.mark.parametrize("name, method", SCHEMES)
+def test_scheme_disk_parity(K, name, method):
+    """Kerr a = 0.9 disk at i = 60 deg, 48x40, rtol 1e-11: hit radius,
+    redshift and intensity to 1e-8."""
+    params = dict(W.kerr_disk(a=0.9, incl_deg=60.0, n=48, r_in=W.isco(0.9), rtol=1e-11), ny=40,
+                  method=method)
+    _announce("scheme disk", name)
+    g = gpu_render(K, params)
+    o = O.trace_pixels(O.Setup(**params))
+    P.check_fates(g["fate"], o["fate"], 48, 40, min_allowed=2)
+    m = P.value_mask(g, o, 48, 40) & (o["fate"] == O.DISK)
+    assert m.sum() > 100
+    for key in ("r_hit", "g", "intensity"):
+        P.check_values(g, o, key, m, rtol=1e-8)
+
+
+@pytest.mark.parametrize("name, method", SCHEMES)
+def test_scheme_batch_and_launch_shapes_bit_identical(K, name, method):
+    """Each scheme's batch instantiation equals its single renders, and its
+    outputs do not depend on the launch shape."""
+    import torch
+    images, integ = W.heterogeneous_batch(n_images=4, seed=3, side_unit=8, side_steps=4)
+    integ = dict(integ, method=method, rtol=1e-10, atol=1e-10)
+    _announce("scheme batch", name)
+    br = K.BatchRenderer(images, device="cuda:0", **integ)
+    br.render()
+    torch.cuda.synchronize()
+    for k, im in enumerate(images):
+        s = gpu_render(K, W.image_params(im, integ))
+        f, n = br.first[k], br.sizes[k]
+        for key in ("fate", "r_hit", "g", "max_rel_h", "n_steps", "n_evals"):
+            np.testing.assert_array_equal(br.out[key][f:f + n].cpu().numpy().view(np.uint8),
+                                          s[key].view(np.uint8), err_msg=f"{name} image {k} {key}")
+    p0 = W.image_params(images[0], integ)
+    ref = gpu_render(K, p0)
+    for ln in [K.kt_launch(1, 64, 1, 1), K.kt_launch(0, 128, 0, 32)]:
+        g = gpu_render(K, p0, launch=ln)
+        for key in ("fate", "r_hit", "g", "max_rel_h", "n_steps"):
+            np.testing.assert_array_equal(g[key].view(np.uint8), ref[key].view(np.uint8), err_msg=key)
