@@ -150,6 +150,38 @@ def _time(torch, fn, steps):
     return (time.perf_counter() - t0) / steps
 
 
+SCHEME_WANT = ("fate", "max_abs_h", "max_rel_h", "n_evals")
+
+
+def run_scheme_forms(K, torch, W, steps):
+    """The four adaptive schemes the paper compares (Sect. 3.1) on the same
+    persistent kernel: on the paper's Hamiltonian-norm grid (625^2, +-8M,
+    r0 = 100M, a = 0.98) and on the headline 1024^2 workload, all at
+    rtol = atol = 1e-12.  Per scheme: time, rays/s, evaluations per ray and
+    the constraint statistics."""
+    res = {"tolerance": 1e-12}
+    for wname, make in (("hamiltonian_norm_map_625", lambda m: W.hamiltonian_norm_map(625, method=m)),
+                        ("kerr_ring_1024_a0.9", lambda m: dict(W.kerr_ring(0.9, n=1024, rtol=1e-12), method=m))):
+        row = {}
+        for m in (K.DP45, K.RKF45, K.CK45, K.BS):
+            r = K.Renderer(device="cuda:0", want=SCHEME_WANT, **make(m))
+            r.render()
+            t = _time(torch, r.render, steps)
+            st = K.read_stats(r.out)
+            ok = r.out["fate"] <= K.DISK
+            ha = r.out["max_abs_h"][ok]
+            hr = r.out["max_rel_h"][ok]
+            row[K.METHOD_NAMES[m]] = {
+                "ms_per_image": 1e3 * t, "rays_per_s": r.n / t, "stage_evals_per_s": st.evals / t,
+                "evals_per_ray": st.evals / r.n, "mean_abs_h": float(ha.mean().item()),
+                "max_abs_h": float(ha.max().item()), "mean_rel_h": float(hr.mean().item()),
+                "max_rel_h": float(hr.max().item()),
+                "p999_rel_h": float(torch.quantile(hr.float()[::max(1, hr.numel() // 200000)], 0.999).item()),
+                "fates": [int(c) for c in st.fate_count[:6]]}
+        res[wname] = row
+    return res
+
+
 def run_batch_forms(K, torch, W, steps):
     """The 256-image heterogeneous Kerr disk workload: one autotuned
     persistent FP64 launch, the same images as 256 separate FP64 launches,
@@ -264,9 +296,10 @@ def main():
                            "max_rel_h": f["max_rel_h"], "p999_rel_h": f["p999_rel_h"],
                            "error_vs_fp64": error_vs(torch, f["out"], main_form["out"])}
 
-    batch = None
+    batch = schemes = None
     if not args.no_forms:
         batch = run_batch_forms(K, torch, W, max(2, args.steps // 8))
+        schemes = run_scheme_forms(K, torch, W, max(2, args.steps // 8))
 
     out = {"metric": METRIC, "value": rays_per_s, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": main_form["ms_per_step"], "higher_is_better": True,
@@ -284,6 +317,8 @@ def main():
         out["forms"] = forms
     if batch:
         out["batch"] = batch
+    if schemes:
+        out["integrators"] = schemes
     if not args.no_cpu:
         cb = cpu_baseline(params)
         out["cpu_baseline"] = cb

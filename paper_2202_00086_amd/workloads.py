@@ -12,6 +12,8 @@ the CPU oracle (oracle.Setup) accept these keyword names.
                             point source at r_src = 1000M behind the hole.
   schwarzschild_disk_2048   a = 0, 2048x2048, i = 80 deg, r_obs = 1000M,
                             +-35M, thin Keplerian disk 6M..30M, I_em ~ r^-2.
+  hamiltonian_norm_map      a = 0.98, 625x625, r_obs = 100M, i = 90 deg, +-8M
+                            (the integrator comparison grid).
   heterogeneous_batch       256 seeded Kerr disk images: sides 64..1024 in
                             steps of 64, a ~ U[0, 0.998], i ~ U[5, 85] deg,
                             r_obs log-uniform in [100, 1e4]M, +-35M, disk
@@ -45,6 +47,15 @@ def kerr_disk(a=0.9, incl_deg=60.0, n=256, r_in=None, r_obs=1000.0, fov=35.0, rt
                 ny=n, method=1, rtol=rtol, atol=rtol, h_init=1.0, cap_buffer=0.01, r_escape=1.1 * r_obs,
                 max_steps=1_000_000, disk_on=1, r_in=r_in if r_in is not None else 6.0, r_out=30.0,
                 emis_q=2.0)
+
+
+def hamiltonian_norm_map(n=625, method=1, rtol=1e-12):
+    """The integrator comparison of Sect. 3.1: a dense n x n grid over
+    -8M <= x, y <= 8M seen from r0 = 100M; spin 0.98 and inclination 90 deg
+    as for the two rays of that section's figures."""
+    return dict(M=1.0, a=0.98, r_obs=100.0, incl=math.pi / 2, fov_x=8.0, fov_y=8.0, nx=n, ny=n,
+                method=method, rtol=rtol, atol=rtol, h_init=1.0, cap_buffer=0.01, r_escape=110.0,
+                max_steps=1_000_000)
 
 
 def isco(a, M=1.0):
