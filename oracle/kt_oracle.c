@@ -25,8 +25,11 @@
  *   - the constraint monitor Error = |H_num| (Sect. 3.1);
  *   - termination at r < r_H + delta_r (captured) and r > r_cs (escaped),
  *     Sect. 4.1, and on a thin equatorial disk (Sect. 5);
- *   - the redshift g = nu_obs/nu_em of eq:redshift for circular Keplerian
- *     emitters, and I_obs = g^3 I_em (Sect. 5).
+ *   - the redshift g = nu_obs/nu_em of eq:redshift for circular emitters
+ *     (Keplerian, or with the constant specific angular momentum l0 of
+ *     Sect. 5), and I_obs = g^3 I_em;
+ *   - the coloured celestial sphere of Sect. 4.1: four quadrants and a
+ *     graticule, hit where the ray crosses r = r_cs.
  * Readings where the paper is silent or garbled (sign of p_r, the printed
  * redshift being -1/g, step control, event location, tolerances) are listed
  * in the design notes; the constants used here are the same readings.
@@ -539,6 +542,36 @@ static double arc_between(double th1, double ph1, double th2, double ph2)
     return atan2(cr, dt);
 }
 
+int ko_sky_code(double theta, double phi, double grid_deg, double line_deg)
+{
+    /* canonical angles from the unit vector of the direction */
+    double n[3];
+    unit_dir(theta, phi, n);
+    double th = acos(fmax(-1.0, fmin(1.0, n[2])));
+    double ph = atan2(n[1], n[0]);
+    if (ph < 0.0) ph += 2.0 * PI;
+    if (ph >= 2.0 * PI) ph -= 2.0 * PI;
+    if (grid_deg > 0.0) {
+        double tdeg = th * 180.0 / PI, pdeg = ph * 180.0 / PI;
+        double dt = fabs(tdeg - grid_deg * round(tdeg / grid_deg));
+        double dp = fabs(pdeg - grid_deg * round(pdeg / grid_deg));
+        if (dt <= line_deg || dp <= line_deg) return KO_SKY_LINE;
+    }
+    if (th < PI / 2) return ph < PI ? KO_SKY_GREEN : KO_SKY_RED;
+    return ph < PI ? KO_SKY_BLUE : KO_SKY_YELLOW;
+}
+
+double ko_disk_omega(double M, double a, double r, int32_t rotation, double l0)
+{
+    if (rotation == 1) {
+        /* constant specific angular momentum l0 = -u_phi / u_t */
+        double g[5];
+        ko_metric_cov(M, a, r, PI / 2, g);
+        return -(g[1] + l0 * g[0]) / (g[4] + l0 * g[1]);
+    }
+    return sqrt(M) / (pow(r, 1.5) + a * sqrt(M));
+}
+
 static int all_finite(const double *v, int n)
 {
     for (int i = 0; i < n; ++i)
@@ -555,6 +588,7 @@ static int64_t trace_ray(const ko_setup *s, double x, double y, const ko_out *o,
     int fate = KO_MAXSTEPS;
     double r_hit = NaN, gred = NaN, inten = 0.0, psi = NaN, defl = NaN;
     int ncross = 0;
+    int sky = KO_SKY_NONE;
     int64_t nsteps = 0, npts = 0;
     double maxabs = NaN, maxrel = NaN;
 
@@ -662,10 +696,13 @@ static int64_t trace_ray(const ko_setup *s, double x, double y, const ko_out *o,
                     if (rc >= s->r_in && rc <= s->r_out) {
                         double gm[5];
                         ko_metric_cov(s->M, s->a, rc, PI / 2, gm);
-                        double Om = sqrt(s->M) / (pow(rc, 1.5) + s->a * sqrt(s->M));
-                        double ut = 1.0 / sqrt(-gm[0] - 2.0 * Om * gm[1] - Om * Om * gm[4]);
-                        gred = 1.0 / (ut * (E - Om * L));
-                        inten = gred * gred * gred * pow(s->M / rc, s->emis_q);
+                        double Om = ko_disk_omega(s->M, s->a, rc, s->rotation, s->l0);
+                        double norm = -gm[0] - 2.0 * Om * gm[1] - Om * Om * gm[4];
+                        if (norm > 0.0) {
+                            double ut = 1.0 / sqrt(norm);
+                            gred = 1.0 / (ut * (E - Om * L));
+                            inten = gred * gred * gred * pow(s->M / rc, s->emis_q);
+                        } /* else: no timelike circular orbit there; g stays NaN */
                         r_hit = rc;
                         fate = KO_DISK;
                         thf = zc[1];
@@ -697,6 +734,15 @@ static int64_t trace_ray(const ko_setup *s, double x, double y, const ko_out *o,
                 fate = KO_ESCAPED;
                 thf = zn[1];
                 phf = zn[2];
+                if (s->sky_on) {
+                    /* the point where the ray meets the celestial sphere */
+                    double zc[5];
+                    locate_event(&t, z, k1, h, 0, s->r_escape, z[0] - s->r_escape,
+                                 zn[0] - s->r_escape, 1e-12 * s->r_escape, zc);
+                    thf = zc[1];
+                    phf = zc[2];
+                    sky = ko_sky_code(thf, phf, s->grid_deg, s->line_deg);
+                }
                 break;
             }
             memcpy(z, zn, sizeof z);
@@ -722,6 +768,7 @@ done:
     if (o->n_cross) o->n_cross[k] = (uint8_t)ncross;
     if (o->n_steps) o->n_steps[k] = (int32_t)nsteps;
     if (o->n_evals) o->n_evals[k] = (int32_t)t.evals;
+    if (o->sky) o->sky[k] = (uint8_t)sky;
     return npts;
 }
 

@@ -54,13 +54,30 @@ typedef struct {
     double cap_buffer;   /* delta_r: captured when r < r_+ + cap_buffer */
     double r_escape;     /* escaped when r > r_escape */
     int64_t max_steps;   /* accepted-step cap */
-    /* thin equatorial disk */
+    /* thin equatorial disk; rotation 0: prograde Keplerian, 1: constant
+       specific angular momentum l0 (Sect. 5) */
     int32_t disk_on;
     double r_in, r_out, emis_q;
+    int32_t rotation;
+    double l0;
     /* point source for the deflection diagnostics */
     int32_t src_on;
     double r_src;
+    /* celestial sphere at r_escape (Sect. 4.1): when sky_on, the crossing
+       of r = r_escape is located and classified into the four coloured
+       quadrants and the graticule of lines every grid_deg degrees with
+       half-width line_deg */
+    int32_t sky_on;
+    double grid_deg, line_deg;
 } ko_setup;
+
+/* sky codes */
+#define KO_SKY_NONE 0   /* the ray did not reach the celestial sphere */
+#define KO_SKY_GREEN 1  /* 0 <= theta < pi/2, 0 <= phi < pi */
+#define KO_SKY_RED 2    /* 0 <= theta < pi/2, pi <= phi < 2 pi */
+#define KO_SKY_BLUE 3   /* pi/2 <= theta <= pi, 0 <= phi < pi */
+#define KO_SKY_YELLOW 4 /* pi/2 <= theta <= pi, pi <= phi < 2 pi */
+#define KO_SKY_LINE 5   /* on a graticule line */
 
 /* Per-ray results.  Arrays hold one entry per traced ray; any pointer may be
    NULL except fate. */
@@ -72,6 +89,7 @@ typedef struct {
     double *theta_f, *phi_f;
     uint8_t *n_cross;
     int32_t *n_steps, *n_evals;
+    uint8_t *sky;
 } ko_out;
 
 /* Covariant Kerr metric at (r, theta): g = {g_tt, g_tph, g_rr, g_thth, g_phph}. */
@@ -122,6 +140,14 @@ int64_t ko_trace_one(const ko_setup *s, double x, double y, double *traj, int64_
    p is flagged when, for its +i or +j neighbour q with both deflections
    finite, an odd multiple of pi lies between Psi_p and Psi_q. */
 void ko_ring_flags(int32_t nx, int32_t ny, const double *deflection, uint8_t *ring);
+
+/* Sky code of the direction (theta, phi), any representation (theta may lie
+   outside [0, pi] after the ray crossed the polar axis). */
+int ko_sky_code(double theta, double phi, double grid_deg, double line_deg);
+
+/* Angular velocity Omega = u^phi / u^t of the disk's circular orbits at
+   radius r in the equatorial plane for the given rotation model. */
+double ko_disk_omega(double M, double a, double r, int32_t rotation, double l0);
 
 /* Outer horizon r_+ = M + sqrt(M^2 - a^2). */
 double ko_horizon(double M, double a);

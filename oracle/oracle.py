@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("KT_ORACLE_LIB") or os.path.join(HERE, "libkt_oracle.s
 
 ESCAPED, CAPTURED, DISK, MAXSTEPS, STEPFAIL, INVALID = range(6)
 RK4_S, DP45, RKF45, CK45, BS = 0, 1, 2, 3, 4
+SKY_NONE, SKY_GREEN, SKY_RED, SKY_BLUE, SKY_YELLOW, SKY_LINE = range(6)
 BS_COLUMNS = 5
 
 
@@ -32,7 +33,9 @@ class _Setup(C.Structure):
         ("cap_buffer", C.c_double), ("r_escape", C.c_double),
         ("max_steps", C.c_int64),
         ("disk_on", C.c_int32), ("r_in", C.c_double), ("r_out", C.c_double), ("emis_q", C.c_double),
+        ("rotation", C.c_int32), ("l0", C.c_double),
         ("src_on", C.c_int32), ("r_src", C.c_double),
+        ("sky_on", C.c_int32), ("grid_deg", C.c_double), ("line_deg", C.c_double),
     ]
 
 
@@ -45,6 +48,7 @@ class _Out(C.Structure):
         ("theta_f", C.c_void_p), ("phi_f", C.c_void_p),
         ("n_cross", C.c_void_p),
         ("n_steps", C.c_void_p), ("n_evals", C.c_void_p),
+        ("sky", C.c_void_p),
     ]
 
 
@@ -75,8 +79,13 @@ class Setup:
     r_in: float = 6.0
     r_out: float = 30.0
     emis_q: float = 2.0
+    rotation: int = 0              # 0 Keplerian, 1 constant l0
+    l0: float = 0.0
     src_on: int = 0
     r_src: float = 1000.0
+    sky_on: int = 0
+    grid_deg: float = 6.0
+    line_deg: float = 0.25
 
     def _c(self):
         s = _Setup()
@@ -121,6 +130,10 @@ def lib():
         L.ko_one_step.argtypes = [C.c_int32, C.c_int32, C.c_double, dp, dp, dp]
         L.ko_one_step.restype = C.c_int
         L.ko_tableau.argtypes = [C.c_int32, dp, dp, dp]
+        L.ko_sky_code.argtypes = [C.c_double] * 4
+        L.ko_sky_code.restype = C.c_int
+        L.ko_disk_omega.argtypes = [C.c_double] * 3 + [C.c_int32, C.c_double]
+        L.ko_disk_omega.restype = C.c_double
         _lib = L
     return _lib
 
@@ -178,7 +191,7 @@ def pixel_xy(setup, i, j):
 
 
 def _alloc(n):
-    o = {"fate": np.zeros(n, np.uint8), "n_cross": np.zeros(n, np.uint8),
+    o = {"fate": np.zeros(n, np.uint8), "n_cross": np.zeros(n, np.uint8), "sky": np.zeros(n, np.uint8),
          "n_steps": np.zeros(n, np.int32), "n_evals": np.zeros(n, np.int32)}
     for k in _F64_OUT:
         o[k] = np.zeros(n, np.float64)
@@ -228,6 +241,14 @@ def ring_flags(nx, ny, deflection):
     ring = np.zeros(nx * ny, np.uint8)
     lib().ko_ring_flags(nx, ny, _dptr(d), ring.ctypes.data)
     return ring
+
+
+def sky_code(theta, phi, grid_deg=6.0, line_deg=0.25):
+    return lib().ko_sky_code(theta, phi, grid_deg, line_deg)
+
+
+def disk_omega(M, a, r, rotation=0, l0=0.0):
+    return lib().ko_disk_omega(M, a, r, rotation, l0)
 
 
 def harmonic_fixed(method, T, n):
