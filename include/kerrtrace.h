@@ -8,7 +8,8 @@
  * a thin equatorial disk or on escape (Sect. 4.1, Sect. 5).
  *
  * Conventions
- *   - Geometrized units; M is a parameter (the paper sets M = 1, Sect. 1).
+ *   - Geometrized units; M is a parameter (the paper sets M = 1, Sect. 1);
+ *     M = 0 (with a = 0) is flat space, the reference image of Sect. 4.2.
  *   - The observer sits at (r_obs, theta_0 = incl, phi_0 = 0).  Pixel (i, j)
  *     has image-plane centre x = -fov_x + (i + 1/2) 2 fov_x / nx,
  *     y = -fov_y + (j + 1/2) 2 fov_y / ny (image plane of Sect. 2.3) and
@@ -36,7 +37,7 @@
 extern "C" {
 #endif
 
-#define KT_VERSION_NUMBER 110
+#define KT_VERSION_NUMBER 120
 
 /* return codes */
 #define KT_OK 0
@@ -74,23 +75,46 @@ typedef struct kt_camera {
     int32_t nx, ny; /* resolution, >= 1 each, nx*ny < 2^31 */
 } kt_camera;
 
-/* Kerr spacetime (eq:Kerr): mass M > 0, spin |a| <= M. */
+/* Kerr spacetime (eq:Kerr): mass M >= 0, spin |a| <= M. */
 typedef struct kt_spacetime {
     double M, a;
 } kt_spacetime;
 
-/* Thin equatorial Keplerian disk (Sect. 5). Emissivity (M/r)^emis_index. */
+/* Thin equatorial disk (Sect. 5). Emissivity (M/r)^emis_index.  Circular
+   orbits rotate with the prograde Keplerian Omega = sqrt(M)/(r^1.5 + a sqrt(M))
+   (rotation = KT_ROT_KEPLER) or with constant specific angular momentum
+   l0 = -u_phi/u_t, Omega = -(g_tphi + l0 g_tt)/(g_phiphi + l0 g_tphi)
+   (rotation = KT_ROT_L0).  Where the orbit is not timelike, g is NaN and the
+   intensity 0. */
+#define KT_ROT_KEPLER 0
+#define KT_ROT_L0 1
 typedef struct kt_disk {
     int32_t enabled;
     double r_in, r_out, emis_index;
+    int32_t rotation;       /* KT_ROT_KEPLER or KT_ROT_L0 */
+    double l0;              /* specific angular momentum for KT_ROT_L0 */
 } kt_disk;
 
-/* Point source at (r_src, pi - incl, pi), behind the hole: deflection
-   diagnostics for Einstein rings (Sect. 4.3). */
+/* Light sources.  A point source at (r_src, pi - incl, pi), behind the hole:
+   deflection diagnostics for Einstein rings (Sect. 4.3).  The coloured
+   celestial sphere r = r_escape of Sect. 4.1: with sky set, the crossing of
+   the sphere is located exactly (theta_f, phi_f are its coordinates) and
+   classified into KT_SKY_* codes: four quadrants and a graticule of lines
+   every grid_deg degrees (0: none) of half-width line_deg. */
 typedef struct kt_source {
     int32_t enabled;
     double r_src;
+    int32_t sky;
+    double grid_deg, line_deg;
 } kt_source;
+
+/* celestial-sphere codes (uint8 per pixel) */
+#define KT_SKY_NONE 0    /* did not reach the sphere (captured, disk, failed) */
+#define KT_SKY_GREEN 1   /* 0 <= theta < pi/2, 0 <= phi < pi */
+#define KT_SKY_RED 2     /* 0 <= theta < pi/2, pi <= phi < 2 pi */
+#define KT_SKY_BLUE 3    /* pi/2 <= theta <= pi, 0 <= phi < pi */
+#define KT_SKY_YELLOW 4  /* pi/2 <= theta <= pi, pi <= phi < 2 pi */
+#define KT_SKY_LINE 5    /* on a graticule line */
 
 typedef struct kt_integrator {
     int32_t method;         /* KT_RK4_S, KT_DP45, KT_RKF45, KT_CK45 or KT_BS */
@@ -143,6 +167,8 @@ typedef struct kt_outputs {
                             deflection and its +i or +j neighbour's */
     int32_t *n_steps;    /* accepted steps */
     int32_t *n_evals;    /* RHS evaluations */
+    uint8_t *sky;        /* KT_SKY_* code (KT_SKY_NONE where the source's sky is off);
+                            needs theta_f and phi_f */
     kt_stats *stats;     /* may be NULL */
 } kt_outputs;
 

@@ -53,7 +53,7 @@ int validate_common(const kt_camera* cam, const kt_spacetime* st) {
     if (!cam || !st) return fail(KT_EINVAL, "camera and spacetime must not be NULL");
     if (!finite_all({cam->r_obs, cam->incl, cam->fov_x, cam->fov_y, st->M, st->a}))
         return fail(KT_EINVAL, "non-finite camera or spacetime parameter");
-    if (!(st->M > 0.0)) return fail(KT_EINVAL, "M must be > 0 (got %g)", st->M);
+    if (!(st->M >= 0.0)) return fail(KT_EINVAL, "M must be >= 0 (got %g)", st->M);
     if (st->a * st->a > st->M * st->M) return fail(KT_EINVAL, "|a| must be <= M (a=%g, M=%g)", st->a, st->M);
     if (!(cam->incl > 0.0 && cam->incl < M_PI))
         return fail(KT_EINVAL, "incl must lie in (0, pi) (got %g)", cam->incl);
@@ -138,10 +138,16 @@ int make_image(const kt_camera* camera, const kt_spacetime* spacetime, const kt_
             return fail(KT_EINVAL, "non-finite disk parameter");
         if (!(disk->r_in > r_plus && disk->r_out > disk->r_in))
             return fail(KT_EINVAL, "disk needs r_+ < r_in < r_out");
+        if (disk->rotation != KT_ROT_KEPLER && disk->rotation != KT_ROT_L0)
+            return fail(KT_EINVAL, "unknown disk rotation %d", disk->rotation);
+        if (disk->rotation == KT_ROT_L0 && !std::isfinite(disk->l0))
+            return fail(KT_EINVAL, "l0 must be finite");
         im.disk_on = 1;
         im.r_in = disk->r_in;
         im.r_out = disk->r_out;
         im.emis_q = disk->emis_index;
+        im.rotation = disk->rotation;
+        im.l0 = disk->l0;
     }
     const bool src_on = source && source->enabled;
     if (src_on) {
@@ -157,6 +163,15 @@ int make_image(const kt_camera* camera, const kt_spacetime* spacetime, const kt_
         im.src_n[2] = std::cos(ts);
     }
     if (want_ring && !src_on) return fail(KT_EINVAL, "ring needs an enabled source and a deflection output");
+    if (source && source->sky) {
+        if (!finite_all({source->grid_deg, source->line_deg}) || !(source->grid_deg >= 0.0) ||
+            !(source->line_deg >= 0.0))
+            return fail(KT_EINVAL, "sky needs finite grid_deg >= 0 and line_deg >= 0");
+        im.sky_on = 1;
+        im.esc_tol = 1e-12 * r_esc;
+        im.grid_deg = source->grid_deg;
+        im.line_deg = source->line_deg;
+    }
     return KT_OK;
 }
 
@@ -215,6 +230,7 @@ int render_images(const std::vector<kt::Image>& table, int64_t n_rays, const kt_
     p.out.ring = out->ring;
     p.out.n_steps = out->n_steps;
     p.out.n_evals = out->n_evals;
+    p.out.sky = out->sky;
     p.out.stats = out->stats;
     char* ws = static_cast<char*>(workspace);
     p.ticket = reinterpret_cast<uint32_t*>(ws + kt::WS_TICKET);
@@ -260,6 +276,8 @@ int render_images(const std::vector<kt::Image>& table, int64_t n_rays, const kt_
         return fail(KT_EDEVICE, "disk observables launch failed: %s", hipGetErrorString(hipGetLastError()));
     if (out->ring && kt::launch_ring(p, hip_stream))
         return fail(KT_EDEVICE, "ring kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+    if (out->sky && kt::launch_sky(p, hip_stream))
+        return fail(KT_EDEVICE, "sky kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
     if (out->stats && kt::launch_stats(p, hip_stream))
         return fail(KT_EDEVICE, "stats kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
     return KT_OK;
@@ -269,6 +287,8 @@ int validate_outputs(const kt_outputs* out) {
     if (!out->fate) return fail(KT_EINVAL, "out->fate must not be NULL");
     if (out->ring && !out->deflection)
         return fail(KT_EINVAL, "ring needs an enabled source and a deflection output");
+    if (out->sky && !(out->theta_f && out->phi_f))
+        return fail(KT_EINVAL, "sky needs the theta_f and phi_f outputs");
     return KT_OK;
 }
 

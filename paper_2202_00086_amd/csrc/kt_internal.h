@@ -15,6 +15,7 @@ struct Outputs {
     double *r_hit, *g, *intensity, *max_abs_h, *max_rel_h, *psi, *deflection, *theta_f, *phi_f;
     uint8_t *n_cross, *used_fp64, *ring;
     int32_t *n_steps, *n_evals;
+    uint8_t* sky;
     kt_stats* stats;
 };
 
@@ -34,12 +35,15 @@ struct Image {
     int32_t nx, ny;
     int64_t first;  // ray id of pixel 0 (outputs of this image start here)
     // disk (Sect. 5)
-    int32_t disk_on;
-    double r_in, r_out, emis_q;
+    int32_t disk_on, rotation;
+    double r_in, r_out, emis_q, l0;
     // source for the deflection diagnostics
     int32_t src_on;
     double r_src, src_tol;
     double src_n[3];  // unit vector towards the source
+    // celestial sphere at r_esc (Sect. 4.1)
+    int32_t sky_on;
+    double esc_tol, grid_deg, line_deg;
 };
 
 // Everything a render needs, copied into the workspace by ws_init.
@@ -96,6 +100,12 @@ inline WsLayout ws_layout(size_t n_rays, size_t n_images, bool batch, bool mixed
     return w;
 }
 
+enum : int32_t { FEAT_DISK = 1, FEAT_SRC = 2, FEAT_SKY = 4 };
+
+constexpr int32_t image_features(const Image& im) {
+    return (im.disk_on ? FEAT_DISK : 0) | (im.src_on ? FEAT_SRC : 0) | (im.sky_on ? FEAT_SKY : 0);
+}
+
 // The values the trace kernel's inner loop reads every step, passed by value
 // so they sit in scalar registers; everything else is read through `cold`.
 // For batch renders the per-image ones become per-lane values.
@@ -103,7 +113,7 @@ struct Hot {
     double M, a, a2, two_a2;
     double rtol, atol, r_cap, r_esc, r_src, r_in, r_out;
     double h_budget, r_switch;  // KT_MIXED
-    int32_t disk_on, src_on;
+    int32_t feat;               // FEAT_* bits of the image's disk, source and sky
     int32_t max_steps, max_evals;
     const Params* cold;         // the workspace copy of Params
 };
@@ -116,6 +126,7 @@ int launch_fallback_list(const Params& p, void* stream);  // compact need_fb, sw
 int launch_trace_fallback(const Params& p, int grid, int block, void* stream);  // FP64 re-run from the list
 int launch_reset_ticket(const Params& p, void* stream);
 int launch_ring(const Params& p, void* stream);
+int launch_sky(const Params& p, void* stream);  // needs theta_f and phi_f outputs
 int launch_disk_obs(const Params& p, void* stream);
 int launch_stats(const Params& p, void* stream);
 int launch_init_rays(const Params& p, double* state, uint8_t* invalid, void* stream);

@@ -55,6 +55,30 @@ __device__ __forceinline__ double arc_angle_short(double s1, double c1, double s
     return h <= 0.0625 ? 2.0 * asin_small(h) : -1.0;
 }
 
+// Celestial-sphere code of the direction (theta, phi) (Sect. 4.1).  theta is
+// folded into [0, pi] (past the polar axis a ray continues on the meridian
+// phi + pi) and phi into [0, 2 pi); then the graticule test (distance to the
+// nearest multiple of grid_deg in either angle) and the quadrant.
+__device__ __forceinline__ uint8_t sky_code(double th, double ph, double grid_deg, double line_deg) {
+    constexpr double PI = 3.14159265358979323846, TWO_PI = 6.28318530717958647692;
+    constexpr double DEG = 180.0 / PI;
+    double t = th - TWO_PI * floor(th * (1.0 / TWO_PI));
+    if (t > PI) {
+        t = TWO_PI - t;
+        ph += PI;
+    }
+    double p = ph - TWO_PI * floor(ph * (1.0 / TWO_PI));
+    if (p >= TWO_PI) p -= TWO_PI;
+    if (grid_deg > 0.0) {
+        const double td = t * DEG, pd = p * DEG;
+        const double dt = fabs(td - grid_deg * rint(td / grid_deg));
+        const double dp = fabs(pd - grid_deg * rint(pd / grid_deg));
+        if (dt <= line_deg || dp <= line_deg) return KT_SKY_LINE;
+    }
+    if (t < HALF_PI) return p < PI ? KT_SKY_GREEN : KT_SKY_RED;
+    return p < PI ? KT_SKY_BLUE : KT_SKY_YELLOW;
+}
+
 // Initial state of pixel `pix` of image `im` (second eq:momentums with p_r
 // ingoing).  Returns false when x^2 + y^2 >= r0^2 (no real p_r).
 __device__ __forceinline__ bool camera_state(const Image& im, int32_t pix, double z[5], double* E,
@@ -98,8 +122,8 @@ __device__ __forceinline__ int find_image(const Params& P, int64_t ray) {
 struct LaneImg {
     Spacetime st;
     double r_cap, r_esc, r_src, r_in, r_out;
-    int32_t disk_on, src_on;
-    int32_t k;  // image index
+    int32_t feat;  // FEAT_* bits
+    int32_t k;     // image index
 };
 
 __device__ __forceinline__ LaneImg lane_img(const Image& im, int k) {
@@ -110,8 +134,7 @@ __device__ __forceinline__ LaneImg lane_img(const Image& im, int k) {
     li.r_src = im.r_src;
     li.r_in = im.r_in;
     li.r_out = im.r_out;
-    li.disk_on = im.disk_on;
-    li.src_on = im.src_on;
+    li.feat = image_features(im);
     li.k = k;
     return li;
 }
@@ -125,8 +148,9 @@ enum : int {
     F_RETAKE = 1 << 4,    // re-taking an accepted step after locating an event in it
     F_SKIPDISK = 1 << 5,  // disk crossing of the re-taken step already handled
     F_SRCDONE = 1 << 6,   // source sphere crossed
-    F_EVSRC = 1 << 7,     // event being located: 0 disk plane, 1 source sphere
+    F_EVSRC = 1 << 7,     // event being located is the source sphere
     F_USED32 = 1 << 24,   // mixed pass: some step used the FP32 mass part
+    F_EVESC = 1 << 25,    // event being located is the celestial sphere
 };
 constexpr int NCROSS_SHIFT = 8;   // 8 bits: equatorial crossings outside the disk
 constexpr int EVIT_SHIFT = 16;    // 8 bits: trial steps of the current event
@@ -218,8 +242,7 @@ trace_kernel(const Hot hp) {
     li.r_src = hp.r_src;
     li.r_in = hp.r_in;
     li.r_out = hp.r_out;
-    li.disk_on = hp.disk_on;
-    li.src_on = hp.src_on;
+    li.feat = hp.feat;
     li.k = 0;
     const uint32_t lane = __lane_id();
     const uint32_t n_total = P.from_list ? *P.fb_count : static_cast<uint32_t>(P.n_rays);
@@ -336,11 +359,18 @@ trace_kernel(const Hot hp) {
             if (locating) {
                 // Illinois regula falsi on the event function
                 const bool src = (fl & F_EVSRC) != 0;
-                const double fc = src ? yn[0] - li.r_src : yn[1] - HALF_PI;
-                const double tol = src ? (BATCH ? P.images[li.k].src_tol : P.img0.src_tol) : 1e-14;
+                const bool esc = (fl & F_EVESC) != 0;
+                const Image& im = BATCH ? P.images[li.k] : P.img0;
+                const double fc = esc ? yn[0] - li.r_esc : src ? yn[0] - li.r_src : yn[1] - HALF_PI;
+                const double tol = esc ? im.esc_tol : src ? im.src_tol : 1e-14;
                 const int it = ((fl >> EVIT_SHIFT) & 0xff) + 1;
                 fl = (fl & ~(0xff << EVIT_SHIFT)) | (it << EVIT_SHIFT);
-                if (fabs(fc) <= tol || it >= 64) {
+                if ((fabs(fc) <= tol || it >= 64) && esc) {
+                    // the ray meets the celestial sphere here
+                    fate = KT_FATE_ESCAPED;
+                    thf = yn[1];
+                    phf = yn[2];
+                } else if (fabs(fc) <= tol || it >= 64) {
                     if (!src) {
                         if (yn[0] >= li.r_in && yn[0] <= li.r_out) {
                             fate = KT_FATE_DISK;
@@ -355,7 +385,7 @@ trace_kernel(const Hot hp) {
                         defl = COLD(C_PSI) + arc_angle(s0, c0, dg.s, dg.c, yn[2] - y[2]);
                         double sp, cp;
                         sincos_fast(yn[2], &sp, &cp);
-                        const double* sn = BATCH ? P.images[li.k].src_n : P.img0.src_n;
+                        const double* sn = im.src_n;
                         const double nx = dg.s * cp, ny = dg.s * sp, nz = dg.c;
                         const double cx = ny * sn[2] - nz * sn[1];
                         const double cy = nz * sn[0] - nx * sn[2];
@@ -423,7 +453,7 @@ trace_kernel(const Hot hp) {
                     fl &= ~F_RETAKE;
                     bool locate = false;
                     // thin disk: sign change of theta - pi/2 over the step
-                    if (li.disk_on && !(fl & F_SKIPDISK)) {
+                    if ((li.feat & FEAT_DISK) && !(fl & F_SKIPDISK)) {
                         const double ga = y[1] - HALF_PI, gb = yn[1] - HALF_PI;
                         if (ga * gb < 0.0) {
                             fl = (fl & ~(F_EVSRC | (0xff << EVIT_SHIFT))) | F_LOCATE;
@@ -451,7 +481,7 @@ trace_kernel(const Hot hp) {
                             thf = yn[1];
                             phf = yn[2];
                         } else {
-                            if (li.src_on && !(fl & F_SRCDONE)) {
+                            if ((li.feat & FEAT_SRC) && !(fl & F_SRCDONE)) {
                                 if (y[0] < li.r_src && yn[0] >= li.r_src) {
                                     const double fa = y[0] - li.r_src, fb = yn[0] - li.r_src;
                                     fl = (fl & ~(0xff << EVIT_SHIFT)) | F_EVSRC | F_LOCATE;
@@ -469,7 +499,16 @@ trace_kernel(const Hot hp) {
                                 }
                             }
                             if (!locate) {
-                                if (yn[0] > li.r_esc) {
+                                if (yn[0] > li.r_esc && (li.feat & FEAT_SKY)) {
+                                    // locate the crossing of the celestial sphere
+                                    const double fa = y[0] - li.r_esc, fb = yn[0] - li.r_esc;
+                                    fl = (fl & ~(F_EVSRC | (0xff << EVIT_SHIFT))) | F_EVESC | F_LOCATE;
+                                    COLD(C_EVA) = 0.0;
+                                    COLD(C_EVFA) = fa;
+                                    COLD(C_EVB) = h;
+                                    COLD(C_EVFB) = fb;
+                                    COLD(C_EVC) = h - fb * h / (fb - fa);
+                                } else if (yn[0] > li.r_esc) {
                                     fate = KT_FATE_ESCAPED;
                                     thf = yn[1];
                                     phf = yn[2];
@@ -570,9 +609,10 @@ __global__ void to_fallback_kernel(Params* wp) {
     }
 }
 
-// Keplerian redshift and observed intensity of every disk pixel from the
-// crossing radius the trace kernel parked in rc_buf (eq:redshift read as
+// Redshift and observed intensity of every disk pixel from the crossing
+// radius the trace kernel parked in rc_buf (eq:redshift read as
 // g = 1 / (u^t (E - Omega L)); I_obs = g^3 I_em with I_em = (M/r)^q).
+// Omega is Keplerian or from the constant specific angular momentum l0.
 __global__ void disk_obs_kernel(const Params* pp) {
     const Params& p = *pp;
     const int64_t n = p.n_rays;
@@ -585,16 +625,23 @@ __global__ void disk_obs_kernel(const Params* pp) {
             double z[5], E, L;
             camera_state(im, static_cast<int32_t>(k - im.first), z, &E, &L);
             const double rc = p.rc_buf[k];
-            const double sM = sqrt(im.M);
-            const double Om = sM / fma(rc, sqrt(rc), im.a * sM);
             const double inv_rc = 1.0 / rc;
             const double gtt = -(1.0 - 2.0 * im.M * inv_rc);
             const double gtp = -2.0 * im.M * im.a * inv_rc;
             const double gpp = rc * rc + im.a2 + 2.0 * im.M * im.a2 * inv_rc;
+            double Om;
+            if (im.rotation == KT_ROT_L0) {
+                Om = -(gtp + im.l0 * gtt) / (gpp + im.l0 * gtp);
+            } else {
+                const double sM = sqrt(im.M);
+                Om = sM / fma(rc, sqrt(rc), im.a * sM);
+            }
             const double norm = -gtt - 2.0 * Om * gtp - Om * Om * gpp;  // (u^t)^-2
             r_hit = rc;
-            g = sqrt(norm) / (E - Om * L);
-            inten = g * g * g * pow(im.M * inv_rc, im.emis_q);
+            if (norm > 0.0) {
+                g = sqrt(norm) / (E - Om * L);
+                inten = g * g * g * pow(im.M * inv_rc, im.emis_q);
+            }
         }
         if (p.out.r_hit) p.out.r_hit[k] = r_hit;
         if (p.out.g) p.out.g[k] = g;
@@ -662,6 +709,21 @@ __global__ void ring_kernel(const Params* pp) {
             if (j + 1 < im.ny && isfinite(defl[p + nx]) && odd_pi_count(defl[p + nx]) != k) flag = 1;
         }
         ring[p] = flag;
+    }
+}
+
+// Celestial-sphere codes from the located crossings (theta_f, phi_f).
+__global__ void sky_kernel(const Params* pp) {
+    const Params& P = *pp;
+    const int64_t n = P.n_rays;
+    for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < n;
+         k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        uint8_t code = KT_SKY_NONE;
+        if (P.out.fate[k] == KT_FATE_ESCAPED) {
+            const Image& im = P.images[find_image(P, k)];
+            if (im.sky_on) code = sky_code(P.out.theta_f[k], P.out.phi_f[k], im.grid_deg, im.line_deg);
+        }
+        P.out.sky[k] = code;
     }
 }
 
@@ -751,8 +813,7 @@ static Hot make_hot(const Params& p) {
     hp.r_out = im.r_out;
     hp.h_budget = p.h_budget;
     hp.r_switch = p.r_switch;
-    hp.disk_on = im.disk_on;
-    hp.src_on = im.src_on;
+    hp.feat = image_features(im);
     hp.max_steps = static_cast<int32_t>(p.max_steps);
     hp.max_evals = static_cast<int32_t>(p.max_evals);
     hp.cold = p.ws_params;
@@ -831,6 +892,12 @@ int launch_disk_obs(const Params& p, void* stream) {
 
 int launch_ring(const Params& p, void* stream) {
     hipLaunchKernelGGL(ring_kernel, dim3(small_grid(p.n_rays, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), p.ws_params);
+    return check_launch();
+}
+
+int launch_sky(const Params& p, void* stream) {
+    hipLaunchKernelGGL(sky_kernel, dim3(small_grid(p.n_rays, 256)), dim3(256), 0,
                        static_cast<hipStream_t>(stream), p.ws_params);
     return check_launch();
 }

@@ -42,11 +42,12 @@ class kt_spacetime(C.Structure):
 
 class kt_disk(C.Structure):
     _fields_ = [("enabled", C.c_int32), ("r_in", C.c_double), ("r_out", C.c_double),
-                ("emis_index", C.c_double)]
+                ("emis_index", C.c_double), ("rotation", C.c_int32), ("l0", C.c_double)]
 
 
 class kt_source(C.Structure):
-    _fields_ = [("enabled", C.c_int32), ("r_src", C.c_double)]
+    _fields_ = [("enabled", C.c_int32), ("r_src", C.c_double), ("sky", C.c_int32),
+                ("grid_deg", C.c_double), ("line_deg", C.c_double)]
 
 
 class kt_image(C.Structure):
@@ -75,7 +76,9 @@ class kt_stats(C.Structure):
 
 
 OUTPUT_FIELDS = ("fate", "r_hit", "g", "intensity", "max_abs_h", "max_rel_h", "psi", "deflection",
-                 "theta_f", "phi_f", "n_cross", "used_fp64", "ring", "n_steps", "n_evals")
+                 "theta_f", "phi_f", "n_cross", "used_fp64", "ring", "n_steps", "n_evals", "sky")
+KEPLER, L0 = 0, 1
+SKY_NONE, SKY_GREEN, SKY_RED, SKY_BLUE, SKY_YELLOW, SKY_LINE = range(6)
 
 
 class kt_outputs(C.Structure):
@@ -179,19 +182,19 @@ def kt_init_rays(camera, spacetime, state_ptr, invalid_ptr, stream_ptr):
 def make_structs(M=1.0, a=0.0, r_obs=1000.0, incl=math.pi / 2, fov_x=10.0, fov_y=10.0, nx=64,
                  ny=64, method=DP45, precision=FP64, h_fixed=1.0 / 128, rtol=1e-12, atol=1e-12,
                  h_init=1.0, cap_buffer=0.01, r_escape=0.0, h_budget=1e-10, r_switch=300.0,
-                 max_steps=1_000_000, disk_on=0, r_in=6.0, r_out=30.0, emis_q=2.0, src_on=0,
-                 r_src=1000.0):
+                 max_steps=1_000_000, disk_on=0, r_in=6.0, r_out=30.0, emis_q=2.0, rotation=0, l0=0.0,
+                 src_on=0, r_src=1000.0, sky_on=0, grid_deg=6.0, line_deg=0.25):
     """C structs from keyword parameters (the same names the workloads use)."""
     cam = kt_camera(r_obs, incl, fov_x, fov_y, nx, ny)
     st = kt_spacetime(M, a)
     integ = kt_integrator(method, precision, h_fixed, rtol, atol, h_init, cap_buffer, r_escape,
                           h_budget, r_switch, int(max_steps))
-    disk = kt_disk(int(disk_on), r_in, r_out, emis_q)
-    src = kt_source(int(src_on), r_src)
+    disk = kt_disk(int(disk_on), r_in, r_out, emis_q, int(rotation), l0)
+    src = kt_source(int(src_on), r_src, int(sky_on), grid_deg, line_deg)
     return cam, st, disk, src, integ
 
 
-_DTYPES = {"fate": "uint8", "n_cross": "uint8", "used_fp64": "uint8", "ring": "uint8",
+_DTYPES = {"fate": "uint8", "n_cross": "uint8", "used_fp64": "uint8", "ring": "uint8", "sky": "uint8",
            "n_steps": "int32", "n_evals": "int32"}
 
 
@@ -234,6 +237,8 @@ class Renderer:
         self.want = tuple(want)
         if "ring" in self.want and not self.src.enabled:
             self.want = tuple(w for w in self.want if w != "ring")
+        if "sky" in self.want:
+            self.want = tuple(dict.fromkeys(self.want + ("theta_f", "phi_f")))
         self.out = alloc_outputs(self.n, self.device, self.want, stats)
         self.ws_bytes = kt_workspace_bytes(self.cam, self.integ)
         if self.ws_bytes == 0:
@@ -256,7 +261,7 @@ class Renderer:
 
 
 _IMAGE_KEYS = ("M", "a", "r_obs", "incl", "fov_x", "fov_y", "nx", "ny", "disk_on", "r_in", "r_out",
-               "emis_q", "src_on", "r_src")
+               "emis_q", "rotation", "l0", "src_on", "r_src", "sky_on", "grid_deg", "line_deg")
 
 
 def split_params(params):
@@ -294,6 +299,8 @@ class BatchRenderer:
         self.want = tuple(want)
         if "ring" in self.want and not all(im.source.enabled for im in self.table):
             self.want = tuple(w for w in self.want if w != "ring")
+        if "sky" in self.want:
+            self.want = tuple(dict.fromkeys(self.want + ("theta_f", "phi_f")))
         self.out = alloc_outputs(self.n, self.device, self.want, stats)
         self.ws_bytes = kt_workspace_bytes_batch(self.table, self.integ)
         if self.ws_bytes == 0:

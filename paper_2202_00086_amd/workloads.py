@@ -14,6 +14,8 @@ the CPU oracle (oracle.Setup) accept these keyword names.
                             +-35M, thin Keplerian disk 6M..30M, I_em ~ r^-2.
   hamiltonian_norm_map      a = 0.98, 625x625, r_obs = 100M, i = 90 deg, +-8M
                             (the integrator comparison grid).
+  lensing(a)                celestial-sphere lensing, r_obs = 100M, i = 90 deg.
+  thin_disk_l0(a)           the Sect. 5 disk images with constant-l0 rotation.
   heterogeneous_batch       256 seeded Kerr disk images: sides 64..1024 in
                             steps of 64, a ~ U[0, 0.998], i ~ U[5, 85] deg,
                             r_obs log-uniform in [100, 1e4]M, +-35M, disk
@@ -58,6 +60,27 @@ def hamiltonian_norm_map(n=625, method=1, rtol=1e-12):
                 max_steps=1_000_000)
 
 
+def lensing(a=0.98, n=512, M=1.0, fov=20.0, rtol=1e-12):
+    """Gravitational lensing of the coloured celestial sphere (Sect. 4.1-4.2):
+    observer in the equatorial plane at r0 = 100M, phi0 = 0; sphere at
+    r_cs = 1.1 r0; graticule every 6 deg (lines 0.25 deg wide on either
+    side).  M = 0 (a = 0) is the flat reference image."""
+    return dict(M=M, a=a, r_obs=100.0, incl=math.pi / 2, fov_x=fov, fov_y=fov, nx=n, ny=n, method=1,
+                rtol=rtol, atol=rtol, h_init=1.0, cap_buffer=0.01, r_escape=110.0, max_steps=1_000_000,
+                sky_on=1, grid_deg=6.0, line_deg=0.25)
+
+
+def thin_disk_l0(a=0.5, nx=2048, ny=1024, rtol=1e-12):
+    """The thin-disk images of Sect. 5: r0 = 1000M, i = 85 deg, x in [-24, 24],
+    y in [-12, 12], disk from the ISCO to 20M rotating with constant specific
+    angular momentum l0 = 2.8 (a = 0, 0.5) or 1.8 (a = 0.95); I_em ~ r^-2
+    stands in for the Page-Thorne model."""
+    return dict(M=1.0, a=a, r_obs=1000.0, incl=math.radians(85.0), fov_x=24.0, fov_y=12.0, nx=nx, ny=ny,
+                method=1, rtol=rtol, atol=rtol, h_init=1.0, cap_buffer=0.01, r_escape=1100.0,
+                max_steps=1_000_000, disk_on=1, r_in=isco(a), r_out=20.0, emis_q=2.0, rotation=1,
+                l0=1.8 if a > 0.9 else 2.8)
+
+
 def isco(a, M=1.0):
     """Radius of the innermost stable circular orbit of Kerr for orbits
     moving in +phi (prograde for a > 0, retrograde for a < 0), from the
@@ -72,7 +95,7 @@ def isco(a, M=1.0):
 
 # keys that describe one image; everything else is the shared integrator
 IMAGE_KEYS = ("M", "a", "r_obs", "incl", "fov_x", "fov_y", "nx", "ny", "disk_on", "r_in", "r_out",
-              "emis_q", "src_on", "r_src")
+              "emis_q", "rotation", "l0", "src_on", "r_src", "sky_on", "grid_deg", "line_deg")
 
 
 def heterogeneous_batch(n_images=256, seed=20220201, side_unit=64, side_steps=16, fov=35.0, rtol=1e-12):

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared_functions():
         assert hasattr(lib, name), name
     assert set(K.EXPORTED) == set(_declared_functions())
-    assert K.kt_version() == 110
+    assert K.kt_version() == 120
 
 
 def test_struct_layouts_match_header():
@@ -49,13 +49,13 @@ def test_struct_layouts_match_header():
     from paper_2202_00086_amd import kerrtrace as K
     assert C.sizeof(K.kt_camera) == 4 * 8 + 2 * 4
     assert C.sizeof(K.kt_spacetime) == 16
-    assert C.sizeof(K.kt_disk) == 32
-    assert C.sizeof(K.kt_source) == 16
+    assert C.sizeof(K.kt_disk) == 48
+    assert C.sizeof(K.kt_source) == 40
     assert C.sizeof(K.kt_integrator) == 8 + 8 * 8 + 8
     assert C.sizeof(K.kt_launch) == 16
     assert C.sizeof(K.kt_stats) == 12 * 8
-    assert C.sizeof(K.kt_outputs) == 16 * 8
-    assert C.sizeof(K.kt_image) == 40 + 16 + 32 + 16
+    assert C.sizeof(K.kt_outputs) == 17 * 8
+    assert C.sizeof(K.kt_image) == 40 + 16 + 48 + 40
 
 
 def _args(**kw):
@@ -66,7 +66,7 @@ def _args(**kw):
 
 BAD = [
     dict(a=1.2),
-    dict(M=0.0),
+    dict(M=0.0, a=0.1),
     dict(M=-1.0),
     dict(r_obs=1.5, a=0.0),
     dict(nx=0),
@@ -85,6 +85,10 @@ BAD = [
     dict(disk_on=1, r_in=10.0, r_out=5.0),
     dict(r_escape=500.0),                            # inside the observer
     dict(src_on=1, r_src=1.0),
+    dict(disk_on=1, rotation=2),
+    dict(disk_on=1, rotation=1, l0=float("nan")),
+    dict(sky_on=1, grid_deg=-6.0),
+    dict(sky_on=1, line_deg=float("inf")),
 ]
 
 
@@ -129,6 +133,16 @@ def test_ring_needs_source_and_deflection():
     out.fate = 0x1000
     out.ring = 0x2000
     assert K.kt_render(cam, st, disk, src, integ, out, C.c_void_p(0x100000), 1 << 30, None) == K.KT_EINVAL
+
+
+@no_gpu_only
+def test_sky_needs_final_angles():
+    K, cam, st, disk, src, integ = _args(sky_on=1)
+    out = K.kt_outputs()
+    out.fate = 0x1000
+    out.sky = 0x2000
+    assert K.kt_render(cam, st, disk, src, integ, out, C.c_void_p(0x100000), 1 << 30, None) == K.KT_EINVAL
+    assert "theta_f" in K.kt_last_error()
 
 
 @no_gpu_only
