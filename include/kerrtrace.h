@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define KT_VERSION_NUMBER 120
+#define KT_VERSION_NUMBER 130
 
 /* return codes */
 #define KT_OK 0
@@ -88,11 +88,17 @@ typedef struct kt_spacetime {
    intensity 0. */
 #define KT_ROT_KEPLER 0
 #define KT_ROT_L0 1
+/* emissivity models */
+#define KT_EMIS_POWER 0     /* I_em = (M/r)^emis_index */
+#define KT_EMIS_TAPERED 1   /* I_em = (M/r)^2 (1 - sqrt(r_in/r)), times 3s^2 - 2s^3 with
+                               s = (r_out - r)/(2M) on [r_out - 2M, r_out]: continuous in
+                               r_in and r_out, so the image is differentiable in r_in */
 typedef struct kt_disk {
     int32_t enabled;
     double r_in, r_out, emis_index;
     int32_t rotation;       /* KT_ROT_KEPLER or KT_ROT_L0 */
     double l0;              /* specific angular momentum for KT_ROT_L0 */
+    int32_t emissivity;     /* KT_EMIS_POWER or KT_EMIS_TAPERED */
 } kt_disk;
 
 /* Light sources.  A point source at (r_src, pi - incl, pi), behind the hole:
@@ -247,6 +253,32 @@ int kt_autotune_batch(int32_t n_images, const kt_image *images, const kt_integra
                       const kt_outputs *out, void *workspace, size_t workspace_bytes,
                       void *hip_stream, const kt_launch *candidates, int32_t n_candidates,
                       int32_t repeats, kt_launch *best, float *times_ms);
+
+/* Gradient of a disk image with respect to the spin a, the inclination and
+   the disk's inner radius r_in: the discrete adjoint of the rendered
+   intensity (Sect. 5 observables, eq:redshift) through the Dormand-Prince
+   integration with its accepted step sizes frozen.  For each pixel with
+   fate KT_FATE_DISK and cot_intensity != 0 it writes
+   cot_intensity * dI/d(a, incl, r_in) to grad_a, grad_incl, grad_r_in
+   (device, nx*ny doubles each, any may be NULL; 0 elsewhere); a loss's
+   gradient is their sum with cot_intensity = dLoss/dI.
+   Inputs: the same camera, spacetime, disk and integrator as the forward
+   kt_render (method KT_DP45, KT_FP64, disk enabled), and that render's fate
+   and (optional, for a bit-identity check) r_hit arrays.  Each ray is
+   re-integrated with the forward's own arithmetic, checkpointed every 64
+   accepted steps, and swept backward segment by segment.
+   stats (device, 4 uint64, may be NULL): rays differentiated, rays that
+   failed, rays beyond the checkpoint capacity (256 x 64 steps), rays whose
+   re-integration did not reproduce r_hit; the last three get zero gradient.
+   workspace: kt_adjoint_workspace_bytes() bytes, 256-byte aligned.
+   Returns KT_OK, KT_EINVAL, KT_ENOMEM or KT_EDEVICE. */
+int kt_adjoint(const kt_camera *camera, const kt_spacetime *spacetime, const kt_disk *disk,
+               const kt_integrator *integ, const uint8_t *fate, const double *r_hit,
+               const double *cot_intensity, double *grad_a, double *grad_incl, double *grad_r_in,
+               uint64_t *stats, void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/* Workspace size of kt_adjoint for this camera and integrator (0 on bad input). */
+size_t kt_adjoint_workspace_bytes(const kt_camera *camera, const kt_integrator *integ);
 
 /* Initial state of every pixel (Sect. 2.3), for checking the camera alone:
    state is a device array of 7*nx*ny doubles laid out SoA as

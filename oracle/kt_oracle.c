@@ -561,6 +561,17 @@ int ko_sky_code(double theta, double phi, double grid_deg, double line_deg)
     return ph < PI ? KO_SKY_BLUE : KO_SKY_YELLOW;
 }
 
+double ko_emissivity(double M, double r, double r_in, double r_out, double emis_q, int32_t model)
+{
+    if (model == 1) {
+        double e = (M / r) * (M / r) * (1.0 - sqrt(r_in / r));
+        double s = (r_out - r) / (2.0 * M);
+        if (s < 1.0) e *= s * s * (3.0 - 2.0 * s);
+        return e;
+    }
+    return pow(M / r, emis_q);
+}
+
 double ko_disk_omega(double M, double a, double r, int32_t rotation, double l0)
 {
     if (rotation == 1) {
@@ -701,7 +712,8 @@ static int64_t trace_ray(const ko_setup *s, double x, double y, const ko_out *o,
                         if (norm > 0.0) {
                             double ut = 1.0 / sqrt(norm);
                             gred = 1.0 / (ut * (E - Om * L));
-                            inten = gred * gred * gred * pow(s->M / rc, s->emis_q);
+                            inten = gred * gred * gred *
+                                    ko_emissivity(s->M, rc, s->r_in, s->r_out, s->emis_q, s->emis_model);
                         } /* else: no timelike circular orbit there; g stays NaN */
                         r_hit = rc;
                         fate = KO_DISK;

@@ -60,6 +60,9 @@ typedef struct {
     double r_in, r_out, emis_q;
     int32_t rotation;
     double l0;
+    /* emissivity: 0 (M/r)^emis_q; 1 (M/r)^2 (1 - sqrt(r_in/r)) tapered to 0
+       over [r_out - 2M, r_out] by the smoothstep 3s^2 - 2s^3 */
+    int32_t emis_model;
     /* point source for the deflection diagnostics */
     int32_t src_on;
     double r_src;
@@ -148,6 +151,9 @@ int ko_sky_code(double theta, double phi, double grid_deg, double line_deg);
 /* Angular velocity Omega = u^phi / u^t of the disk's circular orbits at
    radius r in the equatorial plane for the given rotation model. */
 double ko_disk_omega(double M, double a, double r, int32_t rotation, double l0);
+
+/* Emitted intensity at radius r of the disk for the given model. */
+double ko_emissivity(double M, double r, double r_in, double r_out, double emis_q, int32_t model);
 
 /* Outer horizon r_+ = M + sqrt(M^2 - a^2). */
 double ko_horizon(double M, double a);

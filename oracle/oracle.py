@@ -33,7 +33,7 @@ class _Setup(C.Structure):
         ("cap_buffer", C.c_double), ("r_escape", C.c_double),
         ("max_steps", C.c_int64),
         ("disk_on", C.c_int32), ("r_in", C.c_double), ("r_out", C.c_double), ("emis_q", C.c_double),
-        ("rotation", C.c_int32), ("l0", C.c_double),
+        ("rotation", C.c_int32), ("l0", C.c_double), ("emis_model", C.c_int32),
         ("src_on", C.c_int32), ("r_src", C.c_double),
         ("sky_on", C.c_int32), ("grid_deg", C.c_double), ("line_deg", C.c_double),
     ]
@@ -81,6 +81,7 @@ class Setup:
     emis_q: float = 2.0
     rotation: int = 0              # 0 Keplerian, 1 constant l0
     l0: float = 0.0
+    emis_model: int = 0            # 0 (M/r)^emis_q, 1 tapered (M/r)^2 (1 - sqrt(r_in/r))
     src_on: int = 0
     r_src: float = 1000.0
     sky_on: int = 0
@@ -134,6 +135,8 @@ def lib():
         L.ko_sky_code.restype = C.c_int
         L.ko_disk_omega.argtypes = [C.c_double] * 3 + [C.c_int32, C.c_double]
         L.ko_disk_omega.restype = C.c_double
+        L.ko_emissivity.argtypes = [C.c_double] * 5 + [C.c_int32]
+        L.ko_emissivity.restype = C.c_double
         _lib = L
     return _lib
 
@@ -245,6 +248,10 @@ def ring_flags(nx, ny, deflection):
 
 def sky_code(theta, phi, grid_deg=6.0, line_deg=0.25):
     return lib().ko_sky_code(theta, phi, grid_deg, line_deg)
+
+
+def emissivity(M, r, r_in, r_out, emis_q=2.0, model=0):
+    return lib().ko_emissivity(M, r, r_in, r_out, emis_q, model)
 
 
 def disk_omega(M, a, r, rotation=0, l0=0.0):

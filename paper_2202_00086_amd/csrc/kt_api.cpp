@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "kerrtrace.h"
+#include "kt_dual.h"
 #include "kt_internal.h"
 
 namespace {
@@ -94,6 +95,25 @@ void camera_constants(const kt_camera* cam, const kt_spacetime* st, kt::Image& i
     im.two_a2 = 2.0 * a * a;
 }
 
+// Derivatives of the camera constants (E0, cE, cL, cth, g_rr) with respect to
+// (a, incl): the formulas of camera_constants carried through dual numbers.
+void camera_constant_derivs(const kt_camera* cam, const kt_spacetime* st, double d[5][2]) {
+    using D = kt::Dual<2>;
+    const D a = D::var(st->a, 0), inc = D::var(cam->incl, 1);
+    const double M = st->M, r0 = cam->r_obs;
+    D s, c;
+    kt::dsincos(inc, &s, &c);
+    const D Sig = r0 * r0 + a * a * c * c;
+    const D Del = r0 * r0 - 2.0 * M * r0 + a * a;
+    const D g_tph = -2.0 * M * a * r0 * s * s / Sig;
+    const D g_phph = s * s * (r0 * r0 + a * a + 2.0 * M * a * a * r0 * s * s / Sig);
+    const D At = kt::dsqrt(g_phph / (Del * s * s));
+    const D v[5] = {1.0 / At, g_tph / (r0 * kt::dsqrt(g_phph)), -kt::dsqrt(g_phph) / r0, kt::dsqrt(Sig) / r0,
+                    Sig / Del};
+    for (int i = 0; i < 5; ++i)
+        for (int k = 0; k < 2; ++k) d[i][k] = v[i].d[k];
+}
+
 int validate_integ(const kt_integrator* integ) {
     if (integ->method < KT_RK4_S || integ->method > KT_BS)
         return fail(KT_EINVAL, "unknown integrator method %d", integ->method);
@@ -142,12 +162,17 @@ int make_image(const kt_camera* camera, const kt_spacetime* spacetime, const kt_
             return fail(KT_EINVAL, "unknown disk rotation %d", disk->rotation);
         if (disk->rotation == KT_ROT_L0 && !std::isfinite(disk->l0))
             return fail(KT_EINVAL, "l0 must be finite");
+        if (disk->emissivity != KT_EMIS_POWER && disk->emissivity != KT_EMIS_TAPERED)
+            return fail(KT_EINVAL, "unknown disk emissivity %d", disk->emissivity);
+        if (disk->emissivity == KT_EMIS_TAPERED && !(spacetime->M > 0.0))
+            return fail(KT_EINVAL, "the tapered emissivity needs M > 0");
         im.disk_on = 1;
         im.r_in = disk->r_in;
         im.r_out = disk->r_out;
         im.emis_q = disk->emis_index;
         im.rotation = disk->rotation;
         im.l0 = disk->l0;
+        im.emis_model = disk->emissivity;
     }
     const bool src_on = source && source->enabled;
     if (src_on) {
@@ -392,6 +417,67 @@ int kt_render_batch(int32_t n_images, const kt_image* images, const kt_integrato
     int64_t n = 0;
     if ((rc = make_table(n_images, images, integ, out->ring != nullptr, table, &n))) return rc;
     return render_images(table, n, integ, out, workspace, workspace_bytes, hip_stream, launch);
+}
+
+size_t kt_adjoint_workspace_bytes(const kt_camera* camera, const kt_integrator* integ) {
+    if (!camera || !integ || camera->nx < 1 || camera->ny < 1) return 0;
+    const size_t n = static_cast<size_t>(camera->nx) * static_cast<size_t>(camera->ny);
+    return kt::adj_layout(n, integ->max_steps).total;
+}
+
+int kt_adjoint(const kt_camera* camera, const kt_spacetime* spacetime, const kt_disk* disk,
+               const kt_integrator* integ, const uint8_t* fate, const double* r_hit, const double* cot_intensity,
+               double* grad_a, double* grad_incl, double* grad_r_in, uint64_t* stats, void* workspace,
+               size_t workspace_bytes, void* hip_stream) {
+    g_err[0] = 0;
+    int rc = validate_common(camera, spacetime);
+    if (rc) return rc;
+    if (!integ || !disk) return fail(KT_EINVAL, "integ and disk must not be NULL");
+    if ((rc = validate_integ(integ))) return rc;
+    if (integ->method != KT_DP45 || integ->precision != KT_FP64)
+        return fail(KT_EINVAL, "the adjoint follows the KT_DP45 / KT_FP64 integration");
+    if (!disk->enabled) return fail(KT_EINVAL, "the adjoint differentiates a disk image: enable the disk");
+    if (!(spacetime->M > 0.0)) return fail(KT_EINVAL, "the adjoint needs M > 0");
+    if (!fate || !cot_intensity) return fail(KT_EINVAL, "fate and cot_intensity must not be NULL");
+    kt::Image im;
+    if ((rc = make_image(camera, spacetime, disk, nullptr, integ, false, im))) return rc;
+    im.first = 0;
+    const size_t n = static_cast<size_t>(camera->nx) * static_cast<size_t>(camera->ny);
+    const kt::AdjLayout w = kt::adj_layout(n, integ->max_steps);
+    if (!workspace) return fail(KT_EINVAL, "workspace must not be NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(KT_EINVAL, "workspace must be 256-byte aligned");
+    if (workspace_bytes < w.total)
+        return fail(KT_ENOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes, w.total);
+
+    kt::AdjParams p;
+    std::memset(&p, 0, sizeof p);
+    p.im = im;
+    camera_constant_derivs(camera, spacetime, p.dcam);
+    p.dm = kt::adj::DiskModel{spacetime->M, disk->r_out, disk->emis_index, disk->l0, disk->rotation,
+                              disk->emissivity};
+    p.rtol = integ->rtol;
+    p.atol = integ->atol;
+    p.h_init = integ->h_init;
+    p.max_attempts = 16 * integ->max_steps;
+    p.n_rays = static_cast<int64_t>(n);
+    p.fate = fate;
+    p.r_hit = r_hit;
+    p.cot = cot_intensity;
+    p.grad_a = grad_a;
+    p.grad_incl = grad_incl;
+    p.grad_rin = grad_r_in;
+    char* ws = static_cast<char*>(workspace);
+    p.ticket = reinterpret_cast<uint32_t*>(ws);
+    p.stats = stats ? reinterpret_cast<unsigned long long*>(stats)
+                    : reinterpret_cast<unsigned long long*>(ws + w.stats);
+    p.ckpt = reinterpret_cast<double*>(ws + w.ckpt);
+    p.seg = reinterpret_cast<double*>(ws + w.seg);
+    p.n_lanes = w.n_lanes;
+    p.max_ckpt = w.max_ckpt;
+    if (kt::launch_adjoint(p, hip_stream))
+        return fail(KT_EDEVICE, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError()));
+    return KT_OK;
 }
 
 int kt_autotune_batch(int32_t n_images, const kt_image* images, const kt_integrator* integ,

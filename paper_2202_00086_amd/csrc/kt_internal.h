@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "kerrtrace.h"
+#include "kt_adjoint_math.h"
 
 namespace kt {
 
@@ -35,7 +36,7 @@ struct Image {
     int32_t nx, ny;
     int64_t first;  // ray id of pixel 0 (outputs of this image start here)
     // disk (Sect. 5)
-    int32_t disk_on, rotation;
+    int32_t disk_on, rotation, emis_model;
     double r_in, r_out, emis_q, l0;
     // source for the deflection diagnostics
     int32_t src_on;
@@ -118,7 +119,51 @@ struct Hot {
     const Params* cold;         // the workspace copy of Params
 };
 
-// Host-side launchers (kt_trace.hip).
+// Everything the adjoint kernel needs (passed by value).
+struct AdjParams {
+    Image im;
+    double dcam[5][2];  // d(E0, cE, cL, cth, g_rr) / d(a, incl)
+    adj::DiskModel dm;
+    double rtol, atol, h_init;
+    int64_t max_attempts;
+    int64_t n_rays;
+    const uint8_t* fate;
+    const double* r_hit;
+    const double* cot;
+    double *grad_a, *grad_incl, *grad_rin;
+    uint32_t* ticket;
+    unsigned long long* stats;  // [ok, failed, overflow, mismatch]
+    double* ckpt;               // [max_ckpt][6][n_lanes]
+    double* seg;                // [64][6][n_lanes]
+    int32_t n_lanes, max_ckpt;
+};
+
+constexpr int ADJ_MAX_LANES = 65536;
+constexpr int ADJ_MAX_CKPT = 256;
+
+struct AdjLayout {
+    size_t stats, ckpt, seg, total;
+    int32_t n_lanes, max_ckpt;
+};
+
+inline AdjLayout adj_layout(size_t n_rays, int64_t max_steps) {
+    AdjLayout w;
+    size_t lanes = (n_rays + 255) / 256 * 256;
+    if (lanes > static_cast<size_t>(ADJ_MAX_LANES)) lanes = ADJ_MAX_LANES;
+    if (lanes < 256) lanes = 256;
+    int64_t ck = max_steps / 64 + 2;
+    if (ck > ADJ_MAX_CKPT) ck = ADJ_MAX_CKPT;
+    w.n_lanes = static_cast<int32_t>(lanes);
+    w.max_ckpt = static_cast<int32_t>(ck);
+    w.stats = 64;
+    w.ckpt = 256;
+    w.seg = align256(w.ckpt + static_cast<size_t>(ck) * 6u * lanes * sizeof(double));
+    w.total = align256(w.seg + 64u * 6u * lanes * sizeof(double));
+    return w;
+}
+
+// Host-side launchers (kt_trace.hip, kt_adjoint.hip).
+int launch_adjoint(const AdjParams& p, void* stream);
 int launch_ws_init(const Params& p, void* stream);  // also copies p into the workspace
 int launch_upload_images(const Image* host, int32_t n, Image* dev, void* stream);
 int launch_trace(const Params& p, int grid, int block, void* stream);  // pass of p.precision

@@ -16,14 +16,13 @@
 
 #include "kt_device.h"
 #include "kt_internal.h"
+#include "kt_ray.h"
 
 #ifndef KT_WAVES_PER_EU
 #define KT_WAVES_PER_EU 2
 #endif
 
 namespace kt {
-
-constexpr double HALF_PI = 1.57079632679489661923;
 
 // Great-circle angle between the directions (theta1, phi1) and
 // (theta2, phi1 + dphi), given sin/cos of the thetas: atan2(|n1 x n2|, n1.n2).
@@ -77,30 +76,6 @@ __device__ __forceinline__ uint8_t sky_code(double th, double ph, double grid_de
     }
     if (t < HALF_PI) return p < PI ? KT_SKY_GREEN : KT_SKY_RED;
     return p < PI ? KT_SKY_BLUE : KT_SKY_YELLOW;
-}
-
-// Initial state of pixel `pix` of image `im` (second eq:momentums with p_r
-// ingoing).  Returns false when x^2 + y^2 >= r0^2 (no real p_r).
-__device__ __forceinline__ bool camera_state(const Image& im, int32_t pix, double z[5], double* E,
-                                             double* L) {
-    // separate roundings, no FMA: the pixel centre is the same double the
-    // plain expression -fov + (i + 1/2) dx gives on any IEEE machine
-#pragma clang fp contract(off)
-    const int32_t j = pix / im.nx;
-    const int32_t i = pix - j * im.nx;
-    const double x = -im.fov_x + (static_cast<double>(i) + 0.5) * im.dx;
-    const double y = -im.fov_y + (static_cast<double>(j) + 0.5) * im.dy;
-    const double Pth = y / im.r0;   // observer-frame P^theta with P^t = 1
-    const double Pph = -x / im.r0;  // observer-frame P^phi
-    const double rad = 1.0 - Pth * Pth - Pph * Pph;
-    *E = im.E0 + x * im.cE;
-    *L = x * im.cL;
-    z[0] = im.r0;
-    z[1] = im.incl;
-    z[2] = 0.0;
-    z[3] = rad > 0.0 ? -sqrt(im.g_rr * rad) : 0.0;
-    z[4] = y * im.cth;
-    return rad > 0.0;
 }
 
 // Index of the image that ray id `ray` belongs to (binary search over the
@@ -182,44 +157,6 @@ __device__ __forceinline__ void take_step(const Spacetime& st, const RayConst& r
 #pragma unroll
         for (int i = 0; i < 5; ++i) er[i] = 0.0;
     }
-}
-
-// Evaluations per step and the step-size controller exponent 1/(q + 1), q
-// the order of the method's error estimate (4 for the Runge-Kutta pairs,
-// 2K - 2 for Bulirsch-Stoer with K columns).
-template <int METHOD>
-constexpr int evals_per_step() {
-    return METHOD == KT_RK4_S ? 4 : METHOD == KT_BS ? BS_COLUMNS * BS_COLUMNS + 1 : 6;
-}
-template <int METHOD>
-constexpr float controller_exponent() {
-    return METHOD == KT_BS ? 1.0f / (2 * BS_COLUMNS - 1) : 0.2f;
-}
-
-// Step-size factor 0.9 err^(-1/(q+1)) from the mean-square error msq = err^2,
-// evaluated in FP32: it only steers the step size.
-template <int METHOD>
-__device__ __forceinline__ float step_factor(double msq) {
-    constexpr float x = -0.5f * controller_exponent<METHOD>();
-    return 0.9f * __builtin_amdgcn_exp2f(x * __builtin_amdgcn_logf(static_cast<float>(msq)));
-}
-
-// Mean square of err_i / sc_i over the five components.  The five
-// reciprocals come from one hardware reciprocal estimate of the product of
-// the scales (relative error ~5e-8: this number only steers the step size).
-__device__ __forceinline__ double error_msq(const double er[5], const double sc[5]) {
-    const double p01 = sc[0] * sc[1], p34 = sc[3] * sc[4];
-    const double p012 = p01 * sc[2];
-    const double q = __builtin_amdgcn_rcp(p012 * p34);
-    const double q012 = q * p34;           // 1 / (sc0 sc1 sc2)
-    const double q34 = q * p012;           // 1 / (sc3 sc4)
-    const double q01 = q012 * sc[2];       // 1 / (sc0 sc1)
-    const double e0 = er[0] * (q01 * sc[1]);
-    const double e1 = er[1] * (q01 * sc[0]);
-    const double e2 = er[2] * (q012 * p01);
-    const double e3 = er[3] * (q34 * sc[4]);
-    const double e4 = er[4] * (q34 * sc[3]);
-    return 0.2 * fma(e0, e0, fma(e1, e1, fma(e2, e2, fma(e3, e3, e4 * e4))));
 }
 
 template <int METHOD, int PREC, bool BATCH>
@@ -640,7 +577,16 @@ __global__ void disk_obs_kernel(const Params* pp) {
             r_hit = rc;
             if (norm > 0.0) {
                 g = sqrt(norm) / (E - Om * L);
-                inten = g * g * g * pow(im.M * inv_rc, im.emis_q);
+                double em;
+                if (im.emis_model == KT_EMIS_TAPERED) {
+                    const double mr = im.M * inv_rc;
+                    em = mr * mr * (1.0 - sqrt(im.r_in * inv_rc));
+                    const double sv = (im.r_out - rc) / (2.0 * im.M);
+                    if (sv < 1.0) em *= sv * sv * (3.0 - 2.0 * sv);
+                } else {
+                    em = pow(im.M * inv_rc, im.emis_q);
+                }
+                inten = g * g * g * em;
             }
         }
         if (p.out.r_hit) p.out.r_hit[k] = r_hit;

@@ -1,7 +1,7 @@
 """Python binding of libkerrtrace.so (the C ABI in include/kerrtrace.h).
 
 The functions kt_render, kt_render_ex, kt_render_batch, kt_autotune_batch,
-kt_workspace_bytes,
+kt_adjoint, kt_workspace_bytes, kt_adjoint_workspace_bytes,
 kt_workspace_bytes_batch, kt_init_rays, kt_last_error and kt_version mirror
 the C entry points one to one and only marshal arguments: every step of the ray tracing runs in the HIP kernels of
 the library.  PyTorch supplies device memory and the HIP stream.
@@ -42,7 +42,8 @@ class kt_spacetime(C.Structure):
 
 class kt_disk(C.Structure):
     _fields_ = [("enabled", C.c_int32), ("r_in", C.c_double), ("r_out", C.c_double),
-                ("emis_index", C.c_double), ("rotation", C.c_int32), ("l0", C.c_double)]
+                ("emis_index", C.c_double), ("rotation", C.c_int32), ("l0", C.c_double),
+                ("emissivity", C.c_int32)]
 
 
 class kt_source(C.Structure):
@@ -78,6 +79,7 @@ class kt_stats(C.Structure):
 OUTPUT_FIELDS = ("fate", "r_hit", "g", "intensity", "max_abs_h", "max_rel_h", "psi", "deflection",
                  "theta_f", "phi_f", "n_cross", "used_fp64", "ring", "n_steps", "n_evals", "sky")
 KEPLER, L0 = 0, 1
+EMIS_POWER, EMIS_TAPERED = 0, 1
 SKY_NONE, SKY_GREEN, SKY_RED, SKY_BLUE, SKY_YELLOW, SKY_LINE = range(6)
 
 
@@ -101,6 +103,12 @@ _lib.kt_autotune_batch.restype = C.c_int
 _lib.kt_workspace_bytes.argtypes = [_P(kt_camera), _P(kt_integrator)]
 _lib.kt_workspace_bytes.restype = C.c_size_t
 _lib.kt_workspace_bytes_batch.argtypes = [C.c_int32, _P(kt_image), _P(kt_integrator)]
+_lib.kt_adjoint.argtypes = [_P(kt_camera), _P(kt_spacetime), _P(kt_disk), _P(kt_integrator), C.c_void_p,
+                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.c_void_p, C.c_size_t, C.c_void_p]
+_lib.kt_adjoint.restype = C.c_int
+_lib.kt_adjoint_workspace_bytes.argtypes = [_P(kt_camera), _P(kt_integrator)]
+_lib.kt_adjoint_workspace_bytes.restype = C.c_size_t
 _lib.kt_workspace_bytes_batch.restype = C.c_size_t
 _lib.kt_init_rays.argtypes = [_P(kt_camera), _P(kt_spacetime), C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.kt_init_rays.restype = C.c_int
@@ -109,8 +117,9 @@ _lib.kt_last_error.restype = C.c_char_p
 _lib.kt_version.argtypes = []
 _lib.kt_version.restype = C.c_int
 
-EXPORTED = ("kt_render", "kt_render_ex", "kt_render_batch", "kt_autotune_batch", "kt_workspace_bytes",
-            "kt_workspace_bytes_batch", "kt_init_rays", "kt_last_error", "kt_version")
+EXPORTED = ("kt_render", "kt_render_ex", "kt_render_batch", "kt_autotune_batch", "kt_adjoint",
+            "kt_workspace_bytes", "kt_workspace_bytes_batch", "kt_adjoint_workspace_bytes", "kt_init_rays",
+            "kt_last_error", "kt_version")
 AUTOTUNE_DEFAULT_COUNT = 20
 
 
@@ -171,6 +180,17 @@ def kt_autotune_batch(images, integ, outputs, workspace_ptr, workspace_bytes, st
     return rc, best, list(times)
 
 
+def kt_adjoint_workspace_bytes(camera, integ):
+    return _lib.kt_adjoint_workspace_bytes(C.byref(camera), C.byref(integ))
+
+
+def kt_adjoint(camera, spacetime, disk, integ, fate_ptr, r_hit_ptr, cot_ptr, grad_a_ptr, grad_incl_ptr,
+               grad_rin_ptr, stats_ptr, workspace_ptr, workspace_bytes, stream_ptr):
+    return _lib.kt_adjoint(C.byref(camera), C.byref(spacetime), C.byref(disk), C.byref(integ), fate_ptr,
+                           r_hit_ptr, cot_ptr, grad_a_ptr, grad_incl_ptr, grad_rin_ptr, stats_ptr,
+                           workspace_ptr, workspace_bytes, stream_ptr)
+
+
 def kt_init_rays(camera, spacetime, state_ptr, invalid_ptr, stream_ptr):
     return _lib.kt_init_rays(C.byref(camera), C.byref(spacetime), state_ptr, invalid_ptr, stream_ptr)
 
@@ -183,13 +203,13 @@ def make_structs(M=1.0, a=0.0, r_obs=1000.0, incl=math.pi / 2, fov_x=10.0, fov_y
                  ny=64, method=DP45, precision=FP64, h_fixed=1.0 / 128, rtol=1e-12, atol=1e-12,
                  h_init=1.0, cap_buffer=0.01, r_escape=0.0, h_budget=1e-10, r_switch=300.0,
                  max_steps=1_000_000, disk_on=0, r_in=6.0, r_out=30.0, emis_q=2.0, rotation=0, l0=0.0,
-                 src_on=0, r_src=1000.0, sky_on=0, grid_deg=6.0, line_deg=0.25):
+                 emis_model=0, src_on=0, r_src=1000.0, sky_on=0, grid_deg=6.0, line_deg=0.25):
     """C structs from keyword parameters (the same names the workloads use)."""
     cam = kt_camera(r_obs, incl, fov_x, fov_y, nx, ny)
     st = kt_spacetime(M, a)
     integ = kt_integrator(method, precision, h_fixed, rtol, atol, h_init, cap_buffer, r_escape,
                           h_budget, r_switch, int(max_steps))
-    disk = kt_disk(int(disk_on), r_in, r_out, emis_q, int(rotation), l0)
+    disk = kt_disk(int(disk_on), r_in, r_out, emis_q, int(rotation), l0, int(emis_model))
     src = kt_source(int(src_on), r_src, int(sky_on), grid_deg, line_deg)
     return cam, st, disk, src, integ
 
@@ -261,7 +281,7 @@ class Renderer:
 
 
 _IMAGE_KEYS = ("M", "a", "r_obs", "incl", "fov_x", "fov_y", "nx", "ny", "disk_on", "r_in", "r_out",
-               "emis_q", "rotation", "l0", "src_on", "r_src", "sky_on", "grid_deg", "line_deg")
+               "emis_q", "rotation", "l0", "emis_model", "src_on", "r_src", "sky_on", "grid_deg", "line_deg")
 
 
 def split_params(params):

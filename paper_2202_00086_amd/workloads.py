@@ -16,6 +16,8 @@ the CPU oracle (oracle.Setup) accept these keyword names.
                             (the integrator comparison grid).
   lensing(a)                celestial-sphere lensing, r_obs = 100M, i = 90 deg.
   thin_disk_l0(a)           the Sect. 5 disk images with constant-l0 rotation.
+  differentiable_disk       a = 0.7, i = 45 deg, 512x512 disk with the tapered
+                            emissivity; disk_fit_target is its fit target.
   heterogeneous_batch       256 seeded Kerr disk images: sides 64..1024 in
                             steps of 64, a ~ U[0, 0.998], i ~ U[5, 85] deg,
                             r_obs log-uniform in [100, 1e4]M, +-35M, disk
@@ -81,6 +83,24 @@ def thin_disk_l0(a=0.5, nx=2048, ny=1024, rtol=1e-12):
                 l0=1.8 if a > 0.9 else 2.8)
 
 
+def differentiable_disk(a=0.7, incl_deg=45.0, r_in=None, n=512, rtol=1e-12):
+    """The differentiable disk image: Kerr thin disk seen from r0 = 1000M,
+    +-35M, r_out = 30M, Keplerian rotation, the tapered emissivity
+    (M/r)^2 (1 - sqrt(r_in/r)) that makes the image continuous in r_in, DP45
+    in FP64.  r_in defaults to the ISCO; the gradient's parameters are
+    (a, incl, r_in)."""
+    return dict(M=1.0, a=a, r_obs=1000.0, incl=math.radians(incl_deg), fov_x=35.0, fov_y=35.0, nx=n, ny=n,
+                method=1, rtol=rtol, atol=rtol, h_init=1.0, cap_buffer=0.01, r_escape=1100.0,
+                max_steps=1_000_000, disk_on=1, r_in=isco(a) if r_in is None else r_in, r_out=30.0,
+                emis_q=2.0, emis_model=1)
+
+
+def disk_fit_target(n=512):
+    """The target of the fit: the same image at a = 0.6, i = 50 deg,
+    r_in = 1.1 ISCO(0.6)."""
+    return differentiable_disk(a=0.6, incl_deg=50.0, r_in=1.1 * isco(0.6), n=n)
+
+
 def isco(a, M=1.0):
     """Radius of the innermost stable circular orbit of Kerr for orbits
     moving in +phi (prograde for a > 0, retrograde for a < 0), from the
@@ -95,7 +115,7 @@ def isco(a, M=1.0):
 
 # keys that describe one image; everything else is the shared integrator
 IMAGE_KEYS = ("M", "a", "r_obs", "incl", "fov_x", "fov_y", "nx", "ny", "disk_on", "r_in", "r_out",
-              "emis_q", "rotation", "l0", "src_on", "r_src", "sky_on", "grid_deg", "line_deg")
+              "emis_q", "rotation", "l0", "emis_model", "src_on", "r_src", "sky_on", "grid_deg", "line_deg")
 
 
 def heterogeneous_batch(n_images=256, seed=20220201, side_unit=64, side_steps=16, fov=35.0, rtol=1e-12):

@@ -31,8 +31,9 @@ def _declared_functions():
 
 def test_header_declares_expected_entry_points():
     assert _declared_functions() == sorted(
-        ["kt_render", "kt_render_ex", "kt_render_batch", "kt_autotune_batch", "kt_workspace_bytes",
-         "kt_workspace_bytes_batch", "kt_init_rays", "kt_last_error", "kt_version"])
+        ["kt_render", "kt_render_ex", "kt_render_batch", "kt_autotune_batch", "kt_adjoint",
+         "kt_workspace_bytes", "kt_workspace_bytes_batch", "kt_adjoint_workspace_bytes", "kt_init_rays",
+         "kt_last_error", "kt_version"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -41,7 +42,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared_functions():
         assert hasattr(lib, name), name
     assert set(K.EXPORTED) == set(_declared_functions())
-    assert K.kt_version() == 120
+    assert K.kt_version() == 130
 
 
 def test_struct_layouts_match_header():
@@ -49,13 +50,13 @@ def test_struct_layouts_match_header():
     from paper_2202_00086_amd import kerrtrace as K
     assert C.sizeof(K.kt_camera) == 4 * 8 + 2 * 4
     assert C.sizeof(K.kt_spacetime) == 16
-    assert C.sizeof(K.kt_disk) == 48
+    assert C.sizeof(K.kt_disk) == 56
     assert C.sizeof(K.kt_source) == 40
     assert C.sizeof(K.kt_integrator) == 8 + 8 * 8 + 8
     assert C.sizeof(K.kt_launch) == 16
     assert C.sizeof(K.kt_stats) == 12 * 8
     assert C.sizeof(K.kt_outputs) == 17 * 8
-    assert C.sizeof(K.kt_image) == 40 + 16 + 48 + 40
+    assert C.sizeof(K.kt_image) == 40 + 16 + 56 + 40
 
 
 def _args(**kw):
@@ -86,6 +87,7 @@ BAD = [
     dict(r_escape=500.0),                            # inside the observer
     dict(src_on=1, r_src=1.0),
     dict(disk_on=1, rotation=2),
+    dict(disk_on=1, emis_model=3),
     dict(disk_on=1, rotation=1, l0=float("nan")),
     dict(sky_on=1, grid_deg=-6.0),
     dict(sky_on=1, line_deg=float("inf")),
@@ -256,3 +258,30 @@ def test_autotune_validation():
     assert call(one, 1, 2, None) == K.KT_EINVAL                    # no place for the result
     assert call(bad, 1, 2, C.byref(best)) == K.KT_EINVAL           # shape out of range
     assert "candidate" in K.kt_last_error()
+
+
+@no_gpu_only
+def test_adjoint_validation():
+    from paper_2202_00086_amd import kerrtrace as K
+    from paper_2202_00086_amd import workloads as W
+    p = W.differentiable_disk(n=16)
+    cam, st, disk, src, integ = K.make_structs(**p)
+    ws = C.c_void_p(0x100000)
+    need = K.kt_adjoint_workspace_bytes(cam, integ)
+    assert need > 256 * 64 * 6 * 8
+
+    def call(cam=cam, st=st, disk=disk, integ=integ, fate=0x1000, cot=0x2000, nbytes=1 << 40):
+        return K.kt_adjoint(cam, st, disk, integ, fate, None, cot, None, None, None, None, ws, nbytes, None)
+    _, _, _, _, rk = K.make_structs(**dict(p, method=K.RKF45))
+    assert call(integ=rk) == K.KT_EINVAL and "KT_DP45" in K.kt_last_error()
+    _, _, _, _, mx = K.make_structs(**dict(p, precision=K.MIXED))
+    assert call(integ=mx) == K.KT_EINVAL
+    _, _, nodisk, _, _ = K.make_structs(**dict(p, disk_on=0))
+    assert call(disk=nodisk) == K.KT_EINVAL
+    assert call(fate=None) == K.KT_EINVAL
+    assert call(cot=None) == K.KT_EINVAL
+    assert call(nbytes=need - 1) == K.KT_ENOMEM
+    _, bad_st, _, _, _ = K.make_structs(**dict(p, a=1.5))
+    assert call(st=bad_st) == K.KT_EINVAL
+    assert K.kt_adjoint(cam, st, disk, integ, 0x1000, None, 0x2000, None, None, None, None, None, need,
+                        None) == K.KT_EINVAL

@@ -1,0 +1,109 @@
+"""The discrete adjoint of the disk image against central finite differences
+(h = 1e-6) of the CPU oracle's forward image, pixel by pixel, and through
+torch.autograd for an L2 image loss."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2202_00086_amd import workloads as W
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+H = 1e-6
+KEYS = ("a", "incl", "r_in")
+
+
+def _announce(*what):
+    print("[gpu-case]", *what, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _oracle_fd(params, nx, ny):
+    """Base oracle image and per-pixel central differences of I in a, incl,
+    r_in, with the pixels whose fate or image order changes under the
+    perturbations marked."""
+    base = O.trace_pixels(O.Setup(**params))
+    fd, stable = {}, np.ones(nx * ny, bool)
+    for k in KEYS:
+        up = O.trace_pixels(O.Setup(**dict(params, **{k: params[k] + H})))
+        dn = O.trace_pixels(O.Setup(**dict(params, **{k: params[k] - H})))
+        fd[k] = (up["intensity"] - dn["intensity"]) / (2 * H)
+        for o in (up, dn):
+            stable &= (o["fate"] == base["fate"]) & (o["n_cross"] == base["n_cross"])
+    return base, fd, stable
+
+
+def test_adjoint_matches_oracle_finite_differences(torch_mod):
+    from paper_2202_00086_amd import autograd as AG
+    nx = ny = 40
+    params = W.differentiable_disk(n=nx)
+    _announce("adjoint per-pixel", nx)
+    out, grads, stats = AG.adjoint_maps(**params)
+    torch_mod.cuda.synchronize()
+    st = stats.cpu().numpy()
+    g = {k: v.cpu().numpy() for k, v in zip(KEYS, grads)}
+    fate = out["fate"].cpu().numpy()
+    print(f"[adjoint] stats ok/failed/overflow/mismatch = {st.tolist()}", flush=True)
+    assert st[1] == 0 and st[2] == 0 and st[3] == 0
+    assert st[0] == int((fate == O.DISK).sum())
+    base, fd, stable = _oracle_fd(params, nx, ny)
+    gpu = {"fate": fate, "n_cross": out["n_cross"].cpu().numpy()}
+    m = P.value_mask(gpu, base, nx, ny) & (base["fate"] == O.DISK) & stable
+    assert m.sum() > 150
+    worst = {}
+    for k in KEYS:
+        a, b = g[k][m], fd[k][m]
+        scale = np.abs(b).max()
+        err = np.abs(a - b) / (np.abs(b) + 1e-3 * scale)
+        worst[k] = float(err.max())
+        assert err.max() < 1e-4, (k, err.max(), np.argmax(err))
+    print(f"[adjoint] {m.sum()} pixels; worst relative difference to FD {worst}", flush=True)
+    # zero away from the disk
+    off = fate != O.DISK
+    for k in KEYS:
+        assert (g[k][off] == 0.0).all()
+
+
+def test_autograd_loss_gradient_matches_finite_differences(torch_mod):
+    """L = sum over primary/secondary disk pixels of (I - T)^2, T the image
+    at (0.6, 50 deg, 1.1 ISCO(0.6)); the mask comes from the base render."""
+    torch = torch_mod
+    from paper_2202_00086_amd import autograd as AG
+    nx = 32
+    params = W.differentiable_disk(n=nx)
+    target = W.disk_fit_target(n=nx)
+    _announce("adjoint autograd loss", nx)
+    from paper_2202_00086_amd import kerrtrace as K
+    T = K.Renderer(device="cuda:0", want=("fate", "r_hit", "g", "intensity"), **target).render()["intensity"]
+    a = torch.tensor(params["a"], dtype=torch.float64, requires_grad=True)
+    i = torch.tensor(params["incl"], dtype=torch.float64, requires_grad=True)
+    rin = torch.tensor(params["r_in"], dtype=torch.float64, requires_grad=True)
+    fixed = {k: v for k, v in params.items() if k not in ("a", "incl", "r_in")}
+    I, fate, ncross = AG.disk_image(a, i, rin, **fixed)
+    base, _, stable = _oracle_fd(params, nx, nx)
+    gpu = {"fate": fate.cpu().numpy(), "n_cross": ncross.cpu().numpy()}
+    mask_np = P.value_mask(gpu, base, nx, nx) & (base["fate"] == O.DISK) & stable
+    mask = torch.from_numpy(mask_np).to("cuda:0")
+    loss = ((I - T) ** 2 * mask).sum()
+    loss.backward()
+    got = np.array([a.grad.item(), i.grad.item(), rin.grad.item()])
+    Tn = T.cpu().numpy()
+
+    def oracle_loss(**kw):
+        o = O.trace_pixels(O.Setup(**dict(params, **kw)))
+        return float((((o["intensity"] - Tn) ** 2)[mask_np]).sum())
+    want = np.array([(oracle_loss(**{k: params[k] + H}) - oracle_loss(**{k: params[k] - H})) / (2 * H)
+                     for k in KEYS])
+    print(f"[adjoint] loss {loss.item():.6e}; grad {got}; FD {want}", flush=True)
+    np.testing.assert_allclose(got, want, rtol=1e-4, atol=1e-9 * np.abs(want).max())
