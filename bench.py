@@ -182,6 +182,45 @@ def run_scheme_forms(K, torch, W, steps):
     return res
 
 
+def run_adjoint_form(K, torch, W, steps):
+    """The differentiable disk image (512^2, a = 0.7, i = 45 deg, r_in =
+    ISCO, tapered emissivity): forward render and the discrete adjoint of the
+    L2 loss against the image at (0.6, 50 deg, 1.1 ISCO(0.6)), both timed."""
+    import ctypes as C
+    params = W.differentiable_disk(n=512)
+    want = ("fate", "r_hit", "g", "intensity", "n_cross")
+    T = K.Renderer(device="cuda:0", want=want, stats=False, **W.disk_fit_target(n=512)).render()["intensity"]
+    r = K.Renderer(device="cuda:0", want=want, stats=False, **params)
+    r.render()
+    t_fwd = _time(torch, r.render, steps)
+    out = r.out
+    mask = (out["fate"] == K.DISK) & (out["n_cross"] <= 1)
+    cot = (2.0 * (out["intensity"] - T) * mask).contiguous()
+    grads = [torch.empty(r.n, dtype=torch.float64, device="cuda:0") for _ in range(3)]
+    stats = torch.zeros(4, dtype=torch.int64, device="cuda:0")
+    nbytes = K.kt_adjoint_workspace_bytes(r.cam, r.integ)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def adjoint():
+        rc = K.kt_adjoint(r.cam, r.st, r.disk, r.integ, out["fate"].data_ptr(), out["r_hit"].data_ptr(),
+                          cot.data_ptr(), grads[0].data_ptr(), grads[1].data_ptr(), grads[2].data_ptr(),
+                          stats.data_ptr(), ws.data_ptr(), nbytes, stream)
+        if rc != K.KT_OK:
+            raise K.KtError(rc, K.kt_last_error())
+    adjoint()
+    t_adj = _time(torch, adjoint, steps)
+    st = [int(v) for v in stats.cpu().tolist()]
+    return {"workload": "Kerr a=0.7 disk, 512x512, i=45 deg, r_obs=1000M, +-35M, r_in=ISCO(0.7), r_out=30M, "
+                        "tapered emissivity, DP45 rtol=atol=1e-12; L2 loss vs (a=0.6, i=50 deg, r_in=1.1 ISCO)",
+            "forward_ms": 1e3 * t_fwd, "adjoint_ms": 1e3 * t_adj, "adjoint_over_forward": t_adj / t_fwd,
+            "loss": float((((out["intensity"] - T) ** 2) * mask).sum().item()),
+            "grad": {"a": float(grads[0].sum().item()), "incl": float(grads[1].sum().item()),
+                     "r_in": float(grads[2].sum().item())},
+            "rays_differentiated": st[0], "failed": st[1], "overflow": st[2], "mismatch": st[3],
+            "differentiated_rays_per_s": st[0] / t_adj}
+
+
 def run_batch_forms(K, torch, W, steps):
     """The 256-image heterogeneous Kerr disk workload: one autotuned
     persistent FP64 launch, the same images as 256 separate FP64 launches,
@@ -296,10 +335,11 @@ def main():
                            "max_rel_h": f["max_rel_h"], "p999_rel_h": f["p999_rel_h"],
                            "error_vs_fp64": error_vs(torch, f["out"], main_form["out"])}
 
-    batch = schemes = None
+    batch = schemes = adjoint = None
     if not args.no_forms:
         batch = run_batch_forms(K, torch, W, max(2, args.steps // 8))
         schemes = run_scheme_forms(K, torch, W, max(2, args.steps // 8))
+        adjoint = run_adjoint_form(K, torch, W, max(2, args.steps // 8))
 
     out = {"metric": METRIC, "value": rays_per_s, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": main_form["ms_per_step"], "higher_is_better": True,
@@ -319,6 +359,8 @@ def main():
         out["batch"] = batch
     if schemes:
         out["integrators"] = schemes
+    if adjoint:
+        out["adjoint"] = adjoint
     if not args.no_cpu:
         cb = cpu_baseline(params)
         out["cpu_baseline"] = cb
