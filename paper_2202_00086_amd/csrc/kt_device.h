@@ -14,14 +14,13 @@ namespace kt {
 // Elementary functions
 // ---------------------------------------------------------------------------
 
-// 1/x from the hardware reciprocal estimate refined by two Newton steps
-// (each squares the relative error), so the result is within an ulp or two.
+// 1/x from the hardware reciprocal estimate y (relative error e) refined by
+// one third-order step y (1 + e + e^2), which cubes the error (below 1e-21
+// from the estimate's ~5e-8): the result is within about an ulp.
 __device__ __forceinline__ double rcp(double x) {
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
+    const double y = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, y, 1.0);
+    return fma(y, fma(e, e, e), y);
 }
 
 // sin and cos of x for |x| < ~1e5.  Cody-Waite reduction by pi/2 with a
@@ -139,29 +138,6 @@ __device__ __forceinline__ void sincos_theta(double th, double* s_out, double* c
     *c_out = fma(ps * u2, u, -u);                   // cos theta = -sin u
 }
 
-// sin and cos of a small angle, |x| <= 1/2, from their Taylor series (sin
-// through x^15, cos through x^16: truncation below 1e-19); no reduction.
-__device__ __forceinline__ void sincos_small(double x, double* s_out, double* c_out) {
-    const double x2 = x * x;
-    double ps = -1.0 / 1307674368000.0;
-    ps = fma(ps, x2, 1.0 / 6227020800.0);
-    ps = fma(ps, x2, -1.0 / 39916800.0);
-    ps = fma(ps, x2, 1.0 / 362880.0);
-    ps = fma(ps, x2, -1.0 / 5040.0);
-    ps = fma(ps, x2, 1.0 / 120.0);
-    ps = fma(ps, x2, -1.0 / 6.0);
-    *s_out = fma(ps * x2, x, x);
-    double pc = 1.0 / 20922789888000.0;
-    pc = fma(pc, x2, -1.0 / 87178291200.0);
-    pc = fma(pc, x2, 1.0 / 479001600.0);
-    pc = fma(pc, x2, -1.0 / 3628800.0);
-    pc = fma(pc, x2, 1.0 / 40320.0);
-    pc = fma(pc, x2, -1.0 / 720.0);
-    pc = fma(pc, x2, 1.0 / 24.0);
-    pc = fma(pc, x2, -0.5);
-    *c_out = fma(pc, x2, 1.0);
-}
-
 // Coefficient k of the series asin x = sum_k c_k x^(2k+1),
 // c_k = (2k)! / (4^k (k!)^2 (2k+1)), from c_0 = 1 and
 // c_k = c_(k-1) (2k-1)^2 / ((2k)(2k+1)).
@@ -198,7 +174,7 @@ struct Spacetime {
 struct RayConst {
     double E, L;    // -p_t, p_phi
     double aE, aL;  // a E, a L
-    double fourE;   // 4 E
+    double twoE;    // 2 E
 };
 
 __device__ __forceinline__ RayConst make_ray_const(const Spacetime& st, double E, double L) {
@@ -207,7 +183,7 @@ __device__ __forceinline__ RayConst make_ray_const(const Spacetime& st, double E
     rc.L = L;
     rc.aE = st.a * E;
     rc.aL = st.a * L;
-    rc.fourE = 4.0 * E;
+    rc.twoE = 2.0 * E;
     return rc;
 }
 
@@ -250,17 +226,17 @@ __device__ __forceinline__ void rhs_sc(const Spacetime& st, const RayConst& rc, 
     const double pr2 = pr * pr;
     const double WWd = W * Wd;
     const double K = fma(Del, pr2, fma(pth, pth, fma(T, T, -WWd)));
-    const double hs = 0.5 * inv_Sig;
-    const double H = K * hs;
-    // d K / d r = 2 (r - M) (p_r^2 + Wd^2) - 4 r E Wd
-    const double dKdr = fma(2.0 * (r - st.M), fma(Wd, Wd, pr2), -rc.fourE * r * Wd);
-    // d T / d theta = -cos (L / sin^2 + a E)
-    const double dT = -c * fma(rc.L, inv_s * inv_s, rc.aE);
+    const double H2 = K * inv_Sig;  // 2H
+    // (1/2) d K / d r = (r - M) (p_r^2 + Wd^2) - 2 r E Wd
+    const double hdK = fma(r - st.M, fma(Wd, Wd, pr2), -(rc.twoE * r) * Wd);
+    // d T / d theta = -cos Q, Q = L / sin^2 + a E
+    const double Q = fma(rc.L, inv_s * inv_s, rc.aE);
     double d0 = Del * pr * inv_Sig;
     double d1 = pth * inv_Sig;
     double d2 = fma(T, inv_s, st.a * Wd) * inv_Sig;
-    double d3 = fma(4.0 * r, H, -dKdr) * hs;
-    double d4 = -fma(T, dT, st.two_a2 * H * s * c) * inv_Sig;
+    // -dH/dr = (2 r H - (1/2) dK/dr) / Sigma;  -dH/dtheta = cos (T Q - a^2 sin 2H) / Sigma
+    double d3 = fma(r, H2, -hdK) * inv_Sig;
+    double d4 = (c * inv_Sig) * fma(T, Q, -(st.a2 * H2) * s);
     if (S_TIME) {
         const double w = Del * (s * SD * q);  // Delta / r
         d0 *= w;
@@ -276,7 +252,7 @@ __device__ __forceinline__ void rhs_sc(const Spacetime& st, const RayConst& rc, 
     dz[4] = d4;
     if (WANT_DIAG) {
         const double D = fma(Del, pr2, fma(pth, pth, fma(T, T, WWd)));
-        dg->H = H;
+        dg->H = 0.5 * H2;
         dg->rel = fabs(K) * rcp(D);
         dg->s = s;
         dg->c = c;
