@@ -29,7 +29,9 @@
  *     (Keplerian, or with the constant specific angular momentum l0 of
  *     Sect. 5), and I_obs = g^3 I_em;
  *   - the coloured celestial sphere of Sect. 4.1: four quadrants and a
- *     graticule, hit where the ray crosses r = r_cs.
+ *     graticule, hit where the ray crosses r = r_cs;
+ *   - the q-metric of the appendix (eq:q-metric, written with signature
+ *     (-,+,+,+)) as a second static axisymmetric spacetime for null rays.
  * Readings where the paper is silent or garbled (sign of p_r, the printed
  * redshift being -1/g, step control, event location, tolerances) are listed
  * in the design notes; the constants used here are the same readings.
@@ -95,20 +97,71 @@ static void metric_cov_derivs(double M, double a, double r, double th, double dr
            + 2.0 * M * r * a * a * (4.0 * s * s * s * c * Sig - s * s * s * s * Sig_th) / Sig2;
 }
 
-void ko_metric_inv(double M, double a, double r, double th, double gi[5], double dgi_dr[5],
-                   double dgi_dth[5])
+/* The q-metric (eq:q-metric) with f = 1 - 2M/r, D = 1 + M^2 sin^2/(r^2 - 2Mr),
+   P = q (2 + q):  g_tt = -f^(1+q), g_rr = f^-(1+q) D^-P, g_thth = r^2 f^-q D^-P,
+   g_phph = r^2 sin^2 f^-q; and its r- and theta-derivatives (may be NULL). */
+static void qmetric_cov(double M, double q, double r, double th, double g[5], double dr[5], double dth[5])
+{
+    double s = sin(th), c = cos(th);
+    double f = 1.0 - 2.0 * M / r;
+    double rf = r * r - 2.0 * M * r;
+    double D = 1.0 + M * M * s * s / rf;
+    double P = q * (2.0 + q);
+    double fq = pow(f, q), DmP = pow(D, -P);
+    g[0] = -f * fq;
+    g[1] = 0.0;
+    g[2] = DmP / (f * fq);
+    g[3] = r * r * DmP / fq;
+    g[4] = r * r * s * s / fq;
+    if (dr) {
+        double lf_r = 2.0 * M / (r * r) / f;                       /* d ln f / dr */
+        double lD_r = -M * M * s * s * (2.0 * r - 2.0 * M) / (rf * rf) / D;
+        double lD_th = 2.0 * M * M * s * c / rf / D;
+        dr[0] = g[0] * (1.0 + q) * lf_r;
+        dth[0] = 0.0;
+        dr[1] = dth[1] = 0.0;
+        dr[2] = g[2] * (-(1.0 + q) * lf_r - P * lD_r);
+        dth[2] = g[2] * (-P * lD_th);
+        dr[3] = g[3] * (2.0 / r - q * lf_r - P * lD_r);
+        dth[3] = g[3] * (-P * lD_th);
+        dr[4] = g[4] * (2.0 / r - q * lf_r);
+        dth[4] = 2.0 * r * r * s * c / fq;
+    }
+}
+
+void ko_metric_cov_k(int32_t kind, double M, double a, double q, double r, double th, double g[5])
+{
+    if (kind == KO_QMETRIC)
+        qmetric_cov(M, q, r, th, g, NULL, NULL);
+    else
+        ko_metric_cov(M, a, r, th, g);
+}
+
+void ko_metric_derivs_k(int32_t kind, double M, double a, double q, double r, double th, double dr[5],
+                        double dth[5])
+{
+    if (kind == KO_QMETRIC) {
+        double g[5];
+        qmetric_cov(M, q, r, th, g, dr, dth);
+    } else {
+        metric_cov_derivs(M, a, r, th, dr, dth);
+    }
+}
+
+void ko_metric_inv_k(int32_t kind, double M, double a, double q, double r, double th, double gi[5],
+                     double dgi_dr[5], double dgi_dth[5])
 {
     double g[5], dr[5], dth[5];
-    ko_metric_cov(M, a, r, th, g);
-    metric_cov_derivs(M, a, r, th, dr, dth);
+    ko_metric_cov_k(kind, M, a, q, r, th, g);
+    ko_metric_derivs_k(kind, M, a, q, r, th, dr, dth);
 
     /* The metric is block diagonal: a (t, phi) 2x2 block plus g_rr, g_thth. */
     double det = g[0] * g[4] - g[1] * g[1];
     double p = g[4] / det;  /* g^tt   */
-    double q = -g[1] / det; /* g^tphi */
+    double u = -g[1] / det; /* g^tphi */
     double w = g[0] / det;  /* g^phph */
     gi[0] = p;
-    gi[1] = q;
+    gi[1] = u;
     gi[2] = 1.0 / g[2];
     gi[3] = 1.0 / g[3];
     gi[4] = w;
@@ -118,12 +171,18 @@ void ko_metric_inv(double M, double a, double r, double th, double gi[5], double
     double *o[2] = {dgi_dr, dgi_dth};
     for (int k = 0; k < 2; ++k) {
         double dA = d[k][0], dB = d[k][1], dC = d[k][4];
-        o[k][0] = -(p * p * dA + 2.0 * p * q * dB + q * q * dC);
-        o[k][1] = -(p * q * dA + (q * q + p * w) * dB + q * w * dC);
-        o[k][4] = -(q * q * dA + 2.0 * q * w * dB + w * w * dC);
+        o[k][0] = -(p * p * dA + 2.0 * p * u * dB + u * u * dC);
+        o[k][1] = -(p * u * dA + (u * u + p * w) * dB + u * w * dC);
+        o[k][4] = -(u * u * dA + 2.0 * u * w * dB + w * w * dC);
         o[k][2] = -d[k][2] / (g[2] * g[2]);
         o[k][3] = -d[k][3] / (g[3] * g[3]);
     }
+}
+
+void ko_metric_inv(double M, double a, double r, double th, double gi[5], double dgi_dr[5],
+                   double dgi_dth[5])
+{
+    ko_metric_inv_k(KO_KERR, M, a, 0.0, r, th, gi, dgi_dr, dgi_dth);
 }
 
 double ko_horizon(double M, double a) { return M + sqrt(M * M - a * a); }
@@ -132,13 +191,30 @@ double ko_horizon(double M, double a) { return M + sqrt(M * M - a * a); }
 /* Hamiltonian (eq:ligH) and Hamilton's equations (eq:edm, Sect. 2.1).        */
 /* ------------------------------------------------------------------------ */
 
-double ko_hamiltonian(double M, double a, const double z[5], double E, double L)
+double ko_hamiltonian_k(int32_t kind, double M, double a, double q, const double z[5], double E, double L)
 {
     double gi[5], dr[5], dth[5];
-    ko_metric_inv(M, a, z[0], z[1], gi, dr, dth);
+    ko_metric_inv_k(kind, M, a, q, z[0], z[1], gi, dr, dth);
     double pt = -E, pph = L, pr = z[3], pth = z[4];
     return 0.5 * (gi[0] * pt * pt + 2.0 * gi[1] * pt * pph + gi[2] * pr * pr
                   + gi[3] * pth * pth + gi[4] * pph * pph);
+}
+
+double ko_hamiltonian(double M, double a, const double z[5], double E, double L)
+{
+    return ko_hamiltonian_k(KO_KERR, M, a, 0.0, z, E, L);
+}
+
+/* For the q-metric (diagonal): |2H| over the sum of the magnitudes of the
+   four terms g^{mu mu} p_mu^2. */
+double ko_hamiltonian_rel_k(int32_t kind, double M, double a, double q, const double z[5], double E,
+                            double L)
+{
+    if (kind != KO_QMETRIC) return ko_hamiltonian_rel(M, a, z, E, L);
+    double gi[5], dr[5], dth[5];
+    ko_metric_inv_k(kind, M, a, q, z[0], z[1], gi, dr, dth);
+    double t[4] = {gi[0] * E * E, gi[2] * z[3] * z[3], gi[3] * z[4] * z[4], gi[4] * L * L};
+    return fabs(t[0] + t[1] + t[2] + t[3]) / (fabs(t[0]) + t[1] + t[2] + t[3]);
 }
 
 double ko_hamiltonian_rel(double M, double a, const double z[5], double E, double L)
@@ -154,10 +230,10 @@ double ko_hamiltonian_rel(double M, double a, const double z[5], double E, doubl
     return fabs(2.0 * Sig * H) / D;
 }
 
-void ko_rhs(double M, double a, const double z[5], double E, double L, double out[6])
+void ko_rhs_k(int32_t kind, double M, double a, double q, const double z[5], double E, double L, double out[6])
 {
     double gi[5], dr[5], dth[5];
-    ko_metric_inv(M, a, z[0], z[1], gi, dr, dth);
+    ko_metric_inv_k(kind, M, a, q, z[0], z[1], gi, dr, dth);
     double pt = -E, pph = L, pr = z[3], pth = z[4];
     out[0] = gi[2] * pr;                 /* r dot      = g^rr p_r               */
     out[1] = gi[3] * pth;                /* theta dot  = g^thth p_theta         */
@@ -169,14 +245,20 @@ void ko_rhs(double M, double a, const double z[5], double E, double L, double ou
     out[5] = gi[0] * pt + gi[1] * pph;   /* t dot */
 }
 
+void ko_rhs(double M, double a, const double z[5], double E, double L, double out[6])
+{
+    ko_rhs_k(KO_KERR, M, a, 0.0, z, E, L, out);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Camera: eq:matrix, eq:pimf and the second eq:momentums (Sect. 2.3).       */
 /* ------------------------------------------------------------------------ */
 
-int ko_camera_ray(double M, double a, double r0, double incl, double x, double y, double out[7])
+int ko_camera_ray_k(int32_t kind, double M, double a, double q, double r0, double incl, double x, double y,
+                    double out[7])
 {
     double g[5];
-    ko_metric_cov(M, a, r0, incl, g);
+    ko_metric_cov_k(kind, M, a, q, r0, incl, g);
     double At = sqrt(g[4] / (g[1] * g[1] - g[0] * g[4]));
     /* observer-frame components with P^t = 1 (eq:pimf): */
     double Pth = y / r0;
@@ -193,6 +275,11 @@ int ko_camera_ray(double M, double a, double r0, double incl, double x, double y
     out[5] = E;
     out[6] = L;
     return rad > 0.0 ? 0 : 1;
+}
+
+int ko_camera_ray(double M, double a, double r0, double incl, double x, double y, double out[7])
+{
+    return ko_camera_ray_k(KO_KERR, M, a, 0.0, r0, incl, x, y, out);
 }
 
 void ko_pixel_xy(const ko_setup *s, int32_t i, int32_t j, double *x, double *y)
@@ -466,7 +553,8 @@ void ko_tableau(int32_t method, double A[36], double b_prop[6], double b_emb[6])
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-    double M, a, E, L;
+    double M, a, E, L, q;
+    int kind;
     int s_time; /* 1: field scaled by d(lambda)/ds = Delta / r */
 } ray_ctx;
 
@@ -474,7 +562,7 @@ static void ray_field(const double *z, double *dz, const void *vctx)
 {
     const ray_ctx *c = (const ray_ctx *)vctx;
     double out[6];
-    ko_rhs(c->M, c->a, z, c->E, c->L, out);
+    ko_rhs_k(c->kind, c->M, c->a, c->q, z, c->E, c->L, out);
     double w = 1.0;
     if (c->s_time) {
         double r = z[0];
@@ -604,7 +692,7 @@ static int64_t trace_ray(const ko_setup *s, double x, double y, const ko_out *o,
     double maxabs = NaN, maxrel = NaN;
 
     double init[7];
-    int invalid = ko_camera_ray(s->M, s->a, s->r_obs, s->incl, x, y, init);
+    int invalid = ko_camera_ray_k(s->metric, s->M, s->a, s->q, s->r_obs, s->incl, x, y, init);
     double z[5] = {init[0], init[1], init[2], init[3], init[4]};
     double thf = z[1], phf = z[2];
 
@@ -614,6 +702,8 @@ static int64_t trace_ray(const ko_setup *s, double x, double y, const ko_out *o,
     t.ctx.a = s->a;
     t.ctx.E = init[5];
     t.ctx.L = init[6];
+    t.ctx.kind = s->metric;
+    t.ctx.q = s->q;
     t.ctx.s_time = (s->method == KO_RK4_S);
     t.evals = 0;
 
@@ -624,7 +714,7 @@ static int64_t trace_ray(const ko_setup *s, double x, double y, const ko_out *o,
 
     {
         const double E = init[5], L = init[6];
-        const double r_cap = ko_horizon(s->M, s->a) + s->cap_buffer;
+        const double r_cap = (s->metric == KO_QMETRIC ? 2.0 * s->M : ko_horizon(s->M, s->a)) + s->cap_buffer;
         const int dp = (s->method != KO_RK4_S); /* adaptive */
         const double expo = controller_exponent(s->method);
         double k1[5], zn[5], kn[5], e[5];
@@ -636,8 +726,8 @@ static int64_t trace_ray(const ko_setup *s, double x, double y, const ko_out *o,
 
         ray_field(z, k1, &t.ctx);
         t.evals = 1;
-        maxabs = fabs(ko_hamiltonian(s->M, s->a, z, E, L));
-        maxrel = ko_hamiltonian_rel(s->M, s->a, z, E, L);
+        maxabs = fabs(ko_hamiltonian_k(s->metric, s->M, s->a, s->q, z, E, L));
+        maxrel = ko_hamiltonian_rel_k(s->metric, s->M, s->a, s->q, z, E, L);
         if (traj && npts < maxp) {
             double *p = traj + 6 * npts++;
             p[0] = 0.0;
@@ -684,8 +774,8 @@ static int64_t trace_ray(const ko_setup *s, double x, double y, const ko_out *o,
 
             /* accepted step z -> zn */
             ++nsteps;
-            double ha = fabs(ko_hamiltonian(s->M, s->a, zn, E, L));
-            double hr = ko_hamiltonian_rel(s->M, s->a, zn, E, L);
+            double ha = fabs(ko_hamiltonian_k(s->metric, s->M, s->a, s->q, zn, E, L));
+            double hr = ko_hamiltonian_rel_k(s->metric, s->M, s->a, s->q, zn, E, L);
             if (ha > maxabs) maxabs = ha;
             if (hr > maxrel) maxrel = hr;
             if (traj && npts < maxp) {

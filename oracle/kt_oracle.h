@@ -32,6 +32,10 @@ extern "C" {
 #define KO_STEPFAIL 4
 #define KO_INVALID 5
 
+/* spacetimes */
+#define KO_KERR 0
+#define KO_QMETRIC 1 /* the appendix's q-metric; M is its m, the mass is m (1 + q) */
+
 /* integrators */
 #define KO_RK4_S 0 /* classic RK4, fixed step in s with d(lambda)/ds = Delta/r */
 #define KO_DP45 1  /* Dormand-Prince 5(4), adaptive, FSAL */
@@ -40,8 +44,10 @@ extern "C" {
 #define KO_BS 4    /* Bulirsch-Stoer: modified midpoint n = 2,4,..,10, extrapolated (order 10) */
 
 typedef struct {
-    /* spacetime */
+    /* spacetime: Kerr (M, a) or the q-metric (M, q) */
     double M, a;
+    int32_t metric;
+    double q;
     /* camera: observer at (r_obs, theta0 = incl, phi0 = 0); image plane
        [-fov_x, fov_x] x [-fov_y, fov_y] sampled at nx x ny pixel centres */
     double r_obs, incl, fov_x, fov_y;
@@ -154,6 +160,23 @@ double ko_disk_omega(double M, double a, double r, int32_t rotation, double l0);
 
 /* Emitted intensity at radius r of the disk for the given model. */
 double ko_emissivity(double M, double r, double r_in, double r_out, double emis_q, int32_t model);
+
+/* The same for either spacetime (kind KO_KERR uses a, KO_QMETRIC uses q):
+   covariant components, their r- and theta-derivatives, the contravariant
+   components with derivatives, H, |H|_rel (for the q-metric |2H| over the
+   sum of the magnitudes of its four terms), Hamilton's equations and the
+   camera. */
+void ko_metric_cov_k(int32_t kind, double M, double a, double q, double r, double th, double g[5]);
+void ko_metric_derivs_k(int32_t kind, double M, double a, double q, double r, double th, double dr[5],
+                        double dth[5]);
+void ko_metric_inv_k(int32_t kind, double M, double a, double q, double r, double th, double gi[5],
+                     double dgi_dr[5], double dgi_dth[5]);
+double ko_hamiltonian_k(int32_t kind, double M, double a, double q, const double z[5], double E, double L);
+double ko_hamiltonian_rel_k(int32_t kind, double M, double a, double q, const double z[5], double E,
+                            double L);
+void ko_rhs_k(int32_t kind, double M, double a, double q, const double z[5], double E, double L, double out[6]);
+int ko_camera_ray_k(int32_t kind, double M, double a, double q, double r0, double incl, double x, double y,
+                    double out[7]);
 
 /* Outer horizon r_+ = M + sqrt(M^2 - a^2). */
 double ko_horizon(double M, double a);

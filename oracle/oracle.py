@@ -20,12 +20,13 @@ LIB_PATH = os.environ.get("KT_ORACLE_LIB") or os.path.join(HERE, "libkt_oracle.s
 ESCAPED, CAPTURED, DISK, MAXSTEPS, STEPFAIL, INVALID = range(6)
 RK4_S, DP45, RKF45, CK45, BS = 0, 1, 2, 3, 4
 SKY_NONE, SKY_GREEN, SKY_RED, SKY_BLUE, SKY_YELLOW, SKY_LINE = range(6)
+KERR, QMETRIC = 0, 1
 BS_COLUMNS = 5
 
 
 class _Setup(C.Structure):
     _fields_ = [
-        ("M", C.c_double), ("a", C.c_double),
+        ("M", C.c_double), ("a", C.c_double), ("metric", C.c_int32), ("q", C.c_double),
         ("r_obs", C.c_double), ("incl", C.c_double), ("fov_x", C.c_double), ("fov_y", C.c_double),
         ("nx", C.c_int32), ("ny", C.c_int32),
         ("method", C.c_int32),
@@ -61,6 +62,8 @@ class Setup:
     """Oracle problem description (one image)."""
     M: float = 1.0
     a: float = 0.0
+    metric: int = 0                # 0 Kerr, 1 q-metric
+    q: float = 0.0
     r_obs: float = 1000.0
     incl: float = math.pi / 2
     fov_x: float = 10.0
@@ -135,6 +138,15 @@ def lib():
         L.ko_sky_code.restype = C.c_int
         L.ko_disk_omega.argtypes = [C.c_double] * 3 + [C.c_int32, C.c_double]
         L.ko_disk_omega.restype = C.c_double
+        L.ko_metric_cov_k.argtypes = [C.c_int32] + [C.c_double] * 5 + [dp]
+        L.ko_metric_derivs_k.argtypes = [C.c_int32] + [C.c_double] * 5 + [dp, dp]
+        L.ko_hamiltonian_k.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, dp, C.c_double, C.c_double]
+        L.ko_hamiltonian_k.restype = C.c_double
+        L.ko_hamiltonian_rel_k.argtypes = L.ko_hamiltonian_k.argtypes
+        L.ko_hamiltonian_rel_k.restype = C.c_double
+        L.ko_rhs_k.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, dp, C.c_double, C.c_double, dp]
+        L.ko_camera_ray_k.argtypes = [C.c_int32] + [C.c_double] * 7 + [dp]
+        L.ko_camera_ray_k.restype = C.c_int
         L.ko_emissivity.argtypes = [C.c_double] * 5 + [C.c_int32]
         L.ko_emissivity.restype = C.c_double
         _lib = L
@@ -248,6 +260,41 @@ def ring_flags(nx, ny, deflection):
 
 def sky_code(theta, phi, grid_deg=6.0, line_deg=0.25):
     return lib().ko_sky_code(theta, phi, grid_deg, line_deg)
+
+
+def metric_cov_k(kind, M, a, q, r, th):
+    g = np.zeros(5)
+    lib().ko_metric_cov_k(kind, M, a, q, r, th, _dptr(g))
+    return g
+
+
+def metric_derivs_k(kind, M, a, q, r, th):
+    dr, dth = np.zeros(5), np.zeros(5)
+    lib().ko_metric_derivs_k(kind, M, a, q, r, th, _dptr(dr), _dptr(dth))
+    return dr, dth
+
+
+def hamiltonian_k(kind, M, a, q, state, E, L):
+    z = np.ascontiguousarray(state, dtype=np.float64)
+    return lib().ko_hamiltonian_k(kind, M, a, q, _dptr(z), E, L)
+
+
+def hamiltonian_rel_k(kind, M, a, q, state, E, L):
+    z = np.ascontiguousarray(state, dtype=np.float64)
+    return lib().ko_hamiltonian_rel_k(kind, M, a, q, _dptr(z), E, L)
+
+
+def rhs_k(kind, M, a, q, state, E, L):
+    z = np.ascontiguousarray(state, dtype=np.float64)
+    out = np.zeros(6)
+    lib().ko_rhs_k(kind, M, a, q, _dptr(z), E, L, _dptr(out))
+    return out
+
+
+def camera_ray_k(kind, M, a, q, r_obs, incl, x, y):
+    out = np.zeros(7)
+    bad = lib().ko_camera_ray_k(kind, M, a, q, r_obs, incl, x, y, _dptr(out))
+    return out, bool(bad)
 
 
 def emissivity(M, r, r_in, r_out, emis_q=2.0, model=0):
