@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define KT_VERSION_NUMBER 130
+#define KT_VERSION_NUMBER 140
 
 /* return codes */
 #define KT_OK 0
@@ -75,9 +75,19 @@ typedef struct kt_camera {
     int32_t nx, ny; /* resolution, >= 1 each, nx*ny < 2^31 */
 } kt_camera;
 
-/* Kerr spacetime (eq:Kerr): mass M >= 0, spin |a| <= M. */
+/* The spacetime.  KT_METRIC_KERR: Kerr (eq:Kerr), mass M >= 0, spin |a| <= M.
+   KT_METRIC_Q: the q-metric of the appendix (eq:q-metric, taken with
+   signature (-,+,+,+)), a static axisymmetric vacuum with parameter M (its
+   mass is M (1 + q)) and quadrupole parameter q > -1, a = 0; rays are
+   captured at r < 2M + capture_buffer.  The q-metric runs single images
+   (not kt_render_batch) with the adaptive FP64 schemes, without a disk
+   (its redshift model is Kerr's), and is not differentiated by kt_adjoint. */
+#define KT_METRIC_KERR 0
+#define KT_METRIC_Q 1
 typedef struct kt_spacetime {
     double M, a;
+    int32_t metric;
+    double q;
 } kt_spacetime;
 
 /* Thin equatorial disk (Sect. 5). Emissivity (M/r)^emis_index.  Circular

@@ -48,12 +48,22 @@ int device_cus() {
     return cache[dev];
 }
 
-double horizon(double M, double a) { return M + std::sqrt(M * M - a * a); }
+double horizon(const kt_spacetime* st) {
+    if (st->metric == KT_METRIC_Q) return 2.0 * st->M;
+    return st->M + std::sqrt(st->M * st->M - st->a * st->a);
+}
 
 int validate_common(const kt_camera* cam, const kt_spacetime* st) {
     if (!cam || !st) return fail(KT_EINVAL, "camera and spacetime must not be NULL");
     if (!finite_all({cam->r_obs, cam->incl, cam->fov_x, cam->fov_y, st->M, st->a}))
         return fail(KT_EINVAL, "non-finite camera or spacetime parameter");
+    if (st->metric != KT_METRIC_KERR && st->metric != KT_METRIC_Q)
+        return fail(KT_EINVAL, "unknown metric %d", st->metric);
+    if (st->metric == KT_METRIC_Q) {
+        if (!std::isfinite(st->q) || !(st->q > -1.0)) return fail(KT_EINVAL, "the q-metric needs finite q > -1");
+        if (!(st->M > 0.0)) return fail(KT_EINVAL, "the q-metric needs M > 0");
+        if (st->a != 0.0) return fail(KT_EINVAL, "the q-metric is static: a must be 0");
+    }
     if (!(st->M >= 0.0)) return fail(KT_EINVAL, "M must be >= 0 (got %g)", st->M);
     if (st->a * st->a > st->M * st->M) return fail(KT_EINVAL, "|a| must be <= M (a=%g, M=%g)", st->a, st->M);
     if (!(cam->incl > 0.0 && cam->incl < M_PI))
@@ -70,6 +80,30 @@ int validate_common(const kt_camera* cam, const kt_spacetime* st) {
 void camera_constants(const kt_camera* cam, const kt_spacetime* st, kt::Image& im) {
     const double M = st->M, a = st->a, r0 = cam->r_obs;
     const double s = std::sin(cam->incl), c = std::cos(cam->incl);
+    im.metric = st->metric;
+    im.q = st->q;
+    if (st->metric == KT_METRIC_Q) {
+        // static observer of the q-metric: E0 = sqrt(-g_tt), no frame dragging
+        const double f = 1.0 - 2.0 * M / r0, q = st->q, P = q * (2.0 + q);
+        const double D = 1.0 + M * M * s * s / (r0 * r0 - 2.0 * M * r0);
+        const double fq = std::pow(f, q), DmP = std::pow(D, -P);
+        im.E0 = std::sqrt(f * fq);
+        im.cE = 0.0;
+        im.cL = -std::sqrt(r0 * r0 * s * s / fq) / r0;
+        im.cth = std::sqrt(r0 * r0 * DmP / fq) / r0;
+        im.g_rr = DmP / (f * fq);
+        im.r0 = r0;
+        im.incl = cam->incl;
+        im.fov_x = cam->fov_x;
+        im.fov_y = cam->fov_y;
+        im.dx = 2.0 * cam->fov_x / cam->nx;
+        im.dy = 2.0 * cam->fov_y / cam->ny;
+        im.nx = cam->nx;
+        im.ny = cam->ny;
+        im.M = M;
+        im.a = im.a2 = im.two_a2 = 0.0;
+        return;
+    }
     const double Sig = r0 * r0 + a * a * c * c;
     const double Del = r0 * r0 - 2.0 * M * r0 + a * a;
     const double g_tph = -2.0 * M * a * r0 * s * s / Sig;
@@ -144,7 +178,12 @@ int make_image(const kt_camera* camera, const kt_spacetime* spacetime, const kt_
     if (rc) return rc;
     std::memset(&im, 0, sizeof im);
     camera_constants(camera, spacetime, im);
-    const double r_plus = horizon(spacetime->M, spacetime->a);
+    const double r_plus = horizon(spacetime);
+    if (spacetime->metric == KT_METRIC_Q) {
+        if (integ->method == KT_RK4_S || integ->precision != KT_FP64)
+            return fail(KT_EINVAL, "the q-metric runs with the adaptive FP64 schemes");
+        if (disk && disk->enabled) return fail(KT_EINVAL, "the disk's redshift model needs the Kerr metric");
+    }
     const double r_cap = r_plus + integ->capture_buffer;
     if (!(camera->r_obs > r_cap)) return fail(KT_EINVAL, "r_obs must exceed r_+ + capture_buffer");
     const double r_esc = integ->r_escape == 0.0 ? 1.1 * camera->r_obs : integ->r_escape;
@@ -328,6 +367,8 @@ int make_table(int32_t n_images, const kt_image* images, const kt_integrator* in
     int64_t first = 0;
     for (int32_t k = 0; k < n_images; ++k) {
         const kt_image& in = images[k];
+        if (in.spacetime.metric != KT_METRIC_KERR)
+            return fail(KT_EINVAL, "image %d: batches run the Kerr metric", k);
         int rc = make_image(&in.camera, &in.spacetime, &in.disk, &in.source, integ, want_ring, table[k]);
         if (rc) {
             char msg[512];
@@ -373,7 +414,7 @@ int kt_init_rays(const kt_camera* camera, const kt_spacetime* spacetime, double*
     int rc = validate_common(camera, spacetime);
     if (rc) return rc;
     if (!state || !invalid) return fail(KT_EINVAL, "state and invalid must not be NULL");
-    if (!(camera->r_obs > horizon(spacetime->M, spacetime->a)))
+    if (!(camera->r_obs > horizon(spacetime)))
         return fail(KT_EINVAL, "r_obs must lie outside the horizon");
     kt::Params p;
     std::memset(&p, 0, sizeof p);
@@ -438,6 +479,7 @@ int kt_adjoint(const kt_camera* camera, const kt_spacetime* spacetime, const kt_
         return fail(KT_EINVAL, "the adjoint follows the KT_DP45 / KT_FP64 integration");
     if (!disk->enabled) return fail(KT_EINVAL, "the adjoint differentiates a disk image: enable the disk");
     if (!(spacetime->M > 0.0)) return fail(KT_EINVAL, "the adjoint needs M > 0");
+    if (spacetime->metric != KT_METRIC_KERR) return fail(KT_EINVAL, "the adjoint differentiates Kerr images");
     if (!fate || !cot_intensity) return fail(KT_EINVAL, "fate and cot_intensity must not be NULL");
     kt::Image im;
     if ((rc = make_image(camera, spacetime, disk, nullptr, integ, false, im))) return rc;

@@ -260,12 +260,94 @@ __device__ __forceinline__ void rhs_sc(const Spacetime& st, const RayConst& rc, 
 }
 
 // The RHS at z with sin/cos of theta computed from theta itself.
-template <bool WANT_DIAG, bool S_TIME>
-__device__ __forceinline__ void rhs(const Spacetime& st, const RayConst& rc, const double z[5],
-                                    double dz[5], Diag* dg) {
+// ---------------------------------------------------------------------------
+// The q-metric of the appendix (eq:q-metric, signature (-,+,+,+)): static and
+// diagonal, with f = 1 - 2M/r, D = 1 + M^2 sin^2 / (r^2 f), P = q (2 + q),
+//   g^tt = -f^-(1+q), g^rr = f^(1+q) D^P, g^thth = f^q D^P / r^2,
+//   g^phph = f^q / (r^2 sin^2).
+// H = (-E^2 G + p_r^2 A + p_th^2 B + L^2 C) / 2 with those magnitudes, and
+// each term's r- and theta-derivative is the term times the log-derivative
+// of its factor.
+// ---------------------------------------------------------------------------
+struct QSpacetime {
+    double M, q, P;
+};
+
+__device__ __forceinline__ RayConst make_ray_const(const QSpacetime&, double E, double L) {
+    RayConst rc;
+    rc.E = E;
+    rc.L = L;
+    rc.aE = 0.0;
+    rc.aL = 0.0;
+    rc.twoE = 2.0 * E;
+    return rc;
+}
+
+template <bool WANT_DIAG>
+__device__ __forceinline__ void rhs_q(const QSpacetime& st, const RayConst& rc, const double z[5], double s,
+                                      double c, double dz[5], Diag* dg) {
+    const double r = z[0], pr = z[3], pth = z[4], M = st.M;
+    const double rf = r * (r - 2.0 * M);  // r^2 f
+    // 1/r, 1/(r^2 f) and 1/sin from one reciprocal of their product
+    const double X = r * rf;
+    const double qX = rcp(X * s);
+    const double ir = rf * s * qX;
+    const double irf = r * s * qX;
+    const double is = X * qX;
+    const double f = rf * ir * ir;
+    const double Dm1 = (M * M) * (s * s) * irf;  // D - 1
+    const double D = 1.0 + Dm1;
+    const double lf = log(f);
+    const double fq = exp(st.q * lf);           // f^q
+    const double DP = exp(st.P * log1p(Dm1));   // D^P
+    const double iD = rcp(D);
+    const double ir2 = ir * ir;
+    const double A = f * fq * DP;
+    const double B = fq * DP * ir2;
+    const double C = fq * ir2 * is * is;
+    const double G = rcp(f * fq);
+    const double tG = rc.E * rc.E * G, tA = pr * pr * A, tB = pth * pth * B, tC = rc.L * rc.L * C;
+    const double lf_r = 2.0 * M * irf;                          // d ln f / dr
+    const double PlD_r = -st.P * Dm1 * (2.0 * (r - M)) * irf * iD;  // P d ln D / dr
+    const double PlD_th = 2.0 * st.P * Dm1 * c * is * iD;          // P d ln D / dtheta
+    const double tAB = tA + tB, tBC = tB + tC;
+    // 2 dH/dr and 2 dH/dtheta
+    const double Hr2 = fma((1.0 + st.q) * lf_r, tG + tA, fma(st.q * lf_r, tBC, fma(PlD_r, tAB, -2.0 * ir * tBC)));
+    const double Hth2 = fma(PlD_th, tAB, -2.0 * c * is * tC);
+    dz[0] = A * pr;
+    dz[1] = B * pth;
+    dz[2] = C * rc.L;
+    dz[3] = -0.5 * Hr2;
+    dz[4] = -0.5 * Hth2;
+    if (WANT_DIAG) {
+        const double K = (tA - tG) + (tB + tC);
+        dg->H = 0.5 * K;
+        dg->rel = fabs(K) * rcp(tG + tA + tB + tC);
+        dg->s = s;
+        dg->c = c;
+    }
+}
+
+// The RHS of either spacetime at z, given sin/cos of theta.
+template <bool WANT_DIAG>
+__device__ __forceinline__ void field_at(const Spacetime& st, const RayConst& rc, const double z[5], double s,
+                                         double c, double dz[5], Diag* dg) {
+    rhs_sc<WANT_DIAG, false>(st, rc, z, s, c, dz, dg);
+}
+template <bool WANT_DIAG>
+__device__ __forceinline__ void field_at(const QSpacetime& st, const RayConst& rc, const double z[5], double s,
+                                         double c, double dz[5], Diag* dg) {
+    rhs_q<WANT_DIAG>(st, rc, z, s, c, dz, dg);
+}
+
+template <bool WANT_DIAG, bool S_TIME, class ST>
+__device__ __forceinline__ void rhs(const ST& st, const RayConst& rc, const double z[5], double dz[5], Diag* dg) {
     double s, c;
     sincos_theta(z[1], &s, &c);
-    rhs_sc<WANT_DIAG, S_TIME>(st, rc, z, s, c, dz, dg);
+    if constexpr (S_TIME)
+        rhs_sc<WANT_DIAG, true>(st, rc, z, s, c, dz, dg);
+    else
+        field_at<WANT_DIAG>(st, rc, z, s, c, dz, dg);
 }
 
 // sin and cos of theta0 + d from those of theta0 and the Taylor series of
@@ -375,8 +457,8 @@ __device__ __forceinline__ void rhs_split(const Spacetime& st, const Spacetime32
 // at the step's start angle th0; the last stage (D: the step's end, whose
 // sin/cos seed the next step) computes them from theta itself, so the
 // shifts never accumulate.
-template <bool SPLIT, bool D>
-__device__ __forceinline__ void eval_rhs(const Spacetime& st, const Spacetime32* sf, const RayConst& rc,
+template <bool SPLIT, bool D, class ST>
+__device__ __forceinline__ void eval_rhs(const ST& st, const Spacetime32* sf, const RayConst& rc,
                                          const double* z, double th0, double s0, double c0, double* out,
                                          Diag* dg) {
     double s, c;
@@ -387,7 +469,7 @@ __device__ __forceinline__ void eval_rhs(const Spacetime& st, const Spacetime32*
     if constexpr (SPLIT)
         rhs_split<D>(st, *sf, rc, z, s, c, out, dg);
     else
-        rhs_sc<D, false>(st, rc, z, s, c, out, dg);
+        field_at<D>(st, rc, z, s, c, out, dg);
 }
 
 // ---------------------------------------------------------------------------
@@ -413,8 +495,8 @@ constexpr double E1 = 71.0 / 57600, E3 = -71.0 / 16695, E4 = 71.0 / 1920,
 // solution yn, kn = f(yn) with its diagnostics, and the error vector err.
 // Six RHS evaluations.
 // (s0, c0) are sin and cos of y[1].
-template <bool SPLIT = false>
-__device__ __forceinline__ void dp45_step(const Spacetime& st, const RayConst& rc, const double y[5],
+template <bool SPLIT = false, class ST = Spacetime>
+__device__ __forceinline__ void dp45_step(const ST& st, const RayConst& rc, const double y[5],
                                           const double k1[5], double s0, double c0, double h, double yn[5],
                                           double kn[5], double err[5], Diag* dg,
                                           const Spacetime32* sf = nullptr) {
@@ -504,8 +586,8 @@ struct CashKarp45 {
 // propagated solution yn, kn = f(yn) with its diagnostics, and err = h sum
 // e_j k_j.  Inner stages take sin/cos of theta by angle addition from
 // (s0, c0); f(yn) computes them from theta.  Six RHS evaluations.
-template <class TAB>
-__device__ __forceinline__ void erk6_step(const Spacetime& st, const RayConst& rc, const double y[5],
+template <class TAB, class ST>
+__device__ __forceinline__ void erk6_step(const ST& st, const RayConst& rc, const double y[5],
                                           const double k1[5], double s0, double c0, double h, double yn[5],
                                           double kn[5], double err[5], Diag* dg) {
     double k[6][5];
@@ -556,7 +638,8 @@ constexpr double bs_weight(int k, int j) {
     return 1.0 / (static_cast<double>((k + 1) * (k + 1)) / static_cast<double>((k - j + 1) * (k - j + 1)) - 1.0);
 }
 
-__device__ __forceinline__ void bs_step(const Spacetime& st, const RayConst& rc, const double y[5],
+template <class ST>
+__device__ __forceinline__ void bs_step(const ST& st, const RayConst& rc, const double y[5],
                                         const double k1[5], double h, double yn[5], double kn[5],
                                         double err[5], Diag* dg) {
     double T[BS_COLUMNS][5];  // row k of the tableau after chain k

@@ -23,8 +23,10 @@ struct Outputs {
 // Everything that belongs to one image: spacetime, camera constants, disk,
 // source, and where its rays sit in the batch.
 struct Image {
-    // spacetime (eq:Kerr) and the end radii
+    // spacetime (eq:Kerr; or the q-metric, metric = KT_METRIC_Q) and the end radii
     double M, a, a2, two_a2;
+    int32_t metric;
+    double q;
     double r_cap, r_esc;
     // camera and per-image camera constants (Sect. 2.3)
     double r0, incl, fov_x, fov_y, dx, dy;

@@ -146,8 +146,8 @@ enum : int {
 };
 constexpr int BLOCK_MAX = 256;
 
-template <int METHOD>
-__device__ __forceinline__ void take_step(const Spacetime& st, const RayConst& rc, const double y[5],
+template <int METHOD, class ST>
+__device__ __forceinline__ void take_step(const ST& st, const RayConst& rc, const double y[5],
                                           const double k1[5], double s0, double c0, double h, double yn[5],
                                           double kn[5], double er[5], Diag* dg) {
     if constexpr (METHOD == KT_DP45) {
@@ -165,13 +165,15 @@ __device__ __forceinline__ void take_step(const Spacetime& st, const RayConst& r
     }
 }
 
-template <int METHOD, int PREC, bool BATCH>
+template <int METHOD, int PREC, bool BATCH, bool QMET = false>
 __global__ void __launch_bounds__(BLOCK_MAX) __attribute__((amdgpu_waves_per_eu(KT_WAVES_PER_EU)))
 trace_kernel(const Hot hp) {
+    static_assert(!(QMET && (BATCH || METHOD == KT_RK4_S || PREC != KT_FP64)),
+                  "the q-metric runs single images with the adaptive FP64 schemes");
     constexpr int EVALS_PER_STEP = evals_per_step<METHOD>();
     constexpr bool ADAPTIVE = (METHOD != KT_RK4_S);
     constexpr bool S_TIME = (METHOD == KT_RK4_S);
-    constexpr bool MIXED = (PREC == KT_MIXED) && (METHOD == KT_DP45);
+    constexpr bool MIXED = (PREC == KT_MIXED) && (METHOD == KT_DP45) && !QMET;
     __shared__ double cold[N_COLD][BLOCK_MAX];
     const int tid = threadIdx.x;
 #define COLD(f) cold[f][tid]
@@ -253,7 +255,13 @@ trace_kernel(const Hot hp) {
         if (ray < 0) continue;
 
         // ---- one step per busy lane ----------------------------------------
-        const Spacetime st = li.st;
+        // the q-metric carries (q, q(2+q)) in the spacetime's (a, a^2) slots
+        const auto st = [&]() {
+            if constexpr (QMET)
+                return QSpacetime{li.st.M, li.st.a, li.st.a2};
+            else
+                return li.st;
+        }();
         const RayConst rc = make_ray_const(st, E, L);
         const double NaN = __builtin_nan("");
         int fate = -1;  // >= 0 once the ray ends
@@ -756,6 +764,11 @@ static Hot make_hot(const Params& p) {
     hp.a = im.a;
     hp.a2 = im.a2;
     hp.two_a2 = im.two_a2;
+    if (im.metric == KT_METRIC_Q) {
+        hp.a = im.q;
+        hp.a2 = im.q * (2.0 + im.q);
+        hp.two_a2 = 0.0;
+    }
     hp.rtol = p.rtol;
     hp.atol = p.atol;
     hp.r_cap = im.r_cap;
@@ -774,6 +787,12 @@ static Hot make_hot(const Params& p) {
 
 template <int METHOD, int PREC>
 static void launch_variant(const Params& p, const Hot& hp, int grid, int block, hipStream_t s) {
+    if constexpr (PREC == KT_FP64 && METHOD != KT_RK4_S) {
+        if (p.img0.metric == KT_METRIC_Q) {
+            hipLaunchKernelGGL((trace_kernel<METHOD, PREC, false, true>), dim3(grid), dim3(block), 0, s, hp);
+            return;
+        }
+    }
     if (p.n_images > 1)
         hipLaunchKernelGGL((trace_kernel<METHOD, PREC, true>), dim3(grid), dim3(block), 0, s, hp);
     else
@@ -815,6 +834,10 @@ int launch_trace_fallback(const Params& p, int grid, int block, void* stream) {
 
 template <int METHOD, int PREC>
 static hipError_t occupancy_variant(const Params& p, int* nb, int block) {
+    if constexpr (PREC == KT_FP64 && METHOD != KT_RK4_S) {
+        if (p.img0.metric == KT_METRIC_Q)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, trace_kernel<METHOD, PREC, false, true>, block, 0);
+    }
     if (p.n_images > 1)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, trace_kernel<METHOD, PREC, true>, block, 0);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, trace_kernel<METHOD, PREC, false>, block, 0);

@@ -37,7 +37,7 @@ class kt_camera(C.Structure):
 
 
 class kt_spacetime(C.Structure):
-    _fields_ = [("M", C.c_double), ("a", C.c_double)]
+    _fields_ = [("M", C.c_double), ("a", C.c_double), ("metric", C.c_int32), ("q", C.c_double)]
 
 
 class kt_disk(C.Structure):
@@ -79,6 +79,7 @@ class kt_stats(C.Structure):
 OUTPUT_FIELDS = ("fate", "r_hit", "g", "intensity", "max_abs_h", "max_rel_h", "psi", "deflection",
                  "theta_f", "phi_f", "n_cross", "used_fp64", "ring", "n_steps", "n_evals", "sky")
 KEPLER, L0 = 0, 1
+METRIC_KERR, METRIC_Q = 0, 1
 EMIS_POWER, EMIS_TAPERED = 0, 1
 SKY_NONE, SKY_GREEN, SKY_RED, SKY_BLUE, SKY_YELLOW, SKY_LINE = range(6)
 
@@ -199,14 +200,14 @@ def kt_init_rays(camera, spacetime, state_ptr, invalid_ptr, stream_ptr):
 # Convenience layer over torch tensors
 # ---------------------------------------------------------------------------
 
-def make_structs(M=1.0, a=0.0, r_obs=1000.0, incl=math.pi / 2, fov_x=10.0, fov_y=10.0, nx=64,
+def make_structs(M=1.0, a=0.0, metric=0, q=0.0, r_obs=1000.0, incl=math.pi / 2, fov_x=10.0, fov_y=10.0, nx=64,
                  ny=64, method=DP45, precision=FP64, h_fixed=1.0 / 128, rtol=1e-12, atol=1e-12,
                  h_init=1.0, cap_buffer=0.01, r_escape=0.0, h_budget=1e-10, r_switch=300.0,
                  max_steps=1_000_000, disk_on=0, r_in=6.0, r_out=30.0, emis_q=2.0, rotation=0, l0=0.0,
                  emis_model=0, src_on=0, r_src=1000.0, sky_on=0, grid_deg=6.0, line_deg=0.25):
     """C structs from keyword parameters (the same names the workloads use)."""
     cam = kt_camera(r_obs, incl, fov_x, fov_y, nx, ny)
-    st = kt_spacetime(M, a)
+    st = kt_spacetime(M, a, int(metric), q)
     integ = kt_integrator(method, precision, h_fixed, rtol, atol, h_init, cap_buffer, r_escape,
                           h_budget, r_switch, int(max_steps))
     disk = kt_disk(int(disk_on), r_in, r_out, emis_q, int(rotation), l0, int(emis_model))
@@ -280,7 +281,7 @@ class Renderer:
         return self.out
 
 
-_IMAGE_KEYS = ("M", "a", "r_obs", "incl", "fov_x", "fov_y", "nx", "ny", "disk_on", "r_in", "r_out",
+_IMAGE_KEYS = ("M", "a", "metric", "q", "r_obs", "incl", "fov_x", "fov_y", "nx", "ny", "disk_on", "r_in", "r_out",
                "emis_q", "rotation", "l0", "emis_model", "src_on", "r_src", "sky_on", "grid_deg", "line_deg")
 
 

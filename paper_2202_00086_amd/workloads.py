@@ -16,6 +16,7 @@ the CPU oracle (oracle.Setup) accept these keyword names.
                             (the integrator comparison grid).
   lensing(a)                celestial-sphere lensing, r_obs = 100M, i = 90 deg.
   thin_disk_l0(a)           the Sect. 5 disk images with constant-l0 rotation.
+  qmetric_lensing(q)        the appendix's q-metric in the lensing setup.
   differentiable_disk       a = 0.7, i = 45 deg, 512x512 disk with the tapered
                             emissivity; disk_fit_target is its fit target.
   heterogeneous_batch       256 seeded Kerr disk images: sides 64..1024 in
@@ -72,6 +73,13 @@ def lensing(a=0.98, n=512, M=1.0, fov=20.0, rtol=1e-12):
                 sky_on=1, grid_deg=6.0, line_deg=0.25)
 
 
+def qmetric_lensing(q=0.5, n=512, fov=20.0, rtol=1e-12):
+    """The q-metric (mass parameter M = 1, quadrupole q) seen like the Kerr
+    lensing images: observer at r0 = 100M in the equatorial plane, the
+    coloured sphere at 1.1 r0, capture at r < 2M + 0.01M."""
+    return dict(lensing(a=0.0, n=n, fov=fov, rtol=rtol), metric=1, q=q)
+
+
 def thin_disk_l0(a=0.5, nx=2048, ny=1024, rtol=1e-12):
     """The thin-disk images of Sect. 5: r0 = 1000M, i = 85 deg, x in [-24, 24],
     y in [-12, 12], disk from the ISCO to 20M rotating with constant specific
@@ -114,7 +122,7 @@ def isco(a, M=1.0):
 
 
 # keys that describe one image; everything else is the shared integrator
-IMAGE_KEYS = ("M", "a", "r_obs", "incl", "fov_x", "fov_y", "nx", "ny", "disk_on", "r_in", "r_out",
+IMAGE_KEYS = ("M", "a", "metric", "q", "r_obs", "incl", "fov_x", "fov_y", "nx", "ny", "disk_on", "r_in", "r_out",
               "emis_q", "rotation", "l0", "emis_model", "src_on", "r_src", "sky_on", "grid_deg", "line_deg")
 
 

@@ -42,21 +42,21 @@ def test_library_exports_every_declared_symbol():
     for name in _declared_functions():
         assert hasattr(lib, name), name
     assert set(K.EXPORTED) == set(_declared_functions())
-    assert K.kt_version() == 130
+    assert K.kt_version() == 140
 
 
 def test_struct_layouts_match_header():
     """ctypes mirrors of the header structs have the C sizes."""
     from paper_2202_00086_amd import kerrtrace as K
     assert C.sizeof(K.kt_camera) == 4 * 8 + 2 * 4
-    assert C.sizeof(K.kt_spacetime) == 16
+    assert C.sizeof(K.kt_spacetime) == 32
     assert C.sizeof(K.kt_disk) == 56
     assert C.sizeof(K.kt_source) == 40
     assert C.sizeof(K.kt_integrator) == 8 + 8 * 8 + 8
     assert C.sizeof(K.kt_launch) == 16
     assert C.sizeof(K.kt_stats) == 12 * 8
     assert C.sizeof(K.kt_outputs) == 17 * 8
-    assert C.sizeof(K.kt_image) == 40 + 16 + 56 + 40
+    assert C.sizeof(K.kt_image) == 40 + 32 + 56 + 40
 
 
 def _args(**kw):
@@ -90,6 +90,13 @@ BAD = [
     dict(disk_on=1, emis_model=3),
     dict(disk_on=1, rotation=1, l0=float("nan")),
     dict(sky_on=1, grid_deg=-6.0),
+    dict(metric=2),
+    dict(metric=1, q=-1.0),
+    dict(metric=1, q=float("nan")),
+    dict(metric=1, q=0.5, a=0.3),
+    dict(metric=1, q=0.5, disk_on=1, r_in=6.0),
+    dict(metric=1, q=0.5, method=0),
+    dict(metric=1, q=0.5, precision=1),
     dict(sky_on=1, line_deg=float("inf")),
 ]
 
@@ -285,3 +292,17 @@ def test_adjoint_validation():
     assert call(st=bad_st) == K.KT_EINVAL
     assert K.kt_adjoint(cam, st, disk, integ, 0x1000, None, 0x2000, None, None, None, None, None, need,
                         None) == K.KT_EINVAL
+
+
+@no_gpu_only
+def test_qmetric_not_in_batches_or_the_adjoint():
+    from paper_2202_00086_amd import kerrtrace as K
+    from paper_2202_00086_amd import workloads as W
+    _, table, integ = _batch([dict(GOOD_IMAGE), dict(GOOD_IMAGE, metric=1, q=0.4)])
+    out = K.kt_outputs()
+    out.fate = 0x1000
+    assert K.kt_render_batch(table, integ, out, C.c_void_p(0x100000), 1 << 30, None) == K.KT_EINVAL
+    assert "image 1" in K.kt_last_error()
+    cam, st, disk, src, integ = K.make_structs(**dict(W.differentiable_disk(n=16), metric=1, q=0.4, a=0.0))
+    assert K.kt_adjoint(cam, st, disk, integ, 0x1000, None, 0x2000, None, None, None, None, C.c_void_p(0x100000),
+                        1 << 40, None) == K.KT_EINVAL
