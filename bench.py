@@ -251,7 +251,7 @@ def run_batch_forms(K, torch, W, steps):
     per_image()
     t = _time(torch, per_image, max(1, steps // 2))
     res["per_image_fp64"] = {"rays_per_s": n / t, "ms_per_step": 1e3 * t,
-                             "launches": len(images), "launch": "default (persistent, block 256, batch 32)"}
+                             "launches": len(images), "launch": "default (persistent, block 256, batch 4, ring-first order)"}
     del singles
     bm = K.BatchRenderer(images, device="cuda:0", want=BATCH_WANT, launch=best,
                          **dict(integ, precision=K.MIXED, h_budget=1e-10, r_switch=300.0))

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define KT_VERSION_NUMBER 140
+#define KT_VERSION_NUMBER 150
 
 /* return codes */
 #define KT_OK 0
@@ -145,14 +145,24 @@ typedef struct kt_integrator {
     int64_t max_steps;      /* accepted-step budget per ray, >= 1 */
 } kt_integrator;
 
-/* Launch shape.  Pass NULL for the defaults. */
+/* Launch shape.  Pass NULL for the defaults: persistent, block 256,
+   blocks_per_cu 0, batch 4, KT_ORDER_RING. */
 typedef struct kt_launch {
     int32_t persistent;     /* 1: persistent waves refill lanes from a global ticket;
                                0: one ray per lane, no refill */
     int32_t block;          /* threads per workgroup: 64, 128 or 256 */
     int32_t blocks_per_cu;  /* persistent grid = CUs * blocks_per_cu; 0 = occupancy */
     int32_t batch;          /* ray ids taken per ticket fetch, 1..4096 */
+    int32_t order;          /* KT_ORDER_RING (0) or KT_ORDER_ROWS: the order rays go out in */
 } kt_launch;
+
+/* Dispatch order.  Outputs are identical under both; only the time differs.
+   KT_ORDER_RING sends rays out by their image-plane distance from the
+   photon ring (nearest first: they take the most steps), sorted on the
+   device at the start of each render; KT_ORDER_ROWS sends pixel ids in
+   row-major order. */
+#define KT_ORDER_RING 0
+#define KT_ORDER_ROWS 1
 
 /* Launch statistics (device memory, written at the end of a render). */
 typedef struct kt_stats {

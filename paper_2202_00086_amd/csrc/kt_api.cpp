@@ -3,6 +3,7 @@
 // sequence on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -129,6 +130,23 @@ void camera_constants(const kt_camera* cam, const kt_spacetime* st, kt::Image& i
     im.two_a2 = 2.0 * a * a;
 }
 
+// Image-plane radius of the photon ring seen by a static observer at r_obs:
+// the critical impact parameter (sqrt(27) M for Kerr at a = 0; for the
+// q-metric M (3+2q) ((3+2q)/(1+2q))^((1+2q)/2), which needs q > -1/2)
+// scaled by the observer's redshift factor.  It only orders the dispatch,
+// so the spin's distortion of the ring is left out.
+double ring_radius(const kt_camera* cam, const kt_spacetime* st) {
+    const double M = st->M, r0 = cam->r_obs;
+    if (!(M > 0.0)) return 0.0;
+    const double f = std::max(0.0, 1.0 - 2.0 * M / r0);
+    if (st->metric == KT_METRIC_Q) {
+        const double q = st->q, e = 0.5 + q;
+        if (!(e > 0.0)) return 0.0;
+        return M * (3.0 + 2.0 * q) * std::pow((3.0 + 2.0 * q) / (1.0 + 2.0 * q), e) * std::pow(f, e);
+    }
+    return std::sqrt(27.0 * f) * M;
+}
+
 // Derivatives of the camera constants (E0, cE, cL, cth, g_rr) with respect to
 // (a, incl): the formulas of camera_constants carried through dual numbers.
 void camera_constant_derivs(const kt_camera* cam, const kt_spacetime* st, double d[5][2]) {
@@ -190,6 +208,12 @@ int make_image(const kt_camera* camera, const kt_spacetime* spacetime, const kt_
     if (!(r_esc > camera->r_obs)) return fail(KT_EINVAL, "r_escape must exceed r_obs");
     im.r_cap = r_cap;
     im.r_esc = r_esc;
+    im.rho_ring = ring_radius(camera, spacetime);
+    {
+        const double rho_max = std::sqrt(camera->fov_x * camera->fov_x + camera->fov_y * camera->fov_y);
+        const double span = std::max(im.rho_ring, rho_max - im.rho_ring);
+        im.order_scale = kt::ORDER_BINS / span;
+    }
 
     const bool disk_on = disk && disk->enabled;
     if (disk_on) {
@@ -247,13 +271,15 @@ bool is_mixed(const kt_integrator* integ) { return integ->precision == KT_MIXED;
 int render_images(const std::vector<kt::Image>& table, int64_t n_rays, const kt_integrator* integ,
                   const kt_outputs* out, void* workspace, size_t workspace_bytes, void* hip_stream,
                   const kt_launch* launch) {
-    kt_launch ln{1, 256, 0, 32};
+    kt_launch ln{1, 256, 0, 4, KT_ORDER_RING};
     if (launch) ln = *launch;
     if (ln.block != 64 && ln.block != 128 && ln.block != 256)
         return fail(KT_EINVAL, "launch block must be 64, 128 or 256");
     if (ln.batch < 1 || ln.batch > 4096) return fail(KT_EINVAL, "launch batch must lie in [1, 4096]");
     if (ln.blocks_per_cu < 0 || ln.blocks_per_cu > 64)
         return fail(KT_EINVAL, "launch blocks_per_cu must lie in [0, 64]");
+    if (ln.order != KT_ORDER_RING && ln.order != KT_ORDER_ROWS)
+        return fail(KT_EINVAL, "launch order must be KT_ORDER_RING or KT_ORDER_ROWS");
 
     const int32_t n_images = static_cast<int32_t>(table.size());
     const bool batch = n_images > 1;
@@ -305,6 +331,11 @@ int render_images(const std::vector<kt::Image>& table, int64_t n_rays, const kt_
     p.rc_buf = reinterpret_cast<double*>(ws + w.rc);
     p.fb_list = reinterpret_cast<uint32_t*>(ws + w.fb_list);
     p.need_fb = reinterpret_cast<uint8_t*>(ws + w.need);
+    if (ln.order == KT_ORDER_RING) {
+        p.perm = reinterpret_cast<uint32_t*>(ws + w.perm);
+        p.order_hist = reinterpret_cast<uint32_t*>(ws + w.hist);
+        p.order_bins = reinterpret_cast<uint16_t*>(ws + w.bins);
+    }
     p.persistent = ln.persistent ? 1 : 0;
     p.batch = ln.batch;
     p.from_list = 0;
@@ -314,6 +345,8 @@ int render_images(const std::vector<kt::Image>& table, int64_t n_rays, const kt_
         return fail(KT_EDEVICE, "image table upload failed: %s", hipGetErrorString(hipGetLastError()));
     if (kt::launch_ws_init(p, hip_stream))
         return fail(KT_EDEVICE, "workspace init launch failed: %s", hipGetErrorString(hipGetLastError()));
+    if (p.perm && kt::launch_order(p, hip_stream))
+        return fail(KT_EDEVICE, "dispatch order launch failed: %s", hipGetErrorString(hipGetLastError()));
     const int64_t lane_grid = (n_rays + ln.block - 1) / ln.block;
     int grid;
     if (p.persistent) {

@@ -47,6 +47,9 @@ struct Image {
     // celestial sphere at r_esc (Sect. 4.1)
     int32_t sky_on;
     double esc_tol, grid_deg, line_deg;
+    // dispatch order: pixels go out by the bin of |rho - rho_ring|, rho the
+    // image-plane radius, bin = that distance times order_scale
+    double rho_ring, order_scale;
 };
 
 // Everything a render needs, copied into the workspace by ws_init.
@@ -70,10 +73,16 @@ struct Params {
     double* rc_buf;
     uint8_t* need_fb;   // KT_MIXED: 1 where the ray must be re-run in FP64
     Params* ws_params;  // where ws_init leaves the device copy of this struct
+    uint32_t* perm;     // dispatch order: ray id of each slot, or NULL for slot = ray id
+    uint32_t* order_hist;  // uint32[ORDER_BINS] counts, then running offsets
+    uint16_t* order_bins;  // uint16[n_rays] bin of each ray
     // launch
     int32_t persistent, batch;
     int32_t from_list;  // take ray ids from fb_list[0 .. *fb_count)
 };
+
+// Bins of the dispatch-order counting sort.
+constexpr int ORDER_BINS = 1024;
 
 // Workspace layout (byte offsets from the start of the caller's buffer).
 constexpr size_t WS_TICKET = 0;       // uint32 ray ticket
@@ -90,6 +99,9 @@ struct WsLayout {
     size_t rc;       // double[n_rays] disk crossing radius per ray
     size_t fb_list;  // uint32[n_rays] (KT_MIXED)
     size_t need;     // uint8[n_rays] (KT_MIXED)
+    size_t perm;     // uint32[n_rays] dispatch order
+    size_t hist;     // uint32[ORDER_BINS]
+    size_t bins;     // uint16[n_rays]
     size_t total;
 };
 
@@ -99,7 +111,10 @@ inline WsLayout ws_layout(size_t n_rays, size_t n_images, bool batch, bool mixed
     w.rc = align256(w.images + (batch ? n_images * sizeof(Image) : 0));
     w.fb_list = align256(w.rc + 8 * n_rays);
     w.need = align256(w.fb_list + (mixed ? 4 * n_rays : 0));
-    w.total = align256(w.need + (mixed ? n_rays : 0));
+    w.perm = align256(w.need + (mixed ? n_rays : 0));
+    w.hist = align256(w.perm + 4 * n_rays);
+    w.bins = align256(w.hist + 4 * ORDER_BINS);
+    w.total = align256(w.bins + 2 * n_rays);
     return w;
 }
 
@@ -168,6 +183,7 @@ inline AdjLayout adj_layout(size_t n_rays, int64_t max_steps) {
 int launch_adjoint(const AdjParams& p, void* stream);
 int launch_ws_init(const Params& p, void* stream);  // also copies p into the workspace
 int launch_upload_images(const Image* host, int32_t n, Image* dev, void* stream);
+int launch_order(const Params& p, void* stream);  // fills p.perm (ring-first dispatch)
 int launch_trace(const Params& p, int grid, int block, void* stream);  // pass of p.precision
 int launch_fallback_list(const Params& p, void* stream);  // compact need_fb, switch the copy to from_list
 int launch_trace_fallback(const Params& p, int grid, int block, void* stream);  // FP64 re-run from the list

@@ -68,7 +68,7 @@ class kt_integrator(C.Structure):
 
 class kt_launch(C.Structure):
     _fields_ = [("persistent", C.c_int32), ("block", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("batch", C.c_int32)]
+                ("batch", C.c_int32), ("order", C.c_int32)]
 
 
 class kt_stats(C.Structure):
@@ -81,6 +81,7 @@ OUTPUT_FIELDS = ("fate", "r_hit", "g", "intensity", "max_abs_h", "max_rel_h", "p
 KEPLER, L0 = 0, 1
 METRIC_KERR, METRIC_Q = 0, 1
 EMIS_POWER, EMIS_TAPERED = 0, 1
+ORDER_RING, ORDER_ROWS = 0, 1  # dispatch order (kt_launch.order)
 SKY_NONE, SKY_GREEN, SKY_RED, SKY_BLUE, SKY_YELLOW, SKY_LINE = range(6)
 
 

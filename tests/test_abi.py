@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared_functions():
         assert hasattr(lib, name), name
     assert set(K.EXPORTED) == set(_declared_functions())
-    assert K.kt_version() == 140
+    assert K.kt_version() == 150
 
 
 def test_struct_layouts_match_header():
@@ -53,7 +53,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(K.kt_disk) == 56
     assert C.sizeof(K.kt_source) == 40
     assert C.sizeof(K.kt_integrator) == 8 + 8 * 8 + 8
-    assert C.sizeof(K.kt_launch) == 16
+    assert C.sizeof(K.kt_launch) == 20
     assert C.sizeof(K.kt_stats) == 12 * 8
     assert C.sizeof(K.kt_outputs) == 17 * 8
     assert C.sizeof(K.kt_image) == 40 + 32 + 56 + 40
@@ -159,7 +159,8 @@ def test_launch_shape_validated():
     K, cam, st, disk, src, integ = _args()
     out = K.kt_outputs()
     out.fate = 0x1000
-    for ln in [K.kt_launch(1, 96, 0, 32), K.kt_launch(1, 256, 0, 0), K.kt_launch(1, 256, -1, 32)]:
+    for ln in [K.kt_launch(1, 96, 0, 32), K.kt_launch(1, 256, 0, 0), K.kt_launch(1, 256, -1, 32),
+               K.kt_launch(1, 256, 0, 32, 2)]:
         rc = K.kt_render_ex(cam, st, disk, src, integ, out, C.c_void_p(0x100000), 1 << 30, None, ln)
         assert rc == K.KT_EINVAL
 

@@ -149,15 +149,17 @@ def test_ragged_and_tiny_images(K):
 
 def test_launch_shapes_are_bit_identical(K):
     """Per-ray arithmetic does not depend on which lane or wave runs the ray:
-    persistent / one-ray-per-lane / queue batch 1 / small blocks give
-    bit-identical outputs."""
+    persistent / one-ray-per-lane / queue batch 1 / small blocks and both
+    dispatch orders give bit-identical outputs (the default is ring-first
+    order; every pixel must still be traced exactly once)."""
     params = dict(W.kerr_ring(0.9, n=96), disk_on=1, r_in=2.320883, r_out=30.0)
     _announce("launch shapes")
     base = gpu_render(K, params)
     shapes = [K.kt_launch(0, 256, 0, 32), K.kt_launch(1, 64, 1, 1), K.kt_launch(1, 128, 2, 7),
-              K.kt_launch(1, 256, 1, 4096)]
+              K.kt_launch(1, 256, 1, 4096), K.kt_launch(1, 256, 0, 32, K.ORDER_ROWS),
+              K.kt_launch(0, 64, 0, 32, K.ORDER_ROWS)]
     for ln in shapes:
-        _announce("launch", ln.persistent, ln.block, ln.blocks_per_cu, ln.batch)
+        _announce("launch", ln.persistent, ln.block, ln.blocks_per_cu, ln.batch, ln.order)
         g = gpu_render(K, params, launch=ln)
         for key, v in base.items():
             if key == "stats":
