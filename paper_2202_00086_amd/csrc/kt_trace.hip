@@ -634,11 +634,20 @@ __global__ void ws_init_kernel(const Params p) {
 // ORDER_BINS bins: a histogram, its exclusive scan, and a scatter.  The
 // order within a bin is whatever the atomics give: every ray's arithmetic is
 // independent of the lane and wave that runs it, so outputs do not change.
+#ifndef KT_ORDER_GROUP_SHIFT
+#define KT_ORDER_GROUP_SHIFT 5
+#endif
+// Rays go out in groups of consecutive ids (keyed by the group's first
+// ray), so the outputs of neighbouring pixels, which share cache lines, are
+// written close together in time and merge in L2 instead of reaching HBM as
+// many partial-line writes.
+constexpr int64_t ORDER_GROUP_MASK = (int64_t{1} << KT_ORDER_GROUP_SHIFT) - 1;
 constexpr int ORDER_BLOCK = 256;
 constexpr int ORDER_PER_THREAD = 16;
 constexpr int ORDER_TILE = ORDER_BLOCK * ORDER_PER_THREAD;
 
 __device__ __forceinline__ int order_bin(const Params& P, int64_t ray) {
+    ray &= ~ORDER_GROUP_MASK;
     const Image* im = P.images;
     int64_t pix = ray;
     if (P.n_images > 1) {
@@ -798,12 +807,25 @@ __global__ void sky_kernel(const Params* pp) {
 
 // Fate histogram into acc[8..15].
 __global__ void fate_hist_kernel(const uint8_t* __restrict__ fate, int64_t n, unsigned long long* acc) {
+    // per-lane counts, summed over the wave with shuffles: most fates are
+    // equal, so atomics per element would serialise on one LDS word
     __shared__ unsigned int hist[8];
     if (threadIdx.x < 8) hist[threadIdx.x] = 0u;
     __syncthreads();
+    unsigned int c[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
     for (int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; p < n;
-         p += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        atomicAdd(&hist[fate[p] & 7], 1u);
+         p += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int f = fate[p] & 7;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[k] += f == k ? 1u : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        unsigned int v = c[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += static_cast<unsigned int>(__shfl_xor(static_cast<int>(v), off));
+        if (__lane_id() == 0 && v) atomicAdd(&hist[k], v);
+    }
     __syncthreads();
     if (threadIdx.x < 8 && hist[threadIdx.x]) atomicAdd(acc + 8 + threadIdx.x, static_cast<unsigned long long>(hist[threadIdx.x]));
 }
@@ -999,7 +1021,10 @@ int launch_sky(const Params& p, void* stream) {
 
 int launch_stats(const Params& p, void* stream) {
     const int64_t n = p.n_rays;
-    hipLaunchKernelGGL(fate_hist_kernel, dim3(small_grid(n, 256)), dim3(256), 0,
+    // few blocks: each ends with one 64-bit atomic per fate on the same
+    // eight words, and thousands of those serialise
+    const int grid = small_grid(n, 256) < 256 ? small_grid(n, 256) : 256;
+    hipLaunchKernelGGL(fate_hist_kernel, dim3(grid), dim3(256), 0,
                        static_cast<hipStream_t>(stream), p.out.fate, n, p.acc);
     if (check_launch()) return -1;
     hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), p.acc,
