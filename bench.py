@@ -188,7 +188,7 @@ def run_adjoint_form(K, torch, W, steps):
     L2 loss against the image at (0.6, 50 deg, 1.1 ISCO(0.6)), both timed."""
     import ctypes as C
     params = W.differentiable_disk(n=512)
-    want = ("fate", "r_hit", "g", "intensity", "n_cross")
+    want = ("fate", "r_hit", "g", "intensity", "n_cross", "n_steps")
     T = K.Renderer(device="cuda:0", want=want, stats=False, **W.disk_fit_target(n=512)).render()["intensity"]
     r = K.Renderer(device="cuda:0", want=want, stats=False, **params)
     r.render()
@@ -202,18 +202,22 @@ def run_adjoint_form(K, torch, W, steps):
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
     stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
-    def adjoint():
+    def adjoint(sorted_list=True):
         rc = K.kt_adjoint(r.cam, r.st, r.disk, r.integ, out["fate"].data_ptr(), out["r_hit"].data_ptr(),
                           cot.data_ptr(), grads[0].data_ptr(), grads[1].data_ptr(), grads[2].data_ptr(),
-                          stats.data_ptr(), ws.data_ptr(), nbytes, stream)
+                          stats.data_ptr(), ws.data_ptr(), nbytes, stream,
+                          out["n_steps"].data_ptr() if sorted_list else None)
         if rc != K.KT_OK:
             raise K.KtError(rc, K.kt_last_error())
+    adjoint(False)
+    t_unsorted = _time(torch, lambda: adjoint(False), steps)
     adjoint()
     t_adj = _time(torch, adjoint, steps)
     st = [int(v) for v in stats.cpu().tolist()]
     return {"workload": "Kerr a=0.7 disk, 512x512, i=45 deg, r_obs=1000M, +-35M, r_in=ISCO(0.7), r_out=30M, "
                         "tapered emissivity, DP45 rtol=atol=1e-12; L2 loss vs (a=0.6, i=50 deg, r_in=1.1 ISCO)",
             "forward_ms": 1e3 * t_fwd, "adjoint_ms": 1e3 * t_adj, "adjoint_over_forward": t_adj / t_fwd,
+            "adjoint_ms_without_step_counts": 1e3 * t_unsorted,
             "loss": float((((out["intensity"] - T) ** 2) * mask).sum().item()),
             "grad": {"a": float(grads[0].sum().item()), "incl": float(grads[1].sum().item()),
                      "r_in": float(grads[2].sum().item())},

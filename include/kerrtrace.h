@@ -284,9 +284,12 @@ int kt_autotune_batch(int32_t n_images, const kt_image *images, const kt_integra
    gradient is their sum with cot_intensity = dLoss/dI.
    Inputs: the same camera, spacetime, disk and integrator as the forward
    kt_render (method KT_DP45, KT_FP64, disk enabled), and that render's fate
-   and (optional, for a bit-identity check) r_hit arrays.  Each ray is
-   re-integrated with the forward's own arithmetic, checkpointed every 64
-   accepted steps, and swept backward segment by segment.
+   array, its r_hit array (optional, for a bit-identity check) and its
+   n_steps array (optional: the differentiated rays are run longest first
+   and neighbouring lanes get rays of similar length; it changes only the
+   time).  Each ray is re-integrated with the forward's own arithmetic,
+   checkpointed every 64 accepted steps, and swept backward segment by
+   segment.
    stats (device, 4 uint64, may be NULL): rays differentiated, rays that
    failed, rays beyond the checkpoint capacity (256 x 64 steps), rays whose
    re-integration did not reproduce r_hit; the last three get zero gradient.
@@ -294,8 +297,9 @@ int kt_autotune_batch(int32_t n_images, const kt_image *images, const kt_integra
    Returns KT_OK, KT_EINVAL, KT_ENOMEM or KT_EDEVICE. */
 int kt_adjoint(const kt_camera *camera, const kt_spacetime *spacetime, const kt_disk *disk,
                const kt_integrator *integ, const uint8_t *fate, const double *r_hit,
-               const double *cot_intensity, double *grad_a, double *grad_incl, double *grad_r_in,
-               uint64_t *stats, void *workspace, size_t workspace_bytes, void *hip_stream);
+               const int32_t *n_steps, const double *cot_intensity, double *grad_a,
+               double *grad_incl, double *grad_r_in, uint64_t *stats, void *workspace,
+               size_t workspace_bytes, void *hip_stream);
 
 /* Workspace size of kt_adjoint for this camera and integrator (0 on bad input). */
 size_t kt_adjoint_workspace_bytes(const kt_camera *camera, const kt_integrator *integ);

@@ -12,7 +12,7 @@ import torch
 
 from . import kerrtrace as K
 
-_WANT = ("fate", "r_hit", "g", "intensity", "n_cross")
+_WANT = ("fate", "r_hit", "g", "intensity", "n_cross", "n_steps")
 
 
 class DiskImage(torch.autograd.Function):
@@ -45,7 +45,8 @@ class DiskImage(torch.autograd.Function):
         stream = torch.cuda.current_stream(dev)
         rc = K.kt_adjoint(r.cam, r.st, r.disk, r.integ, r.out["fate"].data_ptr(), r.out["r_hit"].data_ptr(),
                           cot.data_ptr(), grads[0].data_ptr(), grads[1].data_ptr(), grads[2].data_ptr(),
-                          stats.data_ptr(), ws.data_ptr(), nbytes, C.c_void_p(stream.cuda_stream))
+                          stats.data_ptr(), ws.data_ptr(), nbytes, C.c_void_p(stream.cuda_stream),
+                          r.out["n_steps"].data_ptr())
         if rc != K.KT_OK:
             raise K.KtError(rc, K.kt_last_error())
         ctx.renderer.adjoint_stats = stats
@@ -74,7 +75,8 @@ def adjoint_maps(device="cuda:0", cot=None, **params):
     stream = torch.cuda.current_stream(dev)
     rc = K.kt_adjoint(r.cam, r.st, r.disk, r.integ, out["fate"].data_ptr(), out["r_hit"].data_ptr(),
                       cot.data_ptr(), grads[0].data_ptr(), grads[1].data_ptr(), grads[2].data_ptr(),
-                      stats.data_ptr(), ws.data_ptr(), nbytes, C.c_void_p(stream.cuda_stream))
+                      stats.data_ptr(), ws.data_ptr(), nbytes, C.c_void_p(stream.cuda_stream),
+                      out["n_steps"].data_ptr())
     if rc != K.KT_OK:
         raise K.KtError(rc, K.kt_last_error())
     return out, tuple(grads), stats

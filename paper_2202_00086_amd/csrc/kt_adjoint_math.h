@@ -99,40 +99,40 @@ __host__ __device__ constexpr double dp_b(int j) {
     return t[j];
 }
 
-// The step map y -> y + h sum_j b_j k_j with its six stage states.
-__host__ __device__ inline void dp_stages(double M, double a, double E, double L, const double y[5], double h,
-                                          double Y[6][5], double yn[5]) {
-    double K[6][5];
+// Vector-Jacobian product of one step with frozen h: given ybar at the
+// step's end, returns ybar at its start (in place) and accumulates the
+// parameter cotangents.  The stage states are rebuilt from y (the step's
+// end value itself is not needed, so the last stage's field is skipped).
+// Every loop is unrolled so that the stage arrays stay in registers: with
+// run-time indices they would live in scratch memory, at half the speed.
+__host__ __device__ inline void dp_step_vjp(double M, double a, double E, double L, const double y[5], double h,
+                                            double ybar[5], ParBar* pb) {
+    double Y[6][5], K[5][5];
+#pragma unroll
     for (int j = 0; j < 6; ++j) {
+#pragma unroll
         for (int i = 0; i < 5; ++i) {
             double acc = 0.0;
+#pragma unroll
             for (int l = 0; l < j; ++l) acc += dp_a(j, l) * K[l][i];
             Y[j][i] = y[i] + h * acc;
         }
-        field(M, a, E, L, Y[j], K[j]);
+        if (j < 5) field(M, a, E, L, Y[j], K[j]);
     }
-    for (int i = 0; i < 5; ++i) {
-        double acc = 0.0;
-        for (int j = 0; j < 6; ++j) acc += dp_b(j) * K[j][i];
-        yn[i] = y[i] + h * acc;
-    }
-}
-
-// Vector-Jacobian product of one step with frozen h: given ybar at the
-// step's end, returns ybar at its start (in place) and accumulates the
-// parameter cotangents.
-__host__ __device__ inline void dp_step_vjp(double M, double a, double E, double L, const double y[5], double h,
-                                            double ybar[5], ParBar* pb) {
-    double Y[6][5], yn[5];
-    dp_stages(M, a, E, L, y, h, Y, yn);
     double kb[6][5];
+#pragma unroll
     for (int j = 0; j < 6; ++j)
+#pragma unroll
         for (int i = 0; i < 5; ++i) kb[j][i] = h * dp_b(j) * ybar[i];
+#pragma unroll
     for (int j = 5; j >= 0; --j) {
         double Yb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         field_vjp(M, a, E, L, Y[j], kb[j], Yb, pb);
+#pragma unroll
         for (int i = 0; i < 5; ++i) ybar[i] += Yb[i];
+#pragma unroll
         for (int l = 0; l < j; ++l)
+#pragma unroll
             for (int i = 0; i < 5; ++i) kb[l][i] += h * dp_a(j, l) * Yb[i];
     }
 }

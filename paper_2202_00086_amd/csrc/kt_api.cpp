@@ -500,7 +500,8 @@ size_t kt_adjoint_workspace_bytes(const kt_camera* camera, const kt_integrator* 
 }
 
 int kt_adjoint(const kt_camera* camera, const kt_spacetime* spacetime, const kt_disk* disk,
-               const kt_integrator* integ, const uint8_t* fate, const double* r_hit, const double* cot_intensity,
+               const kt_integrator* integ, const uint8_t* fate, const double* r_hit, const int32_t* n_steps,
+               const double* cot_intensity,
                double* grad_a, double* grad_incl, double* grad_r_in, uint64_t* stats, void* workspace,
                size_t workspace_bytes, void* hip_stream) {
     g_err[0] = 0;
@@ -548,6 +549,10 @@ int kt_adjoint(const kt_camera* camera, const kt_spacetime* spacetime, const kt_
                     : reinterpret_cast<unsigned long long*>(ws + w.stats);
     p.ckpt = reinterpret_cast<double*>(ws + w.ckpt);
     p.seg = reinterpret_cast<double*>(ws + w.seg);
+    p.n_steps = n_steps;
+    p.hist = reinterpret_cast<uint32_t*>(ws + w.hist);
+    p.keys = reinterpret_cast<uint16_t*>(ws + w.keys);
+    p.list = reinterpret_cast<uint32_t*>(ws + w.list);
     p.n_lanes = w.n_lanes;
     p.max_ckpt = w.max_ckpt;
     if (kt::launch_adjoint(p, hip_stream))

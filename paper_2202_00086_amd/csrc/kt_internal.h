@@ -153,13 +153,24 @@ struct AdjParams {
     double* ckpt;               // [max_ckpt][6][n_lanes]
     double* seg;                // [64][6][n_lanes]
     int32_t n_lanes, max_ckpt;
+    // work list: the differentiated rays, longest forward integration first
+    const int32_t* n_steps;     // the forward render's step counts (may be NULL)
+    uint32_t* hist;             // [ADJ_BINS + 1] bin counts, then offsets; [ADJ_BINS] = list length
+    uint16_t* keys;             // [n_rays] bin of each ray, ADJ_SKIP if not differentiated
+    uint32_t* list;             // [n_rays] ray ids
 };
 
-constexpr int ADJ_MAX_LANES = 65536;
+constexpr int ADJ_BINS = 1024;
+constexpr uint16_t ADJ_SKIP = 0xffff;
+
+#ifndef KT_ADJ_MAX_LANES
+#define KT_ADJ_MAX_LANES 65536
+#endif
+constexpr int ADJ_MAX_LANES = KT_ADJ_MAX_LANES;
 constexpr int ADJ_MAX_CKPT = 256;
 
 struct AdjLayout {
-    size_t stats, ckpt, seg, total;
+    size_t stats, hist, ckpt, seg, keys, list, total;
     int32_t n_lanes, max_ckpt;
 };
 
@@ -173,9 +184,12 @@ inline AdjLayout adj_layout(size_t n_rays, int64_t max_steps) {
     w.n_lanes = static_cast<int32_t>(lanes);
     w.max_ckpt = static_cast<int32_t>(ck);
     w.stats = 64;
-    w.ckpt = 256;
+    w.hist = 256;
+    w.ckpt = align256(w.hist + 4u * (ADJ_BINS + 1));
     w.seg = align256(w.ckpt + static_cast<size_t>(ck) * 6u * lanes * sizeof(double));
-    w.total = align256(w.seg + 64u * 6u * lanes * sizeof(double));
+    w.keys = align256(w.seg + 64u * 6u * lanes * sizeof(double));
+    w.list = align256(w.keys + 2u * n_rays);
+    w.total = align256(w.list + 4u * n_rays);
     return w;
 }
 

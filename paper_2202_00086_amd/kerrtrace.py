@@ -107,7 +107,7 @@ _lib.kt_workspace_bytes.restype = C.c_size_t
 _lib.kt_workspace_bytes_batch.argtypes = [C.c_int32, _P(kt_image), _P(kt_integrator)]
 _lib.kt_adjoint.argtypes = [_P(kt_camera), _P(kt_spacetime), _P(kt_disk), _P(kt_integrator), C.c_void_p,
                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                            C.c_void_p, C.c_size_t, C.c_void_p]
+                            C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
 _lib.kt_adjoint.restype = C.c_int
 _lib.kt_adjoint_workspace_bytes.argtypes = [_P(kt_camera), _P(kt_integrator)]
 _lib.kt_adjoint_workspace_bytes.restype = C.c_size_t
@@ -187,9 +187,9 @@ def kt_adjoint_workspace_bytes(camera, integ):
 
 
 def kt_adjoint(camera, spacetime, disk, integ, fate_ptr, r_hit_ptr, cot_ptr, grad_a_ptr, grad_incl_ptr,
-               grad_rin_ptr, stats_ptr, workspace_ptr, workspace_bytes, stream_ptr):
+               grad_rin_ptr, stats_ptr, workspace_ptr, workspace_bytes, stream_ptr, n_steps_ptr=None):
     return _lib.kt_adjoint(C.byref(camera), C.byref(spacetime), C.byref(disk), C.byref(integ), fate_ptr,
-                           r_hit_ptr, cot_ptr, grad_a_ptr, grad_incl_ptr, grad_rin_ptr, stats_ptr,
+                           r_hit_ptr, n_steps_ptr, cot_ptr, grad_a_ptr, grad_incl_ptr, grad_rin_ptr, stats_ptr,
                            workspace_ptr, workspace_bytes, stream_ptr)
 
 

@@ -213,6 +213,41 @@ def test_full_size_kerr_ring_sampled(K):
     assert np.nanmax(g["max_rel_h"]) < 1e-10
 
 
+def test_full_size_schwarzschild_disk_sampled(K):
+    """2048x2048 Schwarzschild disk (i = 80 deg, 6..30M, +-35M) at full size
+    in the default launch: a fixed sample of pixels against the oracle traced
+    one by one (hit radius, redshift, intensity to 1e-8 away from fate and
+    image-order boundaries); the mixed form at budget 1e-10 keeps every ray
+    within budget and its FP64 re-runs equal the FP64 render bit for bit."""
+    n = 2048
+    params = W.schwarzschild_disk(n=n)
+    _announce("schwarzschild_disk_2048 sampled")
+    g = gpu_render(K, params)
+    rng = np.random.default_rng(80)
+    pix = np.sort(rng.choice(n * n, size=3000, replace=False)).astype(np.int32)
+    o = ora_render(params, pix)
+    near = (P.boundary_mask(g["fate"].reshape(n, n)) | P.boundary_mask(g["n_cross"].reshape(n, n))).ravel()[pix]
+    same = g["fate"][pix] == o["fate"]
+    assert (same | near).all()
+    ok = same & ~near & (o["fate"] == O.DISK) & (o["n_cross"] <= 1)
+    assert ok.sum() > 250
+    np.testing.assert_array_equal(g["n_cross"][pix][ok], o["n_cross"][ok])
+    for key in ("r_hit", "g", "intensity"):
+        e = P.rel_err(g[key][pix][ok], o[key][ok])
+        assert np.max(e) < 1e-8, (key, np.max(e))
+    st = g["stats"]
+    assert st.rays == n * n and sum(st.fate_count) == n * n
+    assert np.nanmax(g["max_rel_h"]) < 1e-10
+    _announce("schwarzschild_disk_2048 mixed 1e-10")
+    m = gpu_render(K, dict(params, precision=K.MIXED, h_budget=1e-10, r_switch=300.0))
+    assert np.nanmax(m["max_rel_h"]) <= 1e-10
+    re = m["used_fp64"].astype(bool)
+    for key in ("fate", "r_hit", "g", "intensity", "max_rel_h", "n_steps"):
+        np.testing.assert_array_equal(m[key][re].view(np.uint8), g[key][re].view(np.uint8), err_msg=key)
+    P.check_fates(m["fate"], g["fate"], n, n)
+    print(f"[disk 2048 mixed] re-run fraction {re.mean():.4f}", flush=True)
+
+
 # ---------------------------------------------------------------------------
 # Mixed precision: FP32 mass part of the RHS beyond r_switch, FP64 re-run of
 # every ray over the |H|_rel budget.
