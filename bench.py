@@ -182,6 +182,31 @@ def run_scheme_forms(K, torch, W, steps):
     return res
 
 
+def run_f4_forms(K, torch, W, steps):
+    """The Sect. 4-5 and appendix images on the same persistent kernel: the
+    coloured celestial sphere around Kerr a = 0.98 and in flat space, the
+    q-metric (q = 0.5) in the same setup, and the constant-l0 thin disk at
+    a = 0.95.  Per image: time, rays/s, stage-evals/s, evaluations per ray,
+    max |H|_rel and the fate histogram."""
+    res = {}
+    for name, p in (("lensing_1024_a0.98", W.lensing(a=0.98, n=1024)),
+                    ("lensing_1024_flat", W.lensing(a=0.0, n=1024, M=0.0)),
+                    ("qmetric_lensing_1024_q0.5", W.qmetric_lensing(q=0.5, n=1024)),
+                    ("thin_disk_l0_2048x1024_a0.95", W.thin_disk_l0(a=0.95))):
+        r = K.Renderer(device="cuda:0", **p)
+        r.render()
+        t = _time(torch, r.render, steps)
+        st = K.read_stats(r.out)
+        hr = r.out["max_rel_h"][r.out["fate"] <= K.DISK]
+        hr = hr[~torch.isnan(hr)]
+        res[name] = {"ms_per_image": 1e3 * t, "rays_per_s": r.n / t, "stage_evals_per_s": st.evals / t,
+                     "evals_per_ray": st.evals / r.n,
+                     "max_rel_h": float(hr.max().item()) if hr.numel() else None,
+                     "fates": [int(c) for c in st.fate_count[:6]]}
+        del r
+    return res
+
+
 def run_adjoint_form(K, torch, W, steps):
     """The differentiable disk image (512^2, a = 0.7, i = 45 deg, r_in =
     ISCO, tapered emissivity): forward render and the discrete adjoint of the
@@ -339,11 +364,12 @@ def main():
                            "max_rel_h": f["max_rel_h"], "p999_rel_h": f["p999_rel_h"],
                            "error_vs_fp64": error_vs(torch, f["out"], main_form["out"])}
 
-    batch = schemes = adjoint = None
+    batch = schemes = adjoint = images = None
     if not args.no_forms:
         batch = run_batch_forms(K, torch, W, max(2, args.steps // 8))
         schemes = run_scheme_forms(K, torch, W, max(2, args.steps // 8))
         adjoint = run_adjoint_form(K, torch, W, max(2, args.steps // 8))
+        images = run_f4_forms(K, torch, W, max(2, args.steps // 8))
 
     out = {"metric": METRIC, "value": rays_per_s, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": main_form["ms_per_step"], "higher_is_better": True,
@@ -365,6 +391,8 @@ def main():
         out["integrators"] = schemes
     if adjoint:
         out["adjoint"] = adjoint
+    if images:
+        out["images"] = images
     if not args.no_cpu:
         cb = cpu_baseline(params)
         out["cpu_baseline"] = cb
