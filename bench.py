@@ -91,7 +91,14 @@ def cpu_baseline(params, rows_every=16):
     t0 = time.perf_counter()
     o = O.trace_pixels(O.Setup(**params), pix, threads=threads)
     dt = time.perf_counter() - t0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": pix.size / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "cpus_visible": n_avail,
             "sample": f"rows j = 0 mod {rows_every} of the same image ({pix.size} rays, "
                       f"{dt:.1f} s wall on {threads} threads; plain C FP64 oracle, -O2, OpenMP)",
             "stage_evals_per_s": float(o["n_evals"].astype(np.int64).sum()) / dt}
