@@ -301,6 +301,10 @@ def run_batch_forms(K, torch, W, steps):
         "fp32_eval_fraction": sm.evals_fp32 / max(1, sm.evals),
         "max_rel_h": float(h[~torch.isnan(h)].max().item()),
         "error_vs_fp64": error_vs(torch, bm.out, ref, keys=("r_hit", "g", "intensity"))}
+    # the workload's own comparison: the mixed batched launch against
+    # per-image FP64 launches, and against the FP64 batched launch
+    res["mixed_batch_over_per_image_fp64"] = (n / t) / res["per_image_fp64"]["rays_per_s"]
+    res["mixed_batch_over_fp64_batch"] = (n / t) / res["batch_fp64"]["rays_per_s"]
     return res
 
 
