@@ -283,6 +283,63 @@ __device__ __forceinline__ RayConst make_ray_const(const QSpacetime&, double E, 
     return rc;
 }
 
+// e^x for |x| < ~700: x = n ln 2 + t with |t| <= (ln 2)/2 (Cody-Waite with a
+// two-part ln 2), e^t from its Taylor series through t^13 (truncation below
+// 5e-18 relative), scaled by 2^n.  About 1 ulp.
+__device__ __forceinline__ double exp_fast(double x) {
+    constexpr double LOG2E = 1.4426950408889634074;
+    constexpr double LN2_HI = 6.93147180369123816490e-01;  // 32 significant bits
+    constexpr double LN2_LO = 1.90821492927058770002e-10;
+    const double n = __builtin_rint(x * LOG2E);
+    const double t = fma(-n, LN2_LO, fma(-n, LN2_HI, x));
+    double p = 1.0 / 6227020800.0;       // 1/13!
+    p = fma(p, t, 1.0 / 479001600.0);    // 1/12!
+    p = fma(p, t, 1.0 / 39916800.0);     // 1/11!
+    p = fma(p, t, 1.0 / 3628800.0);      // 1/10!
+    p = fma(p, t, 1.0 / 362880.0);       // 1/9!
+    p = fma(p, t, 1.0 / 40320.0);        // 1/8!
+    p = fma(p, t, 1.0 / 5040.0);         // 1/7!
+    p = fma(p, t, 1.0 / 720.0);          // 1/6!
+    p = fma(p, t, 1.0 / 120.0);          // 1/5!
+    p = fma(p, t, 1.0 / 24.0);           // 1/4!
+    p = fma(p, t, 1.0 / 6.0);            // 1/3!
+    p = fma(p, t, 0.5);
+    p = fma(p, t, 1.0);
+    p = fma(p, t, 1.0);
+    return __builtin_amdgcn_ldexp(p, static_cast<int>(n));
+}
+
+// ln x for finite x > 0 (NaN for x <= 0): x = 2^e m with m in [1/sqrt 2,
+// sqrt 2), ln m = 2 atanh s with s = (m - 1)/(m + 1), |s| <= 0.172, from the
+// series of atanh through s^21 (truncation below 3e-17 relative).  About
+// 2 ulp.
+__device__ __forceinline__ double log_fast(double x) {
+    constexpr double LN2_HI = 6.93147180369123816490e-01;
+    constexpr double LN2_LO = 1.90821492927058770002e-10;
+    double m = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1)
+    int e = __builtin_amdgcn_frexp_exp(x);
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) * rcp(m + 1.0);
+    const double s2 = s * s;
+    double p = 1.0 / 21;
+    p = fma(p, s2, 1.0 / 19);
+    p = fma(p, s2, 1.0 / 17);
+    p = fma(p, s2, 1.0 / 15);
+    p = fma(p, s2, 1.0 / 13);
+    p = fma(p, s2, 1.0 / 11);
+    p = fma(p, s2, 1.0 / 9);
+    p = fma(p, s2, 1.0 / 7);
+    p = fma(p, s2, 1.0 / 5);
+    p = fma(p, s2, 1.0 / 3);
+    const double lm = fma((2.0 * s) * s2, p, 2.0 * s);
+    const double de = static_cast<double>(e);
+    const double r = fma(de, LN2_HI, fma(de, LN2_LO, lm));
+    return x > 0.0 ? r : __builtin_nan("");
+}
+
 template <bool WANT_DIAG>
 __device__ __forceinline__ void rhs_q(const QSpacetime& st, const RayConst& rc, const double z[5], double s,
                                       double c, double dz[5], Diag* dg) {
@@ -297,9 +354,9 @@ __device__ __forceinline__ void rhs_q(const QSpacetime& st, const RayConst& rc, 
     const double f = rf * ir * ir;
     const double Dm1 = (M * M) * (s * s) * irf;  // D - 1
     const double D = 1.0 + Dm1;
-    const double lf = log(f);
-    const double fq = exp(st.q * lf);           // f^q
-    const double DP = exp(st.P * log1p(Dm1));   // D^P
+    const double lf = log_fast(f);
+    const double fq = exp_fast(st.q * lf);        // f^q
+    const double DP = exp_fast(st.P * log_fast(D));  // D^P
     const double iD = rcp(D);
     const double ir2 = ir * ir;
     const double A = f * fq * DP;
