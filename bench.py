@@ -375,6 +375,24 @@ def main():
                            "max_rel_h": f["max_rel_h"], "p999_rel_h": f["p999_rel_h"],
                            "error_vs_fp64": error_vs(torch, f["out"], main_form["out"])}
 
+        # the 2048^2 Schwarzschild disk: FP64 against the mixed form, with the
+        # mixed form's error per output
+        pd = W.schwarzschild_disk(n=2048)
+        fd = run_form(K, torch, pd, k, 1)
+        forms["disk_2048_fp64"] = {"rays_per_s": fd["rays"] / (fd["ms_per_step"] / 1e3),
+                                   "stage_evals_per_s": fd["evals"] / (fd["ms_per_step"] / 1e3),
+                                   "ms_per_step": fd["ms_per_step"], "max_rel_h": fd["max_rel_h"],
+                                   "fates": fd["fates"]}
+        fm = run_form(K, torch, dict(pd, precision=K.MIXED, h_budget=1e-10, r_switch=300.0), k, 1)
+        forms["disk_2048_mixed_budget1e-10"] = {
+            "rays_per_s": fm["rays"] / (fm["ms_per_step"] / 1e3),
+            "stage_evals_per_s": fm["evals"] / (fm["ms_per_step"] / 1e3),
+            "ms_per_step": fm["ms_per_step"], "r_switch": 300.0, "h_budget": 1e-10,
+            "fallback_fraction": fm["fallback_rays"] / fm["rays"],
+            "fp32_eval_fraction": fm["evals_fp32"] / max(1, fm["evals"]), "max_rel_h": fm["max_rel_h"],
+            "error_vs_fp64": error_vs(torch, fm["out"], fd["out"], keys=("r_hit", "g", "intensity"))}
+        del fd, fm
+
     batch = schemes = adjoint = images = None
     if not args.no_forms:
         batch = run_batch_forms(K, torch, W, max(2, args.steps // 8))

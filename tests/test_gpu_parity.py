@@ -188,11 +188,13 @@ def test_invalid_pixels(K):
     assert (g["fate"] == K.INVALID).sum() > 0
 
 
-def test_full_size_kerr_ring_sampled(K):
-    """1024x1024, a = 0.9 in the launch configuration the benchmark times:
-    a fixed sample of pixels against the oracle traced one by one."""
-    params = W.kerr_ring(0.9, n=1024)
-    _announce("kerr_ring_1024 sampled")
+@pytest.mark.parametrize("a", [0.9, 0.5, 0.998])
+def test_full_size_kerr_ring_sampled(K, a):
+    """1024x1024 at each spin of the workload, in the launch configuration the
+    benchmark times: a fixed sample of pixels against the oracle traced one
+    by one."""
+    params = W.kerr_ring(a, n=1024)
+    _announce("kerr_ring_1024 sampled", a)
     g = gpu_render(K, params)
     rng = np.random.default_rng(2022)
     pix = np.sort(rng.choice(1024 * 1024, size=400, replace=False)).astype(np.int32)
@@ -210,7 +212,19 @@ def test_full_size_kerr_ring_sampled(K):
     assert st.rays == 1024 * 1024 and sum(st.fate_count) == 1024 * 1024
     assert st.evals == g["n_evals"].astype(np.int64).sum()
     assert (g["fate"] <= K.DISK).all()
-    assert np.nanmax(g["max_rel_h"]) < 1e-10
+    # the constraint: DP45 at rtol 1e-12 keeps |H|_rel near 1e-11; the single
+    # worst ray of the image is traced by the oracle too, whose value must be
+    # of the same size (the method's, not the kernel's)
+    h = g["max_rel_h"]
+    assert np.nanpercentile(h, 99.9) < 1e-10
+    worst = int(np.nanargmax(h))
+    ow = ora_render(params, np.array([worst], np.int32))
+    print(f"[kerr_ring_1024 a={a}] worst |H|_rel {h[worst]:.3e} at pixel {worst}; oracle {ow['max_rel_h'][0]:.3e}",
+          flush=True)
+    assert h[worst] < 2e-10 and ow["max_rel_h"][0] < 2e-10
+    assert 0.5 < h[worst] / ow["max_rel_h"][0] < 2.0
+    if a == 0.9:
+        assert h[worst] < 1e-10  # the benchmarked image meets the budget everywhere
 
 
 def test_full_size_schwarzschild_disk_sampled(K):
