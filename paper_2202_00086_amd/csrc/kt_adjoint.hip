@@ -22,6 +22,7 @@
 #include "kt_device.h"
 #include "kt_internal.h"
 #include "kt_ray.h"
+#include "kt_sort.h"
 
 namespace kt {
 
@@ -236,7 +237,7 @@ adjoint_kernel(const AdjParams P) {
     if (lane >= P.n_lanes) return;
     const Image& im = P.im;
     const Spacetime st{im.M, im.a, im.a2, im.two_a2};
-    const uint32_t n_list = P.hist[ADJ_BINS];
+    const uint32_t n_list = P.hist[SORT_BINS];
     for (;;) {
         const uint32_t t = atomicAdd(P.ticket, 1u);
         if (t >= n_list) break;
@@ -255,115 +256,40 @@ __global__ void adjoint_init_kernel(uint32_t* ticket, unsigned long long* stats,
     const int t = threadIdx.x;
     if (t == 0) *ticket = 0u;
     if (t < 4) stats[t] = 0ull;
-    for (int b = t; b <= ADJ_BINS; b += blockDim.x) hist[b] = 0u;
+    for (int b = t; b <= SORT_BINS; b += blockDim.x) hist[b] = 0u;
 }
 
 // ---- work list ------------------------------------------------------------
 // The lanes of a wave run their rays' loops in step, so a wave costs as much
 // as its longest ray.  The differentiated rays (disk hits with a nonzero
 // cotangent) are compacted into a list sorted by the forward render's step
-// count, longest first, with a counting sort over ADJ_BINS bins of 4 steps:
+// count, longest first (a counting sort over SORT_BINS bins of 4 steps):
 // neighbouring lanes then take rays of nearly equal length.  Pixels outside
-// the list get zero gradients here.
-constexpr int ADJ_SORT_BLOCK = 256;
-constexpr int ADJ_SORT_PER_THREAD = 16;
-constexpr int ADJ_SORT_TILE = ADJ_SORT_BLOCK * ADJ_SORT_PER_THREAD;
-
-__global__ void __launch_bounds__(ADJ_SORT_BLOCK) adjoint_count_kernel(const AdjParams P) {
-    __shared__ uint32_t cnt[ADJ_BINS];
-    const int t = threadIdx.x;
-    for (int b = t; b < ADJ_BINS; b += ADJ_SORT_BLOCK) cnt[b] = 0u;
-    __syncthreads();
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * ADJ_SORT_TILE;
-    for (int k = 0; k < ADJ_SORT_PER_THREAD; ++k) {
-        const int64_t ray = base + k * ADJ_SORT_BLOCK + t;
-        if (ray >= P.n_rays) break;
-        if (P.fate[ray] == KT_FATE_DISK && P.cot[ray] != 0.0) {
-            int steps = P.n_steps ? P.n_steps[ray] >> 2 : 0;
-            steps = steps < 0 ? 0 : steps > ADJ_BINS - 1 ? ADJ_BINS - 1 : steps;
-            const int b = ADJ_BINS - 1 - steps;
-            P.keys[ray] = static_cast<uint16_t>(b);
-            atomicAdd(&cnt[b], 1u);
-        } else {
-            P.keys[ray] = ADJ_SKIP;
-            if (P.grad_a) P.grad_a[ray] = 0.0;
-            if (P.grad_incl) P.grad_incl[ray] = 0.0;
-            if (P.grad_rin) P.grad_rin[ray] = 0.0;
+// the list get zero gradients from the key function.
+struct StepKey {
+    const uint8_t* fate;
+    const double* cot;
+    const int32_t* n_steps;  // may be NULL: every listed ray gets the same key
+    double *ga, *gi, *gr;
+    __device__ int operator()(int64_t ray) const {
+        if (fate[ray] == KT_FATE_DISK && cot[ray] != 0.0) {
+            int steps = n_steps ? n_steps[ray] >> 2 : 0;
+            steps = steps < 0 ? 0 : steps > SORT_BINS - 1 ? SORT_BINS - 1 : steps;
+            return SORT_BINS - 1 - steps;
         }
+        if (ga) ga[ray] = 0.0;
+        if (gi) gi[ray] = 0.0;
+        if (gr) gr[ray] = 0.0;
+        return SORT_SKIP;
     }
-    __syncthreads();
-    for (int b = t; b < ADJ_BINS; b += ADJ_SORT_BLOCK)
-        if (cnt[b]) atomicAdd(&P.hist[b], cnt[b]);
-}
-
-// Exclusive scan of the bin counts in place; the total goes to hist[ADJ_BINS].
-__global__ void __launch_bounds__(ADJ_SORT_BLOCK) adjoint_scan_kernel(uint32_t* h) {
-    constexpr int PER = ADJ_BINS / ADJ_SORT_BLOCK;
-    __shared__ uint32_t part[ADJ_SORT_BLOCK];
-    const int t = threadIdx.x;
-    uint32_t v[PER], sum = 0;
-    for (int k = 0; k < PER; ++k) {
-        v[k] = h[t * PER + k];
-        sum += v[k];
-    }
-    part[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < ADJ_SORT_BLOCK; off <<= 1) {
-        const uint32_t add = t >= off ? part[t - off] : 0u;
-        __syncthreads();
-        part[t] += add;
-        __syncthreads();
-    }
-    uint32_t run = part[t] - sum;
-    for (int k = 0; k < PER; ++k) {
-        h[t * PER + k] = run;
-        run += v[k];
-    }
-    if (t == ADJ_SORT_BLOCK - 1) h[ADJ_BINS] = run;
-}
-
-// Each tile reserves its range in every bin it touches and places its rays;
-// the bins are the stored keys, so positions stay below the list length.
-__global__ void __launch_bounds__(ADJ_SORT_BLOCK) adjoint_scatter_kernel(const AdjParams P) {
-    __shared__ uint32_t cnt[ADJ_BINS];
-    const int t = threadIdx.x;
-    for (int b = t; b < ADJ_BINS; b += ADJ_SORT_BLOCK) cnt[b] = 0u;
-    __syncthreads();
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * ADJ_SORT_TILE;
-    int bin[ADJ_SORT_PER_THREAD];
-    uint32_t rank[ADJ_SORT_PER_THREAD];
-    for (int k = 0; k < ADJ_SORT_PER_THREAD; ++k) {
-        const int64_t ray = base + k * ADJ_SORT_BLOCK + t;
-        bin[k] = -1;
-        rank[k] = 0u;
-        if (ray < P.n_rays && P.keys[ray] != ADJ_SKIP) {
-            bin[k] = P.keys[ray];
-            rank[k] = atomicAdd(&cnt[bin[k]], 1u);
-        }
-    }
-    __syncthreads();
-    for (int b = t; b < ADJ_BINS; b += ADJ_SORT_BLOCK)
-        if (cnt[b]) cnt[b] = atomicAdd(&P.hist[b], cnt[b]);
-    __syncthreads();
-    const uint32_t n_list = P.hist[ADJ_BINS];
-    for (int k = 0; k < ADJ_SORT_PER_THREAD; ++k)
-        if (bin[k] >= 0) {
-            const uint32_t pos = cnt[bin[k]] + rank[k];
-            if (pos < n_list) P.list[pos] = static_cast<uint32_t>(base + k * ADJ_SORT_BLOCK + t);
-        }
-}
+};
 
 int launch_adjoint(const AdjParams& p, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(adjoint_init_kernel, dim3(1), dim3(256), 0, s, p.ticket, p.stats, p.hist);
     if (hipGetLastError() != hipSuccess) return -1;
-    const int tiles = static_cast<int>((p.n_rays + ADJ_SORT_TILE - 1) / ADJ_SORT_TILE);
-    hipLaunchKernelGGL(adjoint_count_kernel, dim3(tiles), dim3(ADJ_SORT_BLOCK), 0, s, p);
-    if (hipGetLastError() != hipSuccess) return -1;
-    hipLaunchKernelGGL(adjoint_scan_kernel, dim3(1), dim3(ADJ_SORT_BLOCK), 0, s, p.hist);
-    if (hipGetLastError() != hipSuccess) return -1;
-    hipLaunchKernelGGL(adjoint_scatter_kernel, dim3(tiles), dim3(ADJ_SORT_BLOCK), 0, s, p);
-    if (hipGetLastError() != hipSuccess) return -1;
+    const SortBufs b{p.n_rays, p.hist, p.keys, p.list};
+    if (launch_sort(b, StepKey{p.fate, p.cot, p.n_steps, p.grad_a, p.grad_incl, p.grad_rin}, s)) return -1;
     const int grid = (p.n_lanes + ADJ_BLOCK - 1) / ADJ_BLOCK;
     hipLaunchKernelGGL(adjoint_kernel, dim3(grid), dim3(ADJ_BLOCK), 0, s, p);
     return hipGetLastError() == hipSuccess ? 0 : -1;

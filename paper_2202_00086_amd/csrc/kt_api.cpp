@@ -212,7 +212,7 @@ int make_image(const kt_camera* camera, const kt_spacetime* spacetime, const kt_
     {
         const double rho_max = std::sqrt(camera->fov_x * camera->fov_x + camera->fov_y * camera->fov_y);
         const double span = std::max(im.rho_ring, rho_max - im.rho_ring);
-        im.order_scale = kt::ORDER_BINS / span;
+        im.order_scale = kt::SORT_BINS / span;
     }
 
     const bool disk_on = disk && disk->enabled;

@@ -74,15 +74,17 @@ struct Params {
     uint8_t* need_fb;   // KT_MIXED: 1 where the ray must be re-run in FP64
     Params* ws_params;  // where ws_init leaves the device copy of this struct
     uint32_t* perm;     // dispatch order: ray id of each slot, or NULL for slot = ray id
-    uint32_t* order_hist;  // uint32[ORDER_BINS] counts, then running offsets
+    uint32_t* order_hist;  // uint32[SORT_BINS + 1] counts, then offsets and the total
     uint16_t* order_bins;  // uint16[n_rays] bin of each ray
     // launch
     int32_t persistent, batch;
     int32_t from_list;  // take ray ids from fb_list[0 .. *fb_count)
 };
 
-// Bins of the dispatch-order counting sort.
-constexpr int ORDER_BINS = 1024;
+// Bins of the device counting sorts (dispatch order, adjoint work list), and
+// the key of an id the sort leaves out.
+constexpr int SORT_BINS = 1024;
+constexpr uint16_t SORT_SKIP = 0xffff;
 
 // Workspace layout (byte offsets from the start of the caller's buffer).
 constexpr size_t WS_TICKET = 0;       // uint32 ray ticket
@@ -100,7 +102,7 @@ struct WsLayout {
     size_t fb_list;  // uint32[n_rays] (KT_MIXED)
     size_t need;     // uint8[n_rays] (KT_MIXED)
     size_t perm;     // uint32[n_rays] dispatch order
-    size_t hist;     // uint32[ORDER_BINS]
+    size_t hist;     // uint32[SORT_BINS + 1]
     size_t bins;     // uint16[n_rays]
     size_t total;
 };
@@ -113,7 +115,7 @@ inline WsLayout ws_layout(size_t n_rays, size_t n_images, bool batch, bool mixed
     w.need = align256(w.fb_list + (mixed ? 4 * n_rays : 0));
     w.perm = align256(w.need + (mixed ? n_rays : 0));
     w.hist = align256(w.perm + 4 * n_rays);
-    w.bins = align256(w.hist + 4 * ORDER_BINS);
+    w.bins = align256(w.hist + 4 * (SORT_BINS + 1));
     w.total = align256(w.bins + 2 * n_rays);
     return w;
 }
@@ -155,13 +157,10 @@ struct AdjParams {
     int32_t n_lanes, max_ckpt;
     // work list: the differentiated rays, longest forward integration first
     const int32_t* n_steps;     // the forward render's step counts (may be NULL)
-    uint32_t* hist;             // [ADJ_BINS + 1] bin counts, then offsets; [ADJ_BINS] = list length
-    uint16_t* keys;             // [n_rays] bin of each ray, ADJ_SKIP if not differentiated
+    uint32_t* hist;             // [SORT_BINS + 1] bin counts, then offsets; [SORT_BINS] = list length
+    uint16_t* keys;             // [n_rays] bin of each ray, SORT_SKIP if not differentiated
     uint32_t* list;             // [n_rays] ray ids
 };
-
-constexpr int ADJ_BINS = 1024;
-constexpr uint16_t ADJ_SKIP = 0xffff;
 
 #ifndef KT_ADJ_MAX_LANES
 #define KT_ADJ_MAX_LANES 65536
@@ -185,7 +184,7 @@ inline AdjLayout adj_layout(size_t n_rays, int64_t max_steps) {
     w.max_ckpt = static_cast<int32_t>(ck);
     w.stats = 64;
     w.hist = 256;
-    w.ckpt = align256(w.hist + 4u * (ADJ_BINS + 1));
+    w.ckpt = align256(w.hist + 4u * (SORT_BINS + 1));
     w.seg = align256(w.ckpt + static_cast<size_t>(ck) * 6u * lanes * sizeof(double));
     w.keys = align256(w.seg + 64u * 6u * lanes * sizeof(double));
     w.list = align256(w.keys + 2u * n_rays);

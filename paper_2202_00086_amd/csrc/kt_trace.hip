@@ -17,6 +17,7 @@
 #include "kt_device.h"
 #include "kt_internal.h"
 #include "kt_ray.h"
+#include "kt_sort.h"
 
 #ifndef KT_WAVES_PER_EU
 #define KT_WAVES_PER_EU 2
@@ -624,16 +625,15 @@ __global__ void ws_init_kernel(const Params p) {
     }
     if (t < 16) p.acc[t] = 0ull;
     if (p.perm)
-        for (int b = t; b < ORDER_BINS; b += blockDim.x) p.order_hist[b] = 0u;
+        for (int b = t; b <= SORT_BINS; b += blockDim.x) p.order_hist[b] = 0u;
 }
 
 // ---- dispatch order ------------------------------------------------------
 // Rays near the photon ring take the most steps; the persistent waves finish
 // soonest when those go out first and the cheap rays fill the tail.  The
-// slots are sorted by the bin of |rho - rho_ring| with a counting sort over
-// ORDER_BINS bins: a histogram, its exclusive scan, and a scatter.  The
-// order within a bin is whatever the atomics give: every ray's arithmetic is
-// independent of the lane and wave that runs it, so outputs do not change.
+// slots are sorted by the bin of |rho - rho_ring| (a counting sort over
+// SORT_BINS bins).  Every ray's arithmetic is independent of the lane and
+// wave that runs it, so outputs do not change.
 #ifndef KT_ORDER_GROUP_SHIFT
 #define KT_ORDER_GROUP_SHIFT 5
 #endif
@@ -642,104 +642,26 @@ __global__ void ws_init_kernel(const Params p) {
 // written close together in time and merge in L2 instead of reaching HBM as
 // many partial-line writes.
 constexpr int64_t ORDER_GROUP_MASK = (int64_t{1} << KT_ORDER_GROUP_SHIFT) - 1;
-constexpr int ORDER_BLOCK = 256;
-constexpr int ORDER_PER_THREAD = 16;
-constexpr int ORDER_TILE = ORDER_BLOCK * ORDER_PER_THREAD;
 
-__device__ __forceinline__ int order_bin(const Params& P, int64_t ray) {
-    ray &= ~ORDER_GROUP_MASK;
-    const Image* im = P.images;
-    int64_t pix = ray;
-    if (P.n_images > 1) {
-        im = &P.images[find_image(P, ray)];
-        pix = ray - im->first;
-    }
-    const int32_t j = static_cast<int32_t>(pix / im->nx);
-    const int32_t i = static_cast<int32_t>(pix - static_cast<int64_t>(j) * im->nx);
-    const double x = -im->fov_x + (static_cast<double>(i) + 0.5) * im->dx;
-    const double y = -im->fov_y + (static_cast<double>(j) + 0.5) * im->dy;
-    const double d = fabs(sqrt(fma(x, x, y * y)) - im->rho_ring) * im->order_scale;
-    return d < static_cast<double>(ORDER_BINS - 1) ? static_cast<int>(d) : ORDER_BINS - 1;
-}
-
-// Per-tile histograms in LDS, added into the global one.
-__global__ void __launch_bounds__(ORDER_BLOCK) order_count_kernel(const Params* pp) {
-    const Params& P = *pp;
-    __shared__ uint32_t cnt[ORDER_BINS];
-    const int t = threadIdx.x;
-    for (int b = t; b < ORDER_BINS; b += ORDER_BLOCK) cnt[b] = 0u;
-    __syncthreads();
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * ORDER_TILE;
-    for (int k = 0; k < ORDER_PER_THREAD; ++k) {
-        const int64_t ray = base + k * ORDER_BLOCK + t;
-        if (ray < P.n_rays) {
-            const int b = order_bin(P, ray);
-            P.order_bins[ray] = static_cast<uint16_t>(b);
-            atomicAdd(&cnt[b], 1u);
+struct RingKey {
+    const Params* p;  // the workspace copy
+    __device__ int operator()(int64_t ray) const {
+        const Params& P = *p;
+        ray &= ~ORDER_GROUP_MASK;
+        const Image* im = P.images;
+        int64_t pix = ray;
+        if (P.n_images > 1) {
+            im = &P.images[find_image(P, ray)];
+            pix = ray - im->first;
         }
+        const int32_t j = static_cast<int32_t>(pix / im->nx);
+        const int32_t i = static_cast<int32_t>(pix - static_cast<int64_t>(j) * im->nx);
+        const double x = -im->fov_x + (static_cast<double>(i) + 0.5) * im->dx;
+        const double y = -im->fov_y + (static_cast<double>(j) + 0.5) * im->dy;
+        const double d = fabs(sqrt(fma(x, x, y * y)) - im->rho_ring) * im->order_scale;
+        return d < static_cast<double>(SORT_BINS - 1) ? static_cast<int>(d) : SORT_BINS - 1;
     }
-    __syncthreads();
-    for (int b = t; b < ORDER_BINS; b += ORDER_BLOCK)
-        if (cnt[b]) atomicAdd(&P.order_hist[b], cnt[b]);
-}
-
-// Exclusive scan of the histogram, in place (one block).
-__global__ void __launch_bounds__(ORDER_BLOCK) order_scan_kernel(const Params* pp) {
-    constexpr int PER = ORDER_BINS / ORDER_BLOCK;
-    uint32_t* h = pp->order_hist;
-    __shared__ uint32_t part[ORDER_BLOCK];
-    const int t = threadIdx.x;
-    uint32_t v[PER], sum = 0;
-    for (int k = 0; k < PER; ++k) {
-        v[k] = h[t * PER + k];
-        sum += v[k];
-    }
-    part[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < ORDER_BLOCK; off <<= 1) {
-        const uint32_t add = t >= off ? part[t - off] : 0u;
-        __syncthreads();
-        part[t] += add;
-        __syncthreads();
-    }
-    uint32_t run = part[t] - sum;
-    for (int k = 0; k < PER; ++k) {
-        h[t * PER + k] = run;
-        run += v[k];
-    }
-}
-
-// Each tile reserves its range in every bin it touches and places its rays.
-// The bins are the ones the count pass stored, so every bin receives exactly
-// the rays it counted and the positions stay inside [0, n_rays).
-__global__ void __launch_bounds__(ORDER_BLOCK) order_scatter_kernel(const Params* pp) {
-    const Params& P = *pp;
-    __shared__ uint32_t cnt[ORDER_BINS];
-    const int t = threadIdx.x;
-    for (int b = t; b < ORDER_BINS; b += ORDER_BLOCK) cnt[b] = 0u;
-    __syncthreads();
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * ORDER_TILE;
-    int bin[ORDER_PER_THREAD];
-    uint32_t rank[ORDER_PER_THREAD];
-    for (int k = 0; k < ORDER_PER_THREAD; ++k) {
-        const int64_t ray = base + k * ORDER_BLOCK + t;
-        bin[k] = -1;
-        rank[k] = 0u;
-        if (ray < P.n_rays) {
-            bin[k] = P.order_bins[ray];
-            rank[k] = atomicAdd(&cnt[bin[k]], 1u);
-        }
-    }
-    __syncthreads();
-    for (int b = t; b < ORDER_BINS; b += ORDER_BLOCK)
-        if (cnt[b]) cnt[b] = atomicAdd(&P.order_hist[b], cnt[b]);
-    __syncthreads();
-    for (int k = 0; k < ORDER_PER_THREAD; ++k)
-        if (bin[k] >= 0) {
-            const uint32_t pos = cnt[bin[k]] + rank[k];
-            if (pos < static_cast<uint64_t>(P.n_rays)) P.perm[pos] = static_cast<uint32_t>(base + k * ORDER_BLOCK + t);
-        }
-}
+};
 
 // Copy a chunk of the image table into device memory (the table travels in
 // kernel arguments, so nothing on the host has to outlive the call).
@@ -871,14 +793,8 @@ int launch_ws_init(const Params& p, void* stream) {
 }
 
 int launch_order(const Params& p, void* stream) {
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int tiles = static_cast<int>((p.n_rays + ORDER_TILE - 1) / ORDER_TILE);
-    hipLaunchKernelGGL(order_count_kernel, dim3(tiles), dim3(ORDER_BLOCK), 0, s, p.ws_params);
-    if (check_launch()) return -1;
-    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(ORDER_BLOCK), 0, s, p.ws_params);
-    if (check_launch()) return -1;
-    hipLaunchKernelGGL(order_scatter_kernel, dim3(tiles), dim3(ORDER_BLOCK), 0, s, p.ws_params);
-    return check_launch();
+    const SortBufs b{p.n_rays, p.order_hist, p.order_bins, p.perm};
+    return launch_sort(b, RingKey{p.ws_params}, static_cast<hipStream_t>(stream));
 }
 
 int launch_reset_ticket(const Params& p, void* stream) {
