@@ -11,41 +11,66 @@
 namespace kt {
 namespace adj {
 
+// sin and cos of theta from their values (sv, cv): for a dual theta the
+// tangents follow from d sin = cos d theta, d cos = -sin d theta.
+__host__ __device__ inline void sincos_from(const double&, double sv, double cv, double* s, double* c) {
+    *s = sv;
+    *c = cv;
+}
+template <int N>
+__host__ __device__ inline void sincos_from(const Dual<N>& th, double sv, double cv, Dual<N>* s, Dual<N>* c) {
+    *s = Dual<N>(sv);
+    *c = Dual<N>(cv);
+    for (int i = 0; i < N; ++i) {
+        s->d[i] = cv * th.d[i];
+        c->d[i] = -sv * th.d[i];
+    }
+}
+
 // Gradient of H = K / (2 Sigma), K = Delta p_r^2 + p_th^2 + T^2 - W^2/Delta
 // (Carter's separated form, T = L/sin - aE sin, W = (r^2 + a^2)E - aL), with
-// respect to X = (r, theta, p_r, p_theta, L, E, a); M is a constant.
+// respect to X = (r, theta, p_r, p_theta, L, E, a); M is a constant.  (sv, cv)
+// are sin and cos of theta's value.  1/sin, 1/Sigma and 1/Delta come from one
+// reciprocal of their product.
 template <class T>
 __host__ __device__ inline void grad_H(double M, const T& r, const T& th, const T& pr, const T& pth,
-                                       const T& L, const T& E, const T& a, T g[7]) {
+                                       const T& L, const T& E, const T& a, double sv, double cv, T g[7]) {
     T s, c;
-    dsincos(th, &s, &c);
+    sincos_from(th, sv, cv, &s, &c);
     const T r2 = r * r, a2 = a * a;
     const T Sig = r2 + a2 * c * c;
     const T Del = r2 - 2.0 * M * r + a2;
     const T rho2 = r2 + a2;
-    const T Tt = L / s - a * E * s;
+    const T SD = Sig * Del;
+    const T R = 1.0 / (SD * s);
+    const T iS = Del * s * R, iD = Sig * s * R, is = SD * R;
+    const T Lis = L * is;
+    const T Tt = Lis - a * E * s;
     const T W = rho2 * E - a * L;
-    const T iS = 1.0 / Sig, iD = 1.0 / Del;
     const T pr2 = pr * pr;
     const T WiD = W * iD;
     const T K = Del * pr2 + pth * pth + Tt * Tt - W * WiD;
     const T H2 = K * iS;  // 2H
-    const T Kr = 2.0 * (r - M) * pr2 - 4.0 * r * E * WiD + WiD * WiD * (2.0 * (r - M));
-    const T Kth = -2.0 * Tt * c * (L / (s * s) + a * E);
+    const T rM2 = 2.0 * (r - M);
+    const T Kr = rM2 * pr2 - 4.0 * r * E * WiD + WiD * WiD * rM2;
+    const T Kth = -2.0 * Tt * c * (Lis * is + a * E);
     const T Ka = 2.0 * a * pr2 - 2.0 * Tt * E * s - 2.0 * WiD * (2.0 * a * E - L) + WiD * WiD * (2.0 * a);
     g[0] = 0.5 * (Kr - 2.0 * r * H2) * iS;
     g[1] = 0.5 * (Kth + 2.0 * a2 * s * c * H2) * iS;
     g[2] = Del * pr * iS;
     g[3] = pth * iS;
-    g[4] = (Tt / s + a * WiD) * iS;
+    g[4] = (Tt * is + a * WiD) * iS;
     g[5] = (-(a * s * Tt) - rho2 * WiD) * iS;
     g[6] = 0.5 * (Ka - 2.0 * a * c * c * H2) * iS;
 }
 
 // Hamilton's equations from the gradient: d/dlambda (r, th, phi, p_r, p_th).
-__host__ __device__ inline void field(double M, double a, double E, double L, const double z[5], double f[5]) {
+// Returns sin and cos of theta, which the step VJP reuses.
+__host__ __device__ inline void field(double M, double a, double E, double L, const double z[5], double f[5],
+                                      double* sv, double* cv) {
+    dsincos(z[1], sv, cv);
     double g[7];
-    grad_H<double>(M, z[0], z[1], z[3], z[4], L, E, a, g);
+    grad_H<double>(M, z[0], z[1], z[3], z[4], L, E, a, *sv, *cv, g);
     f[0] = g[2];
     f[1] = g[3];
     f[2] = g[4];
@@ -63,8 +88,8 @@ struct ParBar {
 // this is the Hessian-vector product of H along u = (-v_pr, -v_th, v_r, v_th,
 // v_phi, 0, 0) in (r, th, p_r, p_th, L, E, a), taken by forward-mode duals
 // on grad_H.
-__host__ __device__ inline void field_vjp(double M, double a, double E, double L, const double z[5],
-                                          const double v[5], double zbar[5], ParBar* pb) {
+__host__ __device__ inline void field_vjp(double M, double a, double E, double L, const double z[5], double sv,
+                                          double cv, const double v[5], double zbar[5], ParBar* pb) {
     using D = Dual<1>;
     D rr(z[0]), tt(z[1]), pp(z[3]), qq(z[4]), LL(L);
     rr.d[0] = -v[3];
@@ -73,7 +98,7 @@ __host__ __device__ inline void field_vjp(double M, double a, double E, double L
     qq.d[0] = v[1];
     LL.d[0] = v[2];
     D g[7];
-    grad_H<D>(M, rr, tt, pp, qq, LL, D(E), D(a), g);
+    grad_H<D>(M, rr, tt, pp, qq, LL, D(E), D(a), sv, cv, g);
     zbar[0] += g[0].d[0];
     zbar[1] += g[1].d[0];
     zbar[3] += g[2].d[0];
@@ -107,7 +132,7 @@ __host__ __device__ constexpr double dp_b(int j) {
 // run-time indices they would live in scratch memory, at half the speed.
 __host__ __device__ inline void dp_step_vjp(double M, double a, double E, double L, const double y[5], double h,
                                             double ybar[5], ParBar* pb) {
-    double Y[6][5], K[5][5];
+    double Y[6][5], K[5][5], S[6], C[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
 #pragma unroll
@@ -117,7 +142,10 @@ __host__ __device__ inline void dp_step_vjp(double M, double a, double E, double
             for (int l = 0; l < j; ++l) acc += dp_a(j, l) * K[l][i];
             Y[j][i] = y[i] + h * acc;
         }
-        if (j < 5) field(M, a, E, L, Y[j], K[j]);
+        if (j < 5)
+            field(M, a, E, L, Y[j], K[j], &S[j], &C[j]);
+        else
+            dsincos(Y[j][1], &S[j], &C[j]);
     }
     double kb[6][5];
 #pragma unroll
@@ -127,7 +155,7 @@ __host__ __device__ inline void dp_step_vjp(double M, double a, double E, double
 #pragma unroll
     for (int j = 5; j >= 0; --j) {
         double Yb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        field_vjp(M, a, E, L, Y[j], kb[j], Yb, pb);
+        field_vjp(M, a, E, L, Y[j], S[j], C[j], kb[j], Yb, pb);
 #pragma unroll
         for (int i = 0; i < 5; ++i) ybar[i] += Yb[i];
 #pragma unroll

@@ -62,9 +62,10 @@ __host__ __device__ inline Dual<N> operator*(const Dual<N>& a, const Dual<N>& b)
 }
 template <int N>
 __host__ __device__ inline Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) {
-    const double q = a.v / b.v;
+    const double ib = 1.0 / b.v;  // one division for the value and all tangents
+    const double q = a.v * ib;
     Dual<N> r(q);
-    for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - q * b.d[i]) / b.v;
+    for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - q * b.d[i]) * ib;
     return r;
 }
 template <int N>
