@@ -206,8 +206,10 @@ def run_f4_forms(K, torch, W, steps):
         st = K.read_stats(r.out)
         hr = r.out["max_rel_h"][r.out["fate"] <= K.DISK]
         hr = hr[~torch.isnan(hr)]
+        kerr_dp45 = p.get("metric", 0) == 0
         res[name] = {"ms_per_image": 1e3 * t, "rays_per_s": r.n / t, "stage_evals_per_s": st.evals / t,
                      "evals_per_ray": st.evals / r.n,
+                     "alu_frac": st.evals / t * flop_per_eval(src_on=False) / PEAK_FP64_VECTOR if kerr_dp45 else None,
                      "max_rel_h": float(hr.max().item()) if hr.numel() else None,
                      "fates": [int(c) for c in st.fate_count[:6]]}
         del r
@@ -277,7 +279,8 @@ def run_batch_forms(K, torch, W, steps):
     br.render()
     t = _time(torch, br.render, steps)
     st = K.read_stats(br.out)
-    res["batch_fp64"] = {"rays_per_s": n / t, "stage_evals_per_s": st.evals / t, "ms_per_step": 1e3 * t}
+    res["batch_fp64"] = {"rays_per_s": n / t, "stage_evals_per_s": st.evals / t, "ms_per_step": 1e3 * t,
+                         "alu_frac": st.evals / t * flop_per_eval(src_on=False) / PEAK_FP64_VECTOR}
     ref = {k: v for k, v in br.out.items()}
     singles = [K.Renderer(device="cuda:0", want=BATCH_WANT, stats=False, **W.image_params(im, integ))
                for im in images]
