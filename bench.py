@@ -321,7 +321,18 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (three times), "
                          "to calibrate HBM byte counters")
+    ap.add_argument("--only", choices=("batch", "adjoint", "images", "integrators"), default=None,
+                    help="run one extra form alone and print its JSON (for profiling); no headline line")
     args = ap.parse_args()
+    if args.only:
+        import torch
+
+        from paper_2202_00086_amd import kerrtrace as K
+        from paper_2202_00086_amd import workloads as W
+        run = {"batch": run_batch_forms, "adjoint": run_adjoint_form, "images": run_f4_forms,
+               "integrators": run_scheme_forms}[args.only]
+        print(json.dumps({args.only: run(K, torch, W, max(1, args.steps))}), flush=True)
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration << 20
