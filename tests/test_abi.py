@@ -307,3 +307,15 @@ def test_qmetric_not_in_batches_or_the_adjoint():
     cam, st, disk, src, integ = K.make_structs(**dict(W.differentiable_disk(n=16), metric=1, q=0.4, a=0.0))
     assert K.kt_adjoint(cam, st, disk, integ, 0x1000, None, 0x2000, None, None, None, None, C.c_void_p(0x100000),
                         1 << 40, None) == K.KT_EINVAL
+
+
+def test_plain_c_program_uses_the_header_and_library(tmp_path):
+    """A C99 program compiled with gcc against include/kerrtrace.h links the
+    library and reads its version (no GPU needed for that call)."""
+    import subprocess
+    from paper_2202_00086_amd import kerrtrace as K
+    from tests.c_abi import build_demo
+    exe = build_demo(str(tmp_path))
+    r = subprocess.run([exe, "--version"], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
+    assert int(r.stdout.strip()) == K.kt_version()
