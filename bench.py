@@ -425,7 +425,12 @@ def main():
            "fates": main_form["fates"], "roofline": roofline,
            "form_note": "value is the FP64 form that meets max |H|_rel <= 1e-10; the FP64 "
                         "rtol 1e-11 and mixed-precision forms are in 'forms'",
-           "kernel_source_sha256": kernel_source_hash()}
+           "kernel_source_sha256": kernel_source_hash(),
+           "paper_context": {"value": 1e3, "unit": "rays/s", "kind": "order of magnitude, not a target",
+                             "note": "the paper states that its serial Fortran code traces 1024^2 geodesics in "
+                                     "a time of the same order as GRay's, O(10^3) s, on an unnamed CPU, and that "
+                                     "Odyssey (CUDA) is about two orders of magnitude faster; it prints no exact "
+                                     "timing"}}
     if forms:
         out["forms"] = forms
     if batch:
