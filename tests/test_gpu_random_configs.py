@@ -1,0 +1,108 @@
+"""Seeded random camera configurations (valid inputs only) on the GPU
+against the oracle, element by element: spins, inclinations near the poles
+and in between, observer distances, fields of view, ragged resolutions,
+tolerances, the four adaptive schemes, Keplerian and constant-l0 disks with
+power-law or tapered emissivity, and the point source."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2202_00086_amd import workloads as W
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+N_CASES = 40
+
+
+def _config(rng):
+    a = float(rng.uniform(0.0, 0.998))
+    band = int(rng.integers(3))
+    incl = float((rng.uniform(0.05, 0.3), rng.uniform(0.3, 2.84), rng.uniform(2.84, 3.09))[band])
+    r_obs = float(10 ** rng.uniform(1.5, 3.0))
+    fov = float(rng.uniform(4.0, 25.0))
+    nx, ny = (int(v) for v in rng.integers(3, 41, size=2))
+    method = int(rng.choice([1, 2, 3, 4]))
+    rtol = float(rng.choice([1e-10, 1e-11, 1e-12]))
+    p = dict(M=1.0, a=a, r_obs=r_obs, incl=incl, fov_x=fov, fov_y=fov * float(rng.uniform(0.5, 1.5)), nx=nx,
+             ny=ny, method=method, rtol=rtol, atol=rtol, h_init=1.0, cap_buffer=0.01, r_escape=0.0,
+             max_steps=1_000_000)
+    if rng.uniform() < 0.6:
+        r_in = W.isco(a) * float(rng.uniform(1.0, 1.5))
+        p.update(disk_on=1, r_in=r_in, r_out=r_in + float(rng.uniform(5.0, 25.0)), emis_q=2.0,
+                 emis_model=int(rng.integers(2)))
+        if rng.uniform() < 0.4:
+            p.update(rotation=1, l0=float(rng.uniform(2.0, 3.5)) if a < 0.9 else float(rng.uniform(1.7, 2.2)))
+    if rng.uniform() < 0.3:
+        p.update(src_on=1, r_src=r_obs)
+    return p
+
+
+CONFIGS = [_config(np.random.default_rng(7000 + k)) for k in range(N_CASES)]
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2202_00086_amd import kerrtrace
+    return kerrtrace
+
+
+@pytest.mark.parametrize("k", range(N_CASES))
+def test_random_configuration(K, k):
+    import torch
+    p = CONFIGS[k]
+    nx, ny = p["nx"], p["ny"]
+    print(f"[gpu-case] random config {k}: {p}", flush=True)
+    sys.stdout.flush()
+    r = K.Renderer(device="cuda:0", **p)
+    out = r.render()
+    torch.cuda.synchronize()
+    g = {key: v.cpu().numpy() for key, v in out.items() if key != "stats"}
+    st = K.read_stats(out)
+    o = O.trace_pixels(O.Setup(**p))
+    P.check_fates(g["fate"], o["fate"], nx, ny, min_allowed=2)
+    m = P.value_mask(g, o, nx, ny)
+    assert st.rays == nx * ny and sum(st.fate_count) == nx * ny
+    np.testing.assert_array_equal(g["fate"] == K.INVALID, o["fate"] == O.INVALID)
+    if p.get("disk_on"):
+        d = m & (o["fate"] == O.DISK)
+        for key in ("r_hit", "g", "intensity"):
+            P.check_values(g, o, key, d, rtol=1e-8)
+    if p.get("src_on") and p["method"] != K.BS:
+        # Bulirsch-Stoer's long steps make the swept angle step-placement
+        # sensitive beyond this tolerance (its own test calibrates it)
+        e = m & np.isfinite(o["deflection"])
+        P.check_values(g, o, "deflection", e, rtol=1e-7)
+    # the constraint: same size on both sides where the rays agree
+    h_g, h_o = g["max_rel_h"][m], o["max_rel_h"][m]
+    ok = np.isfinite(h_g) & np.isfinite(h_o)
+    if ok.any():
+        assert np.nanmax(h_g[ok]) < 10 * max(np.nanmax(h_o[ok]), 1e-14)
+
+
+def test_random_configurations_as_one_batch(K):
+    """The same configurations (with one shared integrator, DP45 at 1e-12) as
+    one batch: every image equals its own single render bit for bit."""
+    import torch
+    integ = dict(method=1, rtol=1e-12, atol=1e-12, h_init=1.0, cap_buffer=0.01, r_escape=0.0,
+                 max_steps=1_000_000)
+    images = [{key: v for key, v in c.items() if key in W.IMAGE_KEYS} for c in CONFIGS]
+    print(f"[gpu-case] random batch of {len(images)} images", flush=True)
+    sys.stdout.flush()
+    br = K.BatchRenderer(images, device="cuda:0", **integ)
+    br.render()
+    torch.cuda.synchronize()
+    for k, im in enumerate(images):
+        r = K.Renderer(device="cuda:0", **W.image_params(im, integ))
+        out = r.render()
+        torch.cuda.synchronize()
+        f, n = br.first[k], br.sizes[k]
+        for key in ("fate", "r_hit", "g", "intensity", "deflection", "max_rel_h", "n_steps"):
+            if key in out and key in br.out:
+                np.testing.assert_array_equal(br.out[key][f:f + n].cpu().numpy().view(np.uint8),
+                                              out[key].cpu().numpy().view(np.uint8), err_msg=f"image {k} {key}")
