@@ -106,3 +106,71 @@ def test_random_configurations_as_one_batch(K):
             if key in out and key in br.out:
                 np.testing.assert_array_equal(br.out[key][f:f + n].cpu().numpy().view(np.uint8),
                                               out[key].cpu().numpy().view(np.uint8), err_msg=f"image {k} {key}")
+
+
+MIXED = [k for k in range(N_CASES) if CONFIGS[k]["method"] == 1][:8]
+
+
+@pytest.mark.parametrize("k", MIXED)
+def test_random_configuration_mixed(K, k):
+    """The DP45 configurations in mixed precision (budget 1e-10, r_switch
+    drawn so that some rays use the FP32 part): rays kept from the mixed
+    pass end within the budget, and rays re-run in FP64 equal the FP64 render
+    bit for bit."""
+    import torch
+    p = CONFIGS[k]
+    rng = np.random.default_rng(9000 + k)
+    r_switch = float(p["r_obs"] * rng.uniform(0.2, 0.9))
+    print(f"[gpu-case] random mixed config {k}: r_switch {r_switch:.1f}", flush=True)
+    sys.stdout.flush()
+    ref = K.Renderer(device="cuda:0", **p).render()
+    mix = K.Renderer(device="cuda:0", **dict(p, precision=K.MIXED, h_budget=1e-10, r_switch=r_switch)).render()
+    torch.cuda.synchronize()
+    f = {key: v.cpu().numpy() for key, v in ref.items() if key != "stats"}
+    m = {key: v.cpu().numpy() for key, v in mix.items() if key != "stats"}
+    # rays kept from the mixed pass are within the budget; the others were
+    # re-run in FP64 (whose own |H|_rel may exceed it at loose rtol)
+    re = m["used_fp64"].astype(bool)
+    kept = ~re & (m["fate"] != K.INVALID)
+    if kept.any():
+        assert np.nanmax(m["max_rel_h"][kept]) <= 1e-10
+    for key in ("fate", "r_hit", "g", "intensity", "max_rel_h", "n_steps"):
+        np.testing.assert_array_equal(m[key][re].view(np.uint8), f[key][re].view(np.uint8), err_msg=key)
+
+
+def _qconfig(rng):
+    q = float(rng.uniform(-0.45, 1.5))
+    return dict(M=1.0, a=0.0, metric=1, q=q, r_obs=float(10 ** rng.uniform(1.7, 2.7)),
+                incl=float(rng.uniform(0.2, 2.9)), fov_x=float(rng.uniform(6.0, 20.0)),
+                fov_y=float(rng.uniform(6.0, 20.0)), nx=int(rng.integers(5, 33)), ny=int(rng.integers(5, 33)),
+                method=int(rng.choice([1, 2, 3, 4])), rtol=1e-12, atol=1e-12, h_init=1.0, cap_buffer=0.01,
+                r_escape=0.0, max_steps=1_000_000, sky_on=1, grid_deg=6.0, line_deg=0.25)
+
+
+QCONFIGS = [_qconfig(np.random.default_rng(8000 + k)) for k in range(8)]
+
+
+@pytest.mark.parametrize("k", range(len(QCONFIGS)))
+def test_random_qmetric_configuration(K, k):
+    """Random q-metric images on the coloured sphere: fates by the boundary
+    rule, escape directions to 1e-9 where the sky codes are away from code
+    boundaries."""
+    import torch
+    p = QCONFIGS[k]
+    nx, ny = p["nx"], p["ny"]
+    print(f"[gpu-case] random q-metric config {k}: {p}", flush=True)
+    sys.stdout.flush()
+    out = K.Renderer(device="cuda:0", **p).render()
+    torch.cuda.synchronize()
+    g = {key: v.cpu().numpy() for key, v in out.items() if key != "stats"}
+    o = O.trace_pixels(O.Setup(**p))
+    P.check_fates(g["fate"], o["fate"], nx, ny, min_allowed=2)
+    esc = (g["fate"] == K.ESCAPED) & (o["fate"] == O.ESCAPED) & ~P.boundary_mask(o["fate"].reshape(ny, nx)).ravel()
+
+    def dirs(th, ph):
+        return np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], -1)
+    if esc.any():
+        d = np.linalg.norm(dirs(g["theta_f"][esc], g["phi_f"][esc]) - dirs(o["theta_f"][esc], o["phi_f"][esc]),
+                           axis=1)
+        tol = 1e-9 if p["method"] != K.BS else 1e-7
+        assert d.max() < tol, (d.max(), p["method"])
