@@ -581,14 +581,16 @@ int kt_autotune_batch(int32_t n_images, const kt_image* images, const kt_integra
     } else {
         for (int block : {128, 256})
             for (int waves : {1, 2})
-                for (int batch : {4, 8, 16, 32, 64}) cand.push_back(kt_launch{1, block, waves * 256 / block, batch});
+                for (int batch : {4, 8, 16, 32, 64})
+                    cand.push_back(kt_launch{1, block, waves * 256 / block, batch, KT_ORDER_RING});
     }
     // the untimed first render also validates every shape before any timing
     for (const kt_launch& ln : cand)
         if ((ln.block != 64 && ln.block != 128 && ln.block != 256) || ln.batch < 1 || ln.batch > 4096 ||
-            ln.blocks_per_cu < 0 || ln.blocks_per_cu > 64)
-            return fail(KT_EINVAL, "candidate launch shape out of range (block %d, blocks_per_cu %d, batch %d)",
-                        ln.block, ln.blocks_per_cu, ln.batch);
+            ln.blocks_per_cu < 0 || ln.blocks_per_cu > 64 ||
+            (ln.order != KT_ORDER_RING && ln.order != KT_ORDER_ROWS))
+            return fail(KT_EINVAL, "candidate launch shape out of range (block %d, blocks_per_cu %d, batch %d, order %d)",
+                        ln.block, ln.blocks_per_cu, ln.batch, ln.order);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {

@@ -266,6 +266,9 @@ def test_autotune_validation():
     assert call(one, 1, 2, None) == K.KT_EINVAL                    # no place for the result
     assert call(bad, 1, 2, C.byref(best)) == K.KT_EINVAL           # shape out of range
     assert "candidate" in K.kt_last_error()
+    bad_order = (K.kt_launch * 1)(K.kt_launch(1, 256, 0, 32, 7))
+    assert call(bad_order, 1, 2, C.byref(best)) == K.KT_EINVAL     # unknown dispatch order
+    assert "order 7" in K.kt_last_error()
 
 
 @no_gpu_only
