@@ -31,13 +31,15 @@ __host__ __device__ inline void sincos_from(const Dual<N>& th, double sv, double
 // (Carter's separated form, T = L/sin - aE sin, W = (r^2 + a^2)E - aL), with
 // respect to X = (r, theta, p_r, p_theta, L, E, a); M is a constant.  (sv, cv)
 // are sin and cos of theta's value.  1/sin, 1/Sigma and 1/Delta come from one
-// reciprocal of their product.
+// reciprocal of their product.  E and a are plain numbers: the dual form is
+// only ever taken along directions in (r, theta, p_r, p_theta, L).
 template <class T>
 __host__ __device__ inline void grad_H(double M, const T& r, const T& th, const T& pr, const T& pth,
-                                       const T& L, const T& E, const T& a, double sv, double cv, T g[7]) {
+                                       const T& L, double E, double a, double sv, double cv, T g[7]) {
     T s, c;
     sincos_from(th, sv, cv, &s, &c);
-    const T r2 = r * r, a2 = a * a;
+    const T r2 = r * r;
+    const double a2 = a * a;
     const T Sig = r2 + a2 * c * c;
     const T Del = r2 - 2.0 * M * r + a2;
     const T rho2 = r2 + a2;
@@ -98,7 +100,7 @@ __host__ __device__ inline void field_vjp(double M, double a, double E, double L
     qq.d[0] = v[1];
     LL.d[0] = v[2];
     D g[7];
-    grad_H<D>(M, rr, tt, pp, qq, LL, D(E), D(a), sv, cv, g);
+    grad_H<D>(M, rr, tt, pp, qq, LL, E, a, sv, cv, g);
     zbar[0] += g[0].d[0];
     zbar[1] += g[1].d[0];
     zbar[3] += g[2].d[0];
