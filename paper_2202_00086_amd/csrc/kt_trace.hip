@@ -4,10 +4,13 @@
 // (r, theta, phi, p_r, p_theta), its constants (E, L) and its step control in
 // VGPRs and advances one integrator step per loop iteration; all busy lanes
 // of a wave evaluate the six (DP45) or four (RK4) right-hand sides together.
-// When a ray ends, the lane writes that ray's outputs and takes the next ray
-// id from its wave's queue, a contiguous range of ids that the wave refills
-// in batches from a global atomic ticket (persistent mode).  A wave exits
-// once the ticket has passed the last ray and all its lanes are idle.
+// When a ray ends, the lane writes that ray's outputs and takes the next
+// slot from its wave's queue, a contiguous range of slots that the wave
+// refills in batches from a global atomic ticket (persistent mode).  A slot
+// names a ray through the dispatch order (ring first: rays near the photon
+// ring, which take the most steps, go out first), through the compacted list
+// of the FP64 re-run pass, or directly.  A wave exits once the ticket has
+// passed the last slot and all its lanes are idle.
 //
 // Event location (disk plane, source sphere) reuses the same loop: a lane in
 // LOCATE mode takes trial steps of size h' from the step's start state, so
