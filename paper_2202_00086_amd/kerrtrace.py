@@ -281,6 +281,21 @@ class Renderer:
             raise KtError(rc, kt_last_error())
         return self.out
 
+    def autotune(self, candidates=None, repeats=2, stream=None):
+        """Pick the fastest launch shape for this image (kt_autotune_batch on
+        a one-image table, Kerr spacetimes), keep it for later renders and
+        return (best, times_ms)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        table = image_table([split_params(self.params)[0]])
+        rc, best, times = kt_autotune_batch(table, self.integ, self.c_out, self.ws.data_ptr(), self.ws_bytes,
+                                            C.c_void_p(stream.cuda_stream), candidates, repeats)
+        if rc != KT_OK:
+            raise KtError(rc, kt_last_error())
+        self.launch = best
+        return best, times
+
 
 _IMAGE_KEYS = ("M", "a", "metric", "q", "r_obs", "incl", "fov_x", "fov_y", "nx", "ny", "disk_on", "r_in", "r_out",
                "emis_q", "rotation", "l0", "emis_model", "src_on", "r_src", "sky_on", "grid_deg", "line_deg")

@@ -211,3 +211,26 @@ def test_autotune_picks_the_fastest_candidate(K):
     best, times = br.autotune(candidates=cands, repeats=2)
     assert len(times) == 2 and min(times) > 0.0
     assert (best.persistent, best.block) == [(1, 64), (0, 128)][int(np.argmin(times))]
+
+
+def test_single_image_autotune(K):
+    """Renderer.autotune (a one-image table): the shape it keeps renders the
+    same outputs as the default launch, bit for bit."""
+    import torch
+    params = dict(W.kerr_disk(a=0.7, incl_deg=50.0, n=48, r_in=W.isco(0.7)), src_on=1, r_src=1000.0)
+    _announce("single-image autotune")
+    r = K.Renderer(device="cuda:0", **params)
+    r.render()
+    torch.cuda.synchronize()
+    ref = _host(K, r.out)
+    best, times = r.autotune(repeats=1)
+    assert len(times) == K.AUTOTUNE_DEFAULT_COUNT and min(times) > 0.0
+    assert r.launch is best
+    for key in ref:
+        r.out[key].fill_(0)
+    r.render()
+    torch.cuda.synchronize()
+    got = _host(K, r.out)
+    for key in _BITWISE:
+        if key in ref:
+            np.testing.assert_array_equal(got[key].view(np.uint8), ref[key].view(np.uint8), err_msg=key)
