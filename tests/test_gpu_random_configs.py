@@ -1,9 +1,9 @@
 """Seeded random camera configurations (valid inputs only) on the GPU
-against the oracle, element by element: spins, inclinations near the poles
-and in between, observer distances, fields of view, ragged resolutions,
-tolerances, the four adaptive schemes, Keplerian and constant-l0 disks with
-power-law or tapered emissivity, and the point source."""
-import math
+against the oracle, element by element: spins of either sign, inclinations
+near the poles and in between, observer distances, fields of view, ragged
+resolutions, tolerances, the four adaptive schemes, Keplerian and
+constant-l0 disks with power-law or tapered emissivity, and the point
+source."""
 import sys
 
 import numpy as np
@@ -15,11 +15,9 @@ from tests import parity as P
 
 pytestmark = pytest.mark.gpu
 
-N_CASES = 40
 
-
-def _config(rng):
-    a = float(rng.uniform(0.0, 0.998))
+def _config(rng, retrograde=False):
+    a = float(rng.uniform(-0.998, -0.05)) if retrograde else float(rng.uniform(0.0, 0.998))
     band = int(rng.integers(3))
     incl = float((rng.uniform(0.05, 0.3), rng.uniform(0.3, 2.84), rng.uniform(2.84, 3.09))[band])
     r_obs = float(10 ** rng.uniform(1.5, 3.0))
@@ -41,7 +39,11 @@ def _config(rng):
     return p
 
 
-CONFIGS = [_config(np.random.default_rng(7000 + k)) for k in range(N_CASES)]
+# 40 with spin along +z, then 8 with negative spin (the hole counter-rotates
+# with respect to the disk and the camera's phi direction)
+CONFIGS = ([_config(np.random.default_rng(7000 + k)) for k in range(40)] +
+           [_config(np.random.default_rng(7500 + k), retrograde=True) for k in range(8)])
+N_CASES = len(CONFIGS)
 
 
 @pytest.fixture(scope="module")
