@@ -250,7 +250,8 @@ int kt_render_batch(int32_t n_images, const kt_image *images, const kt_integrato
                     const kt_outputs *out, void *workspace, size_t workspace_bytes,
                     void *hip_stream, const kt_launch *launch);
 
-/* Workspace size in bytes for kt_render_batch (0 on bad input). */
+/* Workspace size in bytes for kt_render_batch (0 on bad input, including a
+   total of 2^31 rays or more). */
 size_t kt_workspace_bytes_batch(int32_t n_images, const kt_image *images,
                                 const kt_integrator *integ);
 

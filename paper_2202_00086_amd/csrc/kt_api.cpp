@@ -428,6 +428,7 @@ int kt_version(void) { return KT_VERSION_NUMBER; }
 size_t kt_workspace_bytes(const kt_camera* camera, const kt_integrator* integ) {
     if (!camera || !integ || camera->nx < 1 || camera->ny < 1) return 0;
     const size_t n = static_cast<size_t>(camera->nx) * static_cast<size_t>(camera->ny);
+    if (n >= (size_t{1} << 31)) return 0;  // ray ids are int32
     return kt::ws_layout(n, 1, false, is_mixed(integ)).total;
 }
 
@@ -438,6 +439,7 @@ size_t kt_workspace_bytes_batch(int32_t n_images, const kt_image* images, const 
         if (images[k].camera.nx < 1 || images[k].camera.ny < 1) return 0;
         n += static_cast<size_t>(images[k].camera.nx) * static_cast<size_t>(images[k].camera.ny);
     }
+    if (n >= (size_t{1} << 31)) return 0;  // ray ids are int32
     return kt::ws_layout(n, static_cast<size_t>(n_images), n_images > 1, is_mixed(integ)).total;
 }
 

@@ -72,6 +72,7 @@ BAD = [
     dict(r_obs=1.5, a=0.0),
     dict(nx=0),
     dict(ny=-3),
+    dict(nx=65536, ny=32768),                        # 2^31 rays: beyond the int32 ray ids
     dict(fov_x=0.0),
     dict(incl=0.0),
     dict(incl=math.pi),
@@ -168,6 +169,21 @@ def test_launch_shape_validated():
 def test_workspace_bytes_zero_on_bad_camera():
     K, cam, st, disk, src, integ = _args(nx=0)
     assert K.kt_workspace_bytes(cam, integ) == 0
+    K, cam, st, disk, src, integ = _args(nx=65536, ny=32768)  # 2^31 rays
+    assert K.kt_workspace_bytes(cam, integ) == 0
+
+
+@no_gpu_only
+def test_batch_total_beyond_int32_ray_ids_is_rejected():
+    """Three images of 2^30 rays each: every image is valid, their total is
+    not."""
+    K, table, integ = _batch([dict(GOOD_IMAGE, nx=32768, ny=32768) for _ in range(3)])
+    out = K.kt_outputs()
+    out.fate = 0x1000
+    assert K.kt_workspace_bytes_batch(table, integ) == 0
+    rc = K.kt_render_batch(table, integ, out, C.c_void_p(0x100000), 1 << 30, None)
+    assert rc == K.KT_EINVAL
+    assert "2^31" in K.kt_last_error()
 
 
 def _batch(images, **integ_kw):
