@@ -498,6 +498,7 @@ int kt_render_batch(int32_t n_images, const kt_image* images, const kt_integrato
 size_t kt_adjoint_workspace_bytes(const kt_camera* camera, const kt_integrator* integ) {
     if (!camera || !integ || camera->nx < 1 || camera->ny < 1) return 0;
     const size_t n = static_cast<size_t>(camera->nx) * static_cast<size_t>(camera->ny);
+    if (n >= (size_t{1} << 31)) return 0;  // ray ids are int32
     return kt::adj_layout(n, integ->max_steps).total;
 }
 

@@ -171,6 +171,7 @@ def test_workspace_bytes_zero_on_bad_camera():
     assert K.kt_workspace_bytes(cam, integ) == 0
     K, cam, st, disk, src, integ = _args(nx=65536, ny=32768)  # 2^31 rays
     assert K.kt_workspace_bytes(cam, integ) == 0
+    assert K.kt_adjoint_workspace_bytes(cam, integ) == 0
 
 
 @no_gpu_only
