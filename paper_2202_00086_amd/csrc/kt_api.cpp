@@ -204,6 +204,11 @@ int make_image(const kt_camera* camera, const kt_spacetime* spacetime, const kt_
     }
     const double r_cap = r_plus + integ->capture_buffer;
     if (!(camera->r_obs > r_cap)) return fail(KT_EINVAL, "r_obs must exceed r_+ + capture_buffer");
+    // e.g. r_obs so large that r_obs^2 overflows, or a q-metric power that
+    // under- or overflows
+    if (!finite_all({im.E0, im.cE, im.cL, im.cth, im.g_rr, im.dx, im.dy}) || !(im.E0 > 0.0))
+        return fail(KT_EINVAL, "camera constants are not finite (r_obs %g, q %g out of range)", camera->r_obs,
+                    spacetime->q);
     const double r_esc = integ->r_escape == 0.0 ? 1.1 * camera->r_obs : integ->r_escape;
     if (!(r_esc > camera->r_obs)) return fail(KT_EINVAL, "r_escape must exceed r_obs");
     im.r_cap = r_cap;

@@ -70,6 +70,7 @@ BAD = [
     dict(M=0.0, a=0.1),
     dict(M=-1.0),
     dict(r_obs=1.5, a=0.0),
+    dict(r_obs=1e300),                               # r_obs^2 overflows: camera constants not finite
     dict(nx=0),
     dict(ny=-3),
     dict(nx=65536, ny=32768),                        # 2^31 rays: beyond the int32 ray ids
