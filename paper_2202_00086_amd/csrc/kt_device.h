@@ -409,10 +409,11 @@ __device__ __forceinline__ void rhs(const ST& st, const RayConst& rc, const doub
 
 // sin and cos of theta0 + d from those of theta0 and the Taylor series of
 // sin d through d^13 and cos d through d^14: exact to rounding for
-// |d| <= 0.6, which covers the angle change between a step's start and any of
-// its stages (per-step changes stay below ~0.02 rad at the tolerances used);
-// the truncation grows smoothly beyond (1e-12 at |d| = 1) for the wild stages
-// of steps that get rejected.
+// |d| <= 0.5 (truncation of sin d below 0.5 ulp there, 3 ulp at 0.6), which
+// covers the angle change between a step's start and any of its stages
+// (per-step changes stay below ~0.02 rad at the tolerances used); the
+// truncation grows smoothly beyond (1e-12 at |d| = 1) for the wild stages of
+// steps that get rejected.
 __device__ __forceinline__ void sincos_shift(double s0, double c0, double d, double* s_out, double* c_out) {
     const double d2 = d * d;
     double ps = -1.0 / 6227020800.0;       // -1/13!
