@@ -284,60 +284,71 @@ __device__ __forceinline__ RayConst make_ray_const(const QSpacetime&, double E, 
 }
 
 // e^x for |x| < ~700: x = n ln 2 + t with |t| <= (ln 2)/2 (Cody-Waite with a
-// two-part ln 2), e^t from its Taylor series through t^13 (truncation below
-// 5e-18 relative), scaled by 2^n.  About 1 ulp.
+// two-part ln 2), e^t = 1 + t + t^2 G(t) with G a degree-9 minimax polynomial
+// (coefficients from minimax_coefs.py; relative error below 1e-17 with the
+// coefficients rounded to double, where Taylor's series needs through t^13),
+// scaled by 2^n.  About 1 ulp.
 __device__ __forceinline__ double exp_fast(double x) {
     constexpr double LOG2E = 1.4426950408889634074;
     constexpr double LN2_HI = 6.93147180369123816490e-01;  // 32 significant bits
     constexpr double LN2_LO = 1.90821492927058770002e-10;
     const double n = __builtin_rint(x * LOG2E);
     const double t = fma(-n, LN2_LO, fma(-n, LN2_HI, x));
-    double p = 1.0 / 6227020800.0;       // 1/13!
-    p = fma(p, t, 1.0 / 479001600.0);    // 1/12!
-    p = fma(p, t, 1.0 / 39916800.0);     // 1/11!
-    p = fma(p, t, 1.0 / 3628800.0);      // 1/10!
-    p = fma(p, t, 1.0 / 362880.0);       // 1/9!
-    p = fma(p, t, 1.0 / 40320.0);        // 1/8!
-    p = fma(p, t, 1.0 / 5040.0);         // 1/7!
-    p = fma(p, t, 1.0 / 720.0);          // 1/6!
-    p = fma(p, t, 1.0 / 120.0);          // 1/5!
-    p = fma(p, t, 1.0 / 24.0);           // 1/4!
-    p = fma(p, t, 1.0 / 6.0);            // 1/3!
-    p = fma(p, t, 0.5);
-    p = fma(p, t, 1.0);
-    p = fma(p, t, 1.0);
+    double p = 2.511003970895208e-08;
+    p = fma(p, t, 2.763264062648625e-07);
+    p = fma(p, t, 2.755724236405712e-06);
+    p = fma(p, t, 2.4801487366143253e-05);
+    p = fma(p, t, 0.00019841269886566477);
+    p = fma(p, t, 0.001388888894778543);
+    p = fma(p, t, 0.008333333333322215);
+    p = fma(p, t, 0.041666666666522106);
+    p = fma(p, t, 0.16666666666666674);
+    p = fma(p, t, 0.500000000000001);
+    p = fma(p, t, 1.0);  // 1 + t G
+    p = fma(p, t, 1.0);  // 1 + t + t^2 G
     return __builtin_amdgcn_ldexp(p, static_cast<int>(n));
 }
 
-// ln x for finite x > 0 (NaN for x <= 0): x = 2^e m with m in [1/sqrt 2,
-// sqrt 2), ln m = 2 atanh s with s = (m - 1)/(m + 1), |s| <= 0.172, from the
-// series of atanh through s^21 (truncation below 3e-17 relative).  About
-// 2 ulp.
-__device__ __forceinline__ double log_fast(double x) {
-    constexpr double LN2_HI = 6.93147180369123816490e-01;
-    constexpr double LN2_LO = 1.90821492927058770002e-10;
+// ln x = e ln 2 + ln m for x = 2^e m, m in [1/sqrt 2, sqrt 2), and
+// ln m = 2 atanh s = 2 s + 2 s s^2 L(s^2) with s = (m - 1)/(m + 1),
+// |s| <= 0.172, L a degree-6 minimax polynomial (coefficients from
+// minimax_coefs.py; relative error below 2e-18 with the coefficients rounded
+// to double, where the atanh series needs through s^21).  log_split takes x
+// apart; log_join adds the pieces once the caller has s (so that several
+// logarithms can share one reciprocal).  NaN for x <= 0.
+struct LogSplit {
+    double x, m, e;
+};
+
+__device__ __forceinline__ LogSplit log_split(double x) {
     double m = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1)
     int e = __builtin_amdgcn_frexp_exp(x);
     if (m < 0.70710678118654752440) {
         m *= 2.0;
         e -= 1;
     }
-    const double s = (m - 1.0) * rcp(m + 1.0);
+    return LogSplit{x, m, static_cast<double>(e)};
+}
+
+__device__ __forceinline__ double log_join(const LogSplit& ls, double s) {
+    constexpr double LN2_HI = 6.93147180369123816490e-01;
+    constexpr double LN2_LO = 1.90821492927058770002e-10;
     const double s2 = s * s;
-    double p = 1.0 / 21;
-    p = fma(p, s2, 1.0 / 19);
-    p = fma(p, s2, 1.0 / 17);
-    p = fma(p, s2, 1.0 / 15);
-    p = fma(p, s2, 1.0 / 13);
-    p = fma(p, s2, 1.0 / 11);
-    p = fma(p, s2, 1.0 / 9);
-    p = fma(p, s2, 1.0 / 7);
-    p = fma(p, s2, 1.0 / 5);
-    p = fma(p, s2, 1.0 / 3);
+    double p = 0.07397974873252054;
+    p = fma(p, s2, 0.07657025269735923);
+    p = fma(p, s2, 0.09091782163503512);
+    p = fma(p, s2, 0.11111099286578859);
+    p = fma(p, s2, 0.14285714371194005);
+    p = fma(p, s2, 0.19999999999707338);
+    p = fma(p, s2, 0.3333333333333367);
     const double lm = fma((2.0 * s) * s2, p, 2.0 * s);
-    const double de = static_cast<double>(e);
-    const double r = fma(de, LN2_HI, fma(de, LN2_LO, lm));
-    return x > 0.0 ? r : __builtin_nan("");
+    const double r = fma(ls.e, LN2_HI, fma(ls.e, LN2_LO, lm));
+    return ls.x > 0.0 ? r : __builtin_nan("");
+}
+
+__device__ __forceinline__ double log_fast(double x) {
+    const LogSplit ls = log_split(x);
+    return log_join(ls, (ls.m - 1.0) * rcp(ls.m + 1.0));
 }
 
 template <bool WANT_DIAG>
@@ -354,10 +365,17 @@ __device__ __forceinline__ void rhs_q(const QSpacetime& st, const RayConst& rc, 
     const double f = rf * ir * ir;
     const double Dm1 = (M * M) * (s * s) * irf;  // D - 1
     const double D = 1.0 + Dm1;
-    const double lf = log_fast(f);
-    const double fq = exp_fast(st.q * lf);        // f^q
-    const double DP = exp_fast(st.P * log_fast(D));  // D^P
-    const double iD = rcp(D);
+    // ln f, ln D and 1/D with one reciprocal: that of (m_f + 1)(m_D + 1) D,
+    // m_f and m_D the logarithms' mantissas
+    const LogSplit sf = log_split(f), sd = log_split(D);
+    const double af = sf.m + 1.0, ad = sd.m + 1.0;
+    const double afad = af * ad;
+    const double q3 = rcp(afad * D);
+    const double iD = afad * q3;
+    const double qD = D * q3;  // 1 / ((m_f + 1)(m_D + 1))
+    const double lf = log_join(sf, (sf.m - 1.0) * (ad * qD));
+    const double fq = exp_fast(st.q * lf);                                // f^q
+    const double DP = exp_fast(st.P * log_join(sd, (sd.m - 1.0) * (af * qD)));  // D^P
     const double ir2 = ir * ir;
     const double A = f * fq * DP;
     const double B = fq * DP * ir2;

@@ -16,6 +16,14 @@ largest error of the result over the range the kernel needs:
 Taylor's series needs one (staged) or two (full) more terms for the same
 accuracy.
 
+It also fits the polynomials of exp_fast and log_fast (the q-metric's
+powers f^q and D^(q(2+q))):
+    e^t = 1 + t + t^2 G(t), |t| <= (ln 2)/2: G degree 9, weight t^2 / e^t
+        (relative error of e^t); Taylor's series needs through t^13
+    ln m = 2 s + 2 s x L(x), x = s^2, s = (m - 1)/(m + 1) for m in
+        [1/sqrt 2, sqrt 2), L(x) = sum_k x^k / (2k + 3): L degree 6, weight x
+        (relative error of ln m); the atanh series needs through s^21
+
     python paper_2202_00086_amd/csrc/minimax_coefs.py
 """
 import mpmath as mp
@@ -78,6 +86,27 @@ def remez(f, w, b, n, grid=2000, iters=40):
     return c, worst
 
 
+def remez_on(f, w, a, n):
+    """remez on the symmetric interval [-a, a], returned as coefficients of
+    the polynomial in the original variable (low to high)."""
+    c, worst = remez(lambda y: f(y - a), lambda y: w(y - a), 2 * a, n)
+    # p(t) = sum_k c_k (t + a)^k, expanded in powers of t
+    out = [mp.mpf(0)] * (n + 1)
+    for k, ck in enumerate(c):
+        for j in range(k + 1):
+            out[j] += ck * mp.binomial(k, j) * a ** (k - j)
+    return out, worst
+
+
+def G(t):
+    # (e^t - e^0 - t) / t^2 from its series, accurate at and near t = 0
+    return mp.fsum(t ** k / mp.factorial(k + 2) for k in range(60))
+
+
+def L(x):
+    return mp.fsum(x ** k / (2 * k + 3) for k in range(80))
+
+
 def fit_all():
     out = {}
     for name, fn, w, b, n, lead in FITS:
@@ -89,6 +118,13 @@ def fit_all():
             c, worst = remez(lambda x: (f(x) - lead) / x, lambda x: x * w(x), b, n - 1)
             c = [lead] + c
         out[name] = ([float(v) for v in c], float(worst))
+    # exp: the weight t^2 / e^t vanishes at t = 0, inside the interval
+    half_ln2 = mp.log(2) / 2
+    c, worst = remez_on(G, lambda t: t * t / mp.exp(t) + mp.mpf("1e-40"), half_ln2, 9)
+    out["exp_g"] = ([float(v) for v in c], float(worst))
+    smax = (mp.sqrt(2) - 1) / (mp.sqrt(2) + 1)
+    c, worst = remez(L, lambda x: x, smax ** 2, 6)
+    out["log_l"] = ([float(v) for v in c], float(worst))
     return out
 
 

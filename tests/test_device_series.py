@@ -1,6 +1,7 @@
-"""The sin/cos polynomials of the trace kernel's source (sincos_shift, the
-stage angles; sincos_theta, the full polar angle) against the functions they
-approximate, in 50-digit arithmetic: each polynomial, with its coefficients
+"""The polynomials of the trace kernel's source (sincos_shift, the stage
+angles; sincos_theta, the full polar angle; exp_fast and log_join, the
+q-metric's powers) against the functions they approximate, in 50-digit
+arithmetic: each polynomial, with its coefficients
 as the doubles the kernel holds, stays within the error bound its comment
 states over its range.  A wrong sign, a dropped or mistyped coefficient, or
 a polynomial for a different function fails these bounds."""
@@ -18,7 +19,7 @@ mp.mp.dps = 50
 
 def _function_body(name):
     text = open(SRC).read()
-    i = text.index(f"void {name}(")
+    i = re.search(rf"__device__ __forceinline__ \w+ {name}\(", text).start()
     return text[i:text.index("\n}\n", i)]
 
 
@@ -85,3 +86,29 @@ def test_polar_angle_fold_and_signs(theta):
         c = _poly(ps, x) * x * u - u
         assert abs(s - mp.sin(th)) < 1e-15
         assert abs(c - mp.cos(th)) < 1e-15
+
+
+def test_exp_polynomial():
+    """exp_fast: e^t = 1 + t + t^2 G(t) on |t| <= (ln 2)/2, relative error."""
+    body = _function_body("exp_fast")
+    g = _horner(body, "p")
+    assert len(g) == 12  # ten coefficients of G, then the two unit steps
+    assert g[-2:] == [1, 1]
+    T = mp.log(2) / 2
+    worst = max(abs(_poly(g, t) / mp.exp(t) - 1) for t in [T * k / 1500 for k in range(-1500, 1501)])
+    assert worst < 1e-17, worst
+
+
+def test_log_polynomial():
+    """log_join: ln m = 2 s + 2 s s^2 L(s^2) for m in [1/sqrt 2, sqrt 2),
+    s = (m - 1)/(m + 1), relative error."""
+    body = _function_body("log_join")
+    lc = _horner(body, "p")
+    assert len(lc) == 7
+    smax = (mp.sqrt(2) - 1) / (mp.sqrt(2) + 1)
+    worst = mp.mpf(0)
+    for k in range(1, 1501):
+        s = smax * k / 1500
+        lm = 2 * s + 2 * s * s * s * _poly(lc, s * s)
+        worst = max(worst, abs(lm / mp.log((1 + s) / (1 - s)) - 1))
+    assert worst < 2e-18, worst
