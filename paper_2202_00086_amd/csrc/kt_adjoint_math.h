@@ -7,6 +7,7 @@
 #pragma once
 
 #include "kt_dual.h"
+#include "kt_sincos.h"
 
 namespace kt {
 namespace adj {
@@ -67,10 +68,11 @@ __host__ __device__ inline void grad_H(double M, const T& r, const T& th, const 
 }
 
 // Hamilton's equations from the gradient: d/dlambda (r, th, phi, p_r, p_th).
-// Returns sin and cos of theta, which the step VJP reuses.
+// Returns sin and cos of theta (the trace kernel's own sincos_theta), which
+// the step VJP reuses.
 __host__ __device__ inline void field(double M, double a, double E, double L, const double z[5], double f[5],
                                       double* sv, double* cv) {
-    dsincos(z[1], sv, cv);
+    sincos_theta(z[1], sv, cv);
     double g[7];
     grad_H<double>(M, z[0], z[1], z[3], z[4], L, E, a, *sv, *cv, g);
     f[0] = g[2];
@@ -147,7 +149,7 @@ __host__ __device__ inline void dp_step_vjp(double M, double a, double E, double
         if (j < 5)
             field(M, a, E, L, Y[j], K[j], &S[j], &C[j]);
         else
-            dsincos(Y[j][1], &S[j], &C[j]);
+            sincos_theta(Y[j][1], &S[j], &C[j]);
     }
     double kb[6][5];
 #pragma unroll

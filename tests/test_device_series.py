@@ -12,15 +12,20 @@ import mpmath as mp
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SRC = os.path.join(ROOT, "paper_2202_00086_amd", "csrc", "kt_device.h")
+CSRC = os.path.join(ROOT, "paper_2202_00086_amd", "csrc")
+SOURCES = [os.path.join(CSRC, f) for f in ("kt_device.h", "kt_sincos.h")]
 
 mp.mp.dps = 50
 
 
 def _function_body(name):
-    text = open(SRC).read()
-    i = re.search(rf"__device__ __forceinline__ \w+ {name}\(", text).start()
-    return text[i:text.index("\n}\n", i)]
+    for path in SOURCES:
+        text = open(path).read()
+        m = re.search(rf"__device__ (?:__forceinline__|inline __attribute__\(\(always_inline\)\)) \w+ {name}\(",
+                      text)
+        if m:
+            return text[m.start():text.index("\n}\n", m.start())]
+    raise AssertionError(f"{name} not found in {SOURCES}")
 
 
 def _horner(body, var):
