@@ -7,7 +7,7 @@
 #pragma once
 
 #include "kt_dual.h"
-#include "kt_sincos.h"
+#include "kt_elem.h"
 
 namespace kt {
 namespace adj {
@@ -45,7 +45,7 @@ __host__ __device__ inline void grad_H(double M, const T& r, const T& th, const 
     const T Del = r2 - 2.0 * M * r + a2;
     const T rho2 = r2 + a2;
     const T SD = Sig * Del;
-    const T R = 1.0 / (SD * s);
+    const T R = recip(SD * s);
     const T iS = Del * s * R, iD = Sig * s * R, is = SD * R;
     const T Lis = L * is;
     const T Tt = Lis - a * E * s;

@@ -8,22 +8,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "kt_sincos.h"
+#include "kt_elem.h"
 
 namespace kt {
 
 // ---------------------------------------------------------------------------
 // Elementary functions
 // ---------------------------------------------------------------------------
-
-// 1/x from the hardware reciprocal estimate y (relative error e) refined by
-// one third-order step y (1 + e + e^2), which cubes the error (below 1e-21
-// from the estimate's ~5e-8): the result is within about an ulp.
-__device__ __forceinline__ double rcp(double x) {
-    const double y = __builtin_amdgcn_rcp(x);
-    const double e = fma(-x, y, 1.0);
-    return fma(y, fma(e, e, e), y);
-}
 
 // sin and cos of x for |x| < ~1e5.  Cody-Waite reduction by pi/2 with a
 // two-part constant, then the Taylor series of sin through r^15 and of cos

@@ -9,6 +9,8 @@
 
 #include <cmath>
 
+#include "kt_elem.h"
+
 namespace kt {
 
 template <int N>
@@ -62,7 +64,7 @@ __host__ __device__ inline Dual<N> operator*(const Dual<N>& a, const Dual<N>& b)
 }
 template <int N>
 __host__ __device__ inline Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) {
-    const double ib = 1.0 / b.v;  // one division for the value and all tangents
+    const double ib = rcp(b.v);  // one reciprocal for the value and all tangents
     const double q = a.v * ib;
     Dual<N> r(q);
     for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - q * b.d[i]) * ib;
@@ -85,9 +87,16 @@ __host__ __device__ inline Dual<N> operator*(const Dual<N>& a, double b) {
 template <int N>
 __host__ __device__ inline Dual<N> operator*(double a, const Dual<N>& b) { return b * a; }
 template <int N>
-__host__ __device__ inline Dual<N> operator/(const Dual<N>& a, double b) { return a * (1.0 / b); }
+__host__ __device__ inline Dual<N> operator/(const Dual<N>& a, double b) { return a * rcp(b); }
 template <int N>
 __host__ __device__ inline Dual<N> operator/(double a, const Dual<N>& b) { return Dual<N>(a) / b; }
+
+// 1/x for plain and dual numbers
+__host__ __device__ inline double recip(double x) { return rcp(x); }
+template <int N>
+__host__ __device__ inline Dual<N> recip(const Dual<N>& x) {
+    return 1.0 / x;
+}
 
 template <int N>
 __host__ __device__ inline Dual<N> dsqrt(const Dual<N>& a) {

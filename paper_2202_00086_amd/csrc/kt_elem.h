@@ -1,6 +1,8 @@
-// kt_sincos.h -- sin and cos of the polar angle, shared by the trace kernel's
-// RHS and the adjoint's step VJP.  Plain arithmetic (no target builtins), so
-// it compiles on the host as well as on the device.
+// kt_elem.h -- the elementary functions the trace kernel shares with the
+// adjoint: the reciprocal and sin/cos of the polar angle.  sincos_theta is
+// plain arithmetic and compiles on the host as well; rcp has a device form
+// (the hardware estimate, refined) and a host form (a division), chosen by
+// the side that calls it.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,6 +10,16 @@
 #include <cmath>
 
 namespace kt {
+
+// 1/x from the hardware reciprocal estimate y (relative error e) refined by
+// one third-order step y (1 + e + e^2), which cubes the error (below 1e-21
+// from the estimate's ~5e-8): the result is within about an ulp.
+__device__ __forceinline__ double rcp(double x) {
+    const double y = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, y, 1.0);
+    return fma(y, fma(e, e, e), y);
+}
+__host__ inline double rcp(double x) { return 1.0 / x; }
 
 // sin and cos of the polar angle theta.  theta is folded to t in [-pi, pi]
 // by t = theta - 2 pi rint(theta / 2 pi) (t = theta exactly on [0, pi), the
@@ -19,7 +31,8 @@ namespace kt {
 // coefficients rounded to double the absolute error stays below 1.4e-17 for
 // cos u and 4.1e-17 for sin u, under a third of an ulp of 1; Taylor's series
 // needs two more terms each for the same.  No quadrant selects.
-__host__ __device__ inline __attribute__((always_inline)) void sincos_theta(double th, double* s_out, double* c_out) {
+__host__ __device__ inline __attribute__((always_inline)) void sincos_theta(double th, double* s_out,
+                                                                           double* c_out) {
     constexpr double INV_TWO_PI = 0.15915494309189533577;
     constexpr double TWO_PI_HI = 6.2831853071795862320e+00;  // 2 pi rounded to double
     constexpr double TWO_PI_LO = 2.4492935982947064e-16;     // 2 pi - TWO_PI_HI

@@ -13,7 +13,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2202_00086_amd", "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("kt_device.h", "kt_sincos.h")]
+SOURCES = [os.path.join(CSRC, f) for f in ("kt_device.h", "kt_elem.h")]
 
 mp.mp.dps = 50
 
