@@ -1,6 +1,7 @@
 // kt_device.h -- device math for the gfx950 Kerr ray tracer: fast FP64
-// reciprocal and sincos, the Hamiltonian right-hand side in Carter's
-// separated form, and the Dormand-Prince 5(4) / RK4 steppers.
+// elementary functions (with the reciprocal and sin/cos of theta from
+// kt_elem.h), the Hamiltonian right-hand side in Carter's separated form and
+// that of the q-metric, and the Runge-Kutta and Bulirsch-Stoer steppers.
 //
 // Everything here runs one ray per lane in VGPRs; nothing touches memory.
 #pragma once
