@@ -117,3 +117,24 @@ def test_log_polynomial():
         lm = 2 * s + 2 * s * s * s * _poly(lc, s * s)
         worst = max(worst, abs(lm / mp.log((1 + s) / (1 - s)) - 1))
     assert worst < 2e-18, worst
+
+
+def test_coefficients_are_the_generators_output():
+    """Every coefficient list in the kernel source is exactly what
+    csrc/minimax_coefs.py prints (its Remez fits in 50-digit arithmetic,
+    rounded to double)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("minimax_coefs", os.path.join(CSRC, "minimax_coefs.py"))
+    mc = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mc)
+    fits = mc.fit_all()
+
+    def low_first(name, var):
+        return [float(v) for v in _horner(_function_body(name), var)][::-1]
+
+    assert low_first("sincos_shift", "ps") == fits["shift_sin"][0]
+    assert low_first("sincos_shift", "pc") == fits["shift_cos"][0]
+    assert low_first("sincos_theta", "pc") == [-v for v in fits["theta_cos"][0]]
+    assert low_first("sincos_theta", "ps") == fits["theta_sin"][0]
+    assert low_first("exp_fast", "p")[2:] == fits["exp_g"][0]   # after the two unit steps
+    assert low_first("log_join", "p") == fits["log_l"][0]
