@@ -190,21 +190,24 @@ def test_full_size_adjoint_sampled(torch_mod):
 
 
 def _random_disk(seed):
+    """Seeds 31-34: prograde spin, Keplerian or constant-l0 rotation; 35 and 36:
+    retrograde spin (the disk counter-rotates with the hole), Keplerian."""
     rng = np.random.default_rng(seed)
-    a = float(rng.uniform(0.1, 0.95))
+    retro = seed >= 35
+    a = float(rng.uniform(-0.95, -0.1)) if retro else float(rng.uniform(0.1, 0.95))
     p = W.differentiable_disk(a=a, incl_deg=float(rng.uniform(20.0, 80.0)),
                               r_in=W.isco(a) * float(rng.uniform(1.0, 1.3)), n=24)
     p["r_out"] = float(rng.uniform(18.0, 30.0))
-    if rng.uniform() < 0.5:
+    if not retro and rng.uniform() < 0.5:
         p.update(rotation=1, l0=float(rng.uniform(2.2, 3.2)) if a < 0.8 else float(rng.uniform(1.8, 2.3)))
     return p
 
 
-@pytest.mark.parametrize("seed", [31, 32, 33, 34])
+@pytest.mark.parametrize("seed", [31, 32, 33, 34, 35, 36])
 def test_random_disk_adjoint_matches_finite_differences(torch_mod, seed):
-    """Seeded disks (spin, inclination, inner and outer radius, Keplerian or
-    constant-l0 rotation) at 24x24: per-pixel gradients against central
-    differences of the oracle."""
+    """Seeded disks (spin of either sign, inclination, inner and outer
+    radius, Keplerian or constant-l0 rotation) at 24x24: per-pixel gradients
+    against central differences of the oracle."""
     from paper_2202_00086_amd import autograd as AG
     params = _random_disk(seed)
     _announce("adjoint random disk", seed, {k: params[k] for k in ("a", "incl", "r_in", "r_out")},
