@@ -237,6 +237,7 @@ def run_adjoint_form(K, torch, W, steps):
     mask = (out["fate"] == K.DISK) & (out["n_cross"] <= 1)
     cot = (2.0 * (out["intensity"] - T) * mask).contiguous()
     grads = [torch.empty(r.n, dtype=torch.float64, device="cuda:0") for _ in range(3)]
+    grad_sum = torch.empty(3, dtype=torch.float64, device="cuda:0")
     stats = torch.zeros(4, dtype=torch.int64, device="cuda:0")
     nbytes = K.kt_adjoint_workspace_bytes(r.cam, r.integ)
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
@@ -246,7 +247,7 @@ def run_adjoint_form(K, torch, W, steps):
         rc = K.kt_adjoint(r.cam, r.st, r.disk, r.integ, out["fate"].data_ptr(), out["r_hit"].data_ptr(),
                           cot.data_ptr(), grads[0].data_ptr(), grads[1].data_ptr(), grads[2].data_ptr(),
                           stats.data_ptr(), ws.data_ptr(), nbytes, stream,
-                          out["n_steps"].data_ptr() if sorted_list else None)
+                          out["n_steps"].data_ptr() if sorted_list else None, grad_sum.data_ptr())
         if rc != K.KT_OK:
             raise K.KtError(rc, K.kt_last_error())
     adjoint(False)
@@ -259,8 +260,7 @@ def run_adjoint_form(K, torch, W, steps):
             "forward_ms": 1e3 * t_fwd, "adjoint_ms": 1e3 * t_adj, "adjoint_over_forward": t_adj / t_fwd,
             "adjoint_ms_without_step_counts": 1e3 * t_unsorted,
             "loss": float((((out["intensity"] - T) ** 2) * mask).sum().item()),
-            "grad": {"a": float(grads[0].sum().item()), "incl": float(grads[1].sum().item()),
-                     "r_in": float(grads[2].sum().item())},
+            "grad": dict(zip(("a", "incl", "r_in"), grad_sum.cpu().tolist())),
             "rays_differentiated": st[0], "failed": st[1], "overflow": st[2], "mismatch": st[3],
             "differentiated_rays_per_s": st[0] / t_adj}
 

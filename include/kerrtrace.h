@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define KT_VERSION_NUMBER 150
+#define KT_VERSION_NUMBER 200
 
 /* return codes */
 #define KT_OK 0
@@ -143,6 +143,9 @@ typedef struct kt_integrator {
     double h_budget;        /* MIXED: re-run in FP64 when max |H|_rel > h_budget */
     double r_switch;        /* MIXED: FP32 RHS part only where r >= r_switch */
     int64_t max_steps;      /* accepted-step budget per ray, >= 1 */
+    int32_t checkpoint_every; /* kt_adjoint: a checkpoint every this many accepted
+                                 steps, a power of two in [8, 1024]; 0 selects 64.
+                                 Renders ignore it (but reject other values) */
 } kt_integrator;
 
 /* Launch shape.  Pass NULL for the defaults: persistent, block 256,
@@ -281,26 +284,32 @@ int kt_autotune_batch(int32_t n_images, const kt_image *images, const kt_integra
    integration with its accepted step sizes frozen.  For each pixel with
    fate KT_FATE_DISK and cot_intensity != 0 it writes
    cot_intensity * dI/d(a, incl, r_in) to grad_a, grad_incl, grad_r_in
-   (device, nx*ny doubles each, any may be NULL; 0 elsewhere); a loss's
-   gradient is their sum with cot_intensity = dLoss/dI.
+   (device, nx*ny doubles each, any may be NULL; 0 elsewhere).
+   grad_sum (device, 3 doubles, may be NULL) receives the sums of the three
+   maps over the image: with cot_intensity = dLoss/dI that is the loss's
+   gradient in (a, incl, r_in).  The sums are taken in a fixed order (a
+   block-then-grid tree over pixel ids), so they are bit-identical from run
+   to run whatever lanes ran the rays.
    Inputs: the same camera, spacetime, disk and integrator as the forward
    kt_render (method KT_DP45, KT_FP64, disk enabled), and that render's fate
    array, its r_hit array (optional, for a bit-identity check) and its
    n_steps array (optional: the differentiated rays are run longest first
    and neighbouring lanes get rays of similar length; it changes only the
    time).  Each ray is re-integrated with the forward's own arithmetic,
-   checkpointed every 64 accepted steps, and swept backward segment by
-   segment.
+   checkpointed every integ->checkpoint_every accepted steps (64 when 0), and
+   swept backward segment by segment.
    stats (device, 4 uint64, may be NULL): rays differentiated, rays that
-   failed, rays beyond the checkpoint capacity (256 x 64 steps), rays whose
-   re-integration did not reproduce r_hit; the last three get zero gradient.
+   failed, rays beyond the checkpoint capacity (256 checkpoints, i.e.
+   256 * checkpoint_every accepted steps), rays whose re-integration did not
+   reproduce r_hit; the last three get zero gradient and drop out of
+   grad_sum, so a caller that needs the whole gradient checks them.
    workspace: kt_adjoint_workspace_bytes() bytes, 256-byte aligned.
    Returns KT_OK, KT_EINVAL, KT_ENOMEM or KT_EDEVICE. */
 int kt_adjoint(const kt_camera *camera, const kt_spacetime *spacetime, const kt_disk *disk,
                const kt_integrator *integ, const uint8_t *fate, const double *r_hit,
                const int32_t *n_steps, const double *cot_intensity, double *grad_a,
-               double *grad_incl, double *grad_r_in, uint64_t *stats, void *workspace,
-               size_t workspace_bytes, void *hip_stream);
+               double *grad_incl, double *grad_r_in, double *grad_sum, uint64_t *stats,
+               void *workspace, size_t workspace_bytes, void *hip_stream);
 
 /* Workspace size of kt_adjoint for this camera and integrator (0 on bad input). */
 size_t kt_adjoint_workspace_bytes(const kt_camera *camera, const kt_integrator *integ);

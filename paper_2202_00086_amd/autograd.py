@@ -2,9 +2,12 @@
 
 DiskImage.forward renders the observed intensity with kt_render (DP45,
 FP64, disk on); backward calls kt_adjoint with the incoming gradient as the
-per-pixel cotangent and returns the summed gradients of the three scalar
-parameters.  Both directions run in the library's HIP kernels; this module
-only marshals tensors.
+per-pixel cotangent and returns the three image sums the library computes
+(grad_sum).  Both directions, the reduction included, run in the library's
+HIP kernels; this module only marshals tensors.  A backward pass in which
+any differentiated ray failed, overflowed the checkpoint store or did not
+reproduce the forward's hit radius raises KtError instead of returning a
+gradient with those rays missing.
 """
 import ctypes as C
 
@@ -38,19 +41,29 @@ class DiskImage(torch.autograd.Function):
         n = r.n
         cot = torch.zeros(n, dtype=torch.float64, device=dev) if g_int is None else \
             g_int.to(dtype=torch.float64).contiguous()
-        grads = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3)]
+        grad_sum = torch.empty(3, dtype=torch.float64, device=dev)
         stats = torch.zeros(4, dtype=torch.int64, device=dev)
         nbytes = K.kt_adjoint_workspace_bytes(r.cam, r.integ)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         stream = torch.cuda.current_stream(dev)
         rc = K.kt_adjoint(r.cam, r.st, r.disk, r.integ, r.out["fate"].data_ptr(), r.out["r_hit"].data_ptr(),
-                          cot.data_ptr(), grads[0].data_ptr(), grads[1].data_ptr(), grads[2].data_ptr(),
-                          stats.data_ptr(), ws.data_ptr(), nbytes, C.c_void_p(stream.cuda_stream),
-                          r.out["n_steps"].data_ptr())
+                          cot.data_ptr(), None, None, None, stats.data_ptr(), ws.data_ptr(), nbytes,
+                          C.c_void_p(stream.cuda_stream), r.out["n_steps"].data_ptr(), grad_sum.data_ptr())
         if rc != K.KT_OK:
             raise K.KtError(rc, K.kt_last_error())
+        check_adjoint_stats(stats)
         ctx.renderer.adjoint_stats = stats
-        return grads[0].sum(), grads[1].sum(), grads[2].sum(), None, None
+        return grad_sum[0], grad_sum[1], grad_sum[2], None, None
+
+
+def check_adjoint_stats(stats):
+    """Raise KtError when kt_adjoint left any differentiated ray out
+    (stats = [differentiated, failed, overflow, mismatch]; synchronises)."""
+    ok, failed, overflow, mismatch = (int(v) for v in stats.cpu().tolist())
+    if failed or overflow or mismatch:
+        raise K.KtError(K.KT_EINVAL, f"adjoint left rays out of the gradient: {failed} failed, {overflow} beyond "
+                                     f"the checkpoint capacity, {mismatch} not reproducing the forward hit "
+                                     f"radius (of {ok + failed + overflow + mismatch})")
 
 
 def disk_image(a, incl, r_in, device="cuda:0", **params):
@@ -61,14 +74,15 @@ def disk_image(a, incl, r_in, device="cuda:0", **params):
 
 def adjoint_maps(device="cuda:0", cot=None, **params):
     """Per-pixel gradients dI/d(a, incl, r_in) (times cot, default 1) of one
-    render, with the adjoint's statistics: (render outputs, (ga, gi, gr),
-    stats[ok, failed, overflow, mismatch])."""
+    render, with the adjoint's statistics and image sums: (render outputs,
+    (ga, gi, gr), stats[ok, failed, overflow, mismatch], grad_sum[3])."""
     r = K.Renderer(device=device, want=_WANT, stats=False, **params)
     out = r.render()
     n = r.n
     dev = torch.device(device)
     cot = torch.ones(n, dtype=torch.float64, device=dev) if cot is None else cot
     grads = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3)]
+    grad_sum = torch.empty(3, dtype=torch.float64, device=dev)
     stats = torch.zeros(4, dtype=torch.int64, device=dev)
     nbytes = K.kt_adjoint_workspace_bytes(r.cam, r.integ)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -76,7 +90,7 @@ def adjoint_maps(device="cuda:0", cot=None, **params):
     rc = K.kt_adjoint(r.cam, r.st, r.disk, r.integ, out["fate"].data_ptr(), out["r_hit"].data_ptr(),
                       cot.data_ptr(), grads[0].data_ptr(), grads[1].data_ptr(), grads[2].data_ptr(),
                       stats.data_ptr(), ws.data_ptr(), nbytes, C.c_void_p(stream.cuda_stream),
-                      out["n_steps"].data_ptr())
+                      out["n_steps"].data_ptr(), grad_sum.data_ptr())
     if rc != K.KT_OK:
         raise K.KtError(rc, K.kt_last_error())
-    return out, tuple(grads), stats
+    return out, tuple(grads), stats, grad_sum

@@ -6,16 +6,20 @@
 // the differentiated rays sorted by forward step count):
 //   1. re-integrate from the camera with the trace kernel's own stepper and
 //      controller (bit-identical steps), keeping a checkpoint (state, trial
-//      step) every 64 accepted steps, up to the located disk crossing;
+//      step) every 2^ck_shift accepted steps (64 by default), up to the
+//      located disk crossing;
 //   2. seed the cotangent of the crossing state from the intensity's
 //      derivatives, with the crossing-time correction that keeps theta on
 //      the equatorial plane;
 //   3. run the vector-Jacobian products of the Dormand-Prince steps backward
 //      with the accepted step sizes frozen: the located partial step first,
-//      then each 64-step segment, recomputed forward from its checkpoint;
+//      then each segment between checkpoints, recomputed forward from its
+//      checkpoint;
 //   4. chain the cotangents of the initial state and of (E, L) through the
 //      camera's dependence on (a, inclination).
-// The results are the per-pixel products cot_I * dI/d(a, incl, r_in).
+// The results are the per-pixel products cot_I * dI/d(a, incl, r_in) and,
+// on request, their three sums over the image (a fixed-order block-then-grid
+// reduction, so the sums do not depend on which lane ran which ray).
 #include <hip/hip_runtime.h>
 
 #include "kt_adjoint_math.h"
@@ -28,7 +32,7 @@ namespace kt {
 
 enum : int { ADJ_OK = 0, ADJ_FAIL = 1, ADJ_OVERFLOW = 2, ADJ_MISMATCH = 3 };
 
-// Checkpoint c (c-th multiple of 64 accepted steps) and segment slot j of a
+// Checkpoint c (after c * 2^ck_shift accepted steps) and segment slot j of a
 // lane: [index][field][lane], fields 0..4 the state, 5 the step size.
 __device__ __forceinline__ double* slot(double* base, int idx, int lane, int n_lanes) {
     return base + static_cast<size_t>(idx) * 6u * static_cast<size_t>(n_lanes) + lane;
@@ -62,12 +66,11 @@ __device__ __forceinline__ int try_step(const Spacetime& st, const RayConst& rc,
     const double msq = error_msq(er, sc);
     if (isnan(msq)) return -1;
     if (msq > 1.0) {
-        *h *= static_cast<double>(fmaxf(0.2f, step_factor<KT_DP45>(msq)));
+        *h *= reject_factor<KT_DP45>(msq);
         *rejected = true;
         return 0;
     }
-    double fac = 5.0;
-    if (msq >= 1e-20) fac = static_cast<double>(fminf(5.0f, fmaxf(0.2f, step_factor<KT_DP45>(msq))));
+    double fac = accept_factor<KT_DP45>(msq);
     if (*rejected) fac = fmin(fac, 1.0);
     *h_next = *h * fac;
     return 1;
@@ -81,6 +84,7 @@ __device__ int adjoint_ray(const AdjParams& P, const Spacetime& st, int lane, in
     double y[5], E, L;
     camera_state(im, ray, y, &E, &L);
     const RayConst rc = make_ray_const(st, E, L);
+    const int ck_mask = (1 << P.ck_shift) - 1;
     double k1[5];
     Diag dg;
     rhs<true, false>(st, rc, y, k1, &dg);
@@ -150,9 +154,9 @@ __device__ int adjoint_ray(const AdjParams& P, const Spacetime& st, int lane, in
         h = hn;
         rej = false;
         ++n;
-        if ((n & 63) == 0) {
-            if ((n >> 6) >= P.max_ckpt) return ADJ_OVERFLOW;
-            put6(slot(P.ckpt, n >> 6, lane, P.n_lanes), P.n_lanes, y, h);
+        if ((n & ck_mask) == 0) {
+            if ((n >> P.ck_shift) >= P.max_ckpt) return ADJ_OVERFLOW;
+            put6(slot(P.ckpt, n >> P.ck_shift, lane, P.n_lanes), P.n_lanes, y, h);
         }
     }
     if (!hit) return ADJ_FAIL;
@@ -168,8 +172,8 @@ __device__ int adjoint_ray(const AdjParams& P, const Spacetime& st, int lane, in
 
     // ---- 3. reverse sweep with frozen steps ------------------------------
     adj::dp_step_vjp(im.M, im.a, E, L, y, hstar, zb, &pb);
-    for (int s = (n - 1) >> 6; n > 0 && s >= 0; --s) {
-        const int first = s << 6, last = min(n, first + 64);
+    for (int s = (n - 1) >> P.ck_shift; n > 0 && s >= 0; --s) {
+        const int first = s << P.ck_shift, last = min(n, first + ck_mask + 1);
         double ys[5], hs;
         get6(slot(P.ckpt, s, lane, P.n_lanes), P.n_lanes, ys, &hs);
         double kk[5];
@@ -181,7 +185,7 @@ __device__ int adjoint_ray(const AdjParams& P, const Spacetime& st, int lane, in
         for (int j = first; j < last;) {
             // the recomputation repeats the forward's attempts exactly; the
             // bound only guarantees that the loop ends
-            if (++attempts > 64 * 64) return ADJ_FAIL;
+            if (++attempts > 64 * (ck_mask + 1)) return ADJ_FAIL;
             double yn[5], kn[5], hn = 0.0;
             Diag dn;
             const int ok = try_step(st, rc, P, ys, kk, ss, cc, &hs, &rj, yn, kn, &dn, &hn);
@@ -284,6 +288,57 @@ struct StepKey {
     }
 };
 
+// ---- the image sums of the three gradient maps ---------------------------
+// A fixed grid of ADJ_RED_BLOCKS blocks: thread t of block b adds pixels
+// t + 256 b, t + 256 (b + ADJ_RED_BLOCKS), ... in that order, the block adds
+// its 256 partial sums by a fixed tree in LDS, and one block then adds the
+// ADJ_RED_BLOCKS block sums by the same tree.  Every sum is taken in one
+// order whatever the device or the lanes that ran the rays.
+constexpr int RED_THREADS = 256;
+
+__device__ __forceinline__ void tree_sum3(double (*v)[RED_THREADS], int t) {
+#pragma unroll
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        __syncthreads();
+        if (t < w) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[c][t] += v[c][t + w];
+        }
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(RED_THREADS) grad_block_sum_kernel(const double* __restrict__ ga,
+                                                                     const double* __restrict__ gi,
+                                                                     const double* __restrict__ gr, int64_t n,
+                                                                     double* __restrict__ partials) {
+    __shared__ double v[3][RED_THREADS];
+    const int t = threadIdx.x;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * RED_THREADS + t; k < n;
+         k += static_cast<int64_t>(ADJ_RED_BLOCKS) * RED_THREADS) {
+        s0 += ga[k];
+        s1 += gi[k];
+        s2 += gr[k];
+    }
+    v[0][t] = s0;
+    v[1][t] = s1;
+    v[2][t] = s2;
+    tree_sum3(v, t);
+    if (t < 3) partials[t * ADJ_RED_BLOCKS + blockIdx.x] = v[t][0];
+}
+
+__global__ void __launch_bounds__(RED_THREADS) grad_final_sum_kernel(const double* __restrict__ partials,
+                                                                     double* __restrict__ out) {
+    static_assert(ADJ_RED_BLOCKS == RED_THREADS, "one partial per thread");
+    __shared__ double v[3][RED_THREADS];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c][t] = partials[c * ADJ_RED_BLOCKS + t];
+    tree_sum3(v, t);
+    if (t < 3) out[t] = v[t][0];
+}
+
 int launch_adjoint(const AdjParams& p, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(adjoint_init_kernel, dim3(1), dim3(256), 0, s, p.ticket, p.stats, p.hist);
@@ -292,6 +347,13 @@ int launch_adjoint(const AdjParams& p, void* stream) {
     if (launch_sort(b, StepKey{p.fate, p.cot, p.n_steps, p.grad_a, p.grad_incl, p.grad_rin}, s)) return -1;
     const int grid = (p.n_lanes + ADJ_BLOCK - 1) / ADJ_BLOCK;
     hipLaunchKernelGGL(adjoint_kernel, dim3(grid), dim3(ADJ_BLOCK), 0, s, p);
+    if (hipGetLastError() != hipSuccess) return -1;
+    if (p.grad_sum) {
+        hipLaunchKernelGGL(grad_block_sum_kernel, dim3(ADJ_RED_BLOCKS), dim3(RED_THREADS), 0, s, p.grad_a,
+                           p.grad_incl, p.grad_rin, static_cast<int64_t>(p.n_rays), p.partials);
+        if (hipGetLastError() != hipSuccess) return -1;
+        hipLaunchKernelGGL(grad_final_sum_kernel, dim3(1), dim3(RED_THREADS), 0, s, p.partials, p.grad_sum);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

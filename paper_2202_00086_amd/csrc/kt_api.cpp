@@ -186,6 +186,9 @@ int validate_integ(const kt_integrator* integ) {
     if (!(integ->capture_buffer >= 0.0)) return fail(KT_EINVAL, "capture_buffer must be >= 0");
     if (integ->max_steps < 1 || integ->max_steps > 100000000)
         return fail(KT_EINVAL, "max_steps must lie in [1, 1e8]");
+    if (kt::adj_ck_shift(integ->checkpoint_every) < 0)
+        return fail(KT_EINVAL, "checkpoint_every must be 0 or a power of two in [8, 1024] (got %d)",
+                    integ->checkpoint_every);
     return KT_OK;
 }
 
@@ -504,14 +507,16 @@ size_t kt_adjoint_workspace_bytes(const kt_camera* camera, const kt_integrator* 
     if (!camera || !integ || camera->nx < 1 || camera->ny < 1) return 0;
     const size_t n = static_cast<size_t>(camera->nx) * static_cast<size_t>(camera->ny);
     if (n >= (size_t{1} << 31)) return 0;  // ray ids are int32
-    return kt::adj_layout(n, integ->max_steps).total;
+    const int ck_shift = kt::adj_ck_shift(integ->checkpoint_every);
+    if (ck_shift < 0) return 0;
+    return kt::adj_layout(n, integ->max_steps, ck_shift).total;
 }
 
 int kt_adjoint(const kt_camera* camera, const kt_spacetime* spacetime, const kt_disk* disk,
                const kt_integrator* integ, const uint8_t* fate, const double* r_hit, const int32_t* n_steps,
                const double* cot_intensity,
-               double* grad_a, double* grad_incl, double* grad_r_in, uint64_t* stats, void* workspace,
-               size_t workspace_bytes, void* hip_stream) {
+               double* grad_a, double* grad_incl, double* grad_r_in, double* grad_sum, uint64_t* stats,
+               void* workspace, size_t workspace_bytes, void* hip_stream) {
     g_err[0] = 0;
     int rc = validate_common(camera, spacetime);
     if (rc) return rc;
@@ -523,11 +528,15 @@ int kt_adjoint(const kt_camera* camera, const kt_spacetime* spacetime, const kt_
     if (!(spacetime->M > 0.0)) return fail(KT_EINVAL, "the adjoint needs M > 0");
     if (spacetime->metric != KT_METRIC_KERR) return fail(KT_EINVAL, "the adjoint differentiates Kerr images");
     if (!fate || !cot_intensity) return fail(KT_EINVAL, "fate and cot_intensity must not be NULL");
+    const int ck_shift = kt::adj_ck_shift(integ->checkpoint_every);
+    if (ck_shift < 0)
+        return fail(KT_EINVAL, "checkpoint_every must be 0 or a power of two in [8, 1024] (got %d)",
+                    integ->checkpoint_every);
     kt::Image im;
     if ((rc = make_image(camera, spacetime, disk, nullptr, integ, false, im))) return rc;
     im.first = 0;
     const size_t n = static_cast<size_t>(camera->nx) * static_cast<size_t>(camera->ny);
-    const kt::AdjLayout w = kt::adj_layout(n, integ->max_steps);
+    const kt::AdjLayout w = kt::adj_layout(n, integ->max_steps, ck_shift);
     if (!workspace) return fail(KT_EINVAL, "workspace must not be NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
         return fail(KT_EINVAL, "workspace must be 256-byte aligned");
@@ -548,10 +557,16 @@ int kt_adjoint(const kt_camera* camera, const kt_spacetime* spacetime, const kt_
     p.fate = fate;
     p.r_hit = r_hit;
     p.cot = cot_intensity;
-    p.grad_a = grad_a;
-    p.grad_incl = grad_incl;
-    p.grad_rin = grad_r_in;
     char* ws = static_cast<char*>(workspace);
+    // per-pixel gradients go to the caller's arrays, else to the workspace
+    // (the image sums read them)
+    double* wg = reinterpret_cast<double*>(ws + w.grad);
+    p.grad_a = grad_a ? grad_a : wg;
+    p.grad_incl = grad_incl ? grad_incl : wg + n;
+    p.grad_rin = grad_r_in ? grad_r_in : wg + 2 * n;
+    p.grad_sum = grad_sum;
+    p.partials = reinterpret_cast<double*>(ws + w.partials);
+    p.ck_shift = ck_shift;
     p.ticket = reinterpret_cast<uint32_t*>(ws);
     p.stats = stats ? reinterpret_cast<unsigned long long*>(stats)
                     : reinterpret_cast<unsigned long long*>(ws + w.stats);

@@ -149,12 +149,15 @@ struct AdjParams {
     const uint8_t* fate;
     const double* r_hit;
     const double* cot;
-    double *grad_a, *grad_incl, *grad_rin;
+    double *grad_a, *grad_incl, *grad_rin;  // per pixel: the caller's arrays or the workspace's
+    double* grad_sum;           // the three sums (caller's device memory), or NULL
+    double* partials;           // [3][ADJ_RED_BLOCKS] block sums of the reduction
     uint32_t* ticket;
     unsigned long long* stats;  // [ok, failed, overflow, mismatch]
     double* ckpt;               // [max_ckpt][6][n_lanes]
-    double* seg;                // [64][6][n_lanes]
+    double* seg;                // [1 << ck_shift][6][n_lanes]
     int32_t n_lanes, max_ckpt;
+    int32_t ck_shift;           // checkpoints every 1 << ck_shift accepted steps
     // work list: the differentiated rays, longest forward integration first
     const int32_t* n_steps;     // the forward render's step counts (may be NULL)
     uint32_t* hist;             // [SORT_BINS + 1] bin counts, then offsets; [SORT_BINS] = list length
@@ -167,28 +170,42 @@ struct AdjParams {
 #endif
 constexpr int ADJ_MAX_LANES = KT_ADJ_MAX_LANES;
 constexpr int ADJ_MAX_CKPT = 256;
+constexpr int ADJ_CK_SHIFT_DEFAULT = 6;  // checkpoints every 64 accepted steps
+constexpr int ADJ_CK_SHIFT_MIN = 3, ADJ_CK_SHIFT_MAX = 10;
+constexpr int ADJ_RED_BLOCKS = 256;      // fixed grid of the gradient reduction (deterministic)
+
+// log2 of kt_integrator.checkpoint_every (0 selects 64); -1 unless a power
+// of two in [8, 1024].
+inline int adj_ck_shift(int32_t every) {
+    if (every == 0) return ADJ_CK_SHIFT_DEFAULT;
+    for (int s = ADJ_CK_SHIFT_MIN; s <= ADJ_CK_SHIFT_MAX; ++s)
+        if (every == (1 << s)) return s;
+    return -1;
+}
 
 struct AdjLayout {
-    size_t stats, hist, ckpt, seg, keys, list, total;
+    size_t stats, hist, partials, ckpt, seg, keys, list, grad, total;
     int32_t n_lanes, max_ckpt;
 };
 
-inline AdjLayout adj_layout(size_t n_rays, int64_t max_steps) {
+inline AdjLayout adj_layout(size_t n_rays, int64_t max_steps, int ck_shift) {
     AdjLayout w;
     size_t lanes = (n_rays + 255) / 256 * 256;
     if (lanes > static_cast<size_t>(ADJ_MAX_LANES)) lanes = ADJ_MAX_LANES;
     if (lanes < 256) lanes = 256;
-    int64_t ck = max_steps / 64 + 2;
+    int64_t ck = (max_steps >> ck_shift) + 2;
     if (ck > ADJ_MAX_CKPT) ck = ADJ_MAX_CKPT;
     w.n_lanes = static_cast<int32_t>(lanes);
     w.max_ckpt = static_cast<int32_t>(ck);
     w.stats = 64;
     w.hist = 256;
-    w.ckpt = align256(w.hist + 4u * (SORT_BINS + 1));
+    w.partials = align256(w.hist + 4u * (SORT_BINS + 1));
+    w.ckpt = align256(w.partials + 3u * ADJ_RED_BLOCKS * sizeof(double));
     w.seg = align256(w.ckpt + static_cast<size_t>(ck) * 6u * lanes * sizeof(double));
-    w.keys = align256(w.seg + 64u * 6u * lanes * sizeof(double));
+    w.keys = align256(w.seg + (size_t{1} << ck_shift) * 6u * lanes * sizeof(double));
     w.list = align256(w.keys + 2u * n_rays);
-    w.total = align256(w.list + 4u * n_rays);
+    w.grad = align256(w.list + 4u * n_rays);
+    w.total = align256(w.grad + 3u * sizeof(double) * n_rays);
     return w;
 }
 

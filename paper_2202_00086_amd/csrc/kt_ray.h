@@ -49,6 +49,18 @@ constexpr float controller_exponent() {
     return METHOD == KT_BS ? 1.0f / (2 * BS_COLUMNS - 1) : 0.2f;
 }
 
+// Whether the step-size control runs entirely in FP64.  For the Runge-Kutta
+// pairs the factor only steers the step size and is taken in FP32 (with one
+// hardware reciprocal estimate in the error norm).  Bulirsch-Stoer takes
+// about 60 long steps per ray, and where its steps land moves the swept
+// angle by up to 1e-5 under a 1e-7 change of the step size, so its control
+// follows the plain FP64 arithmetic: refined reciprocals, an FP64 power and
+// FP64 clamps.
+template <int METHOD>
+constexpr bool fp64_control() {
+    return METHOD == KT_BS;
+}
+
 // Step-size factor 0.9 err^(-1/(q+1)) from the mean-square error msq = err^2,
 // evaluated in FP32: it only steers the step size.
 template <int METHOD>
@@ -57,13 +69,43 @@ __device__ __forceinline__ float step_factor(double msq) {
     return 0.9f * __builtin_amdgcn_exp2f(x * __builtin_amdgcn_logf(static_cast<float>(msq)));
 }
 
+// The same factor in FP64: 0.9 exp(-ln(msq) / (2 (q + 1))) with the kernel's
+// own logarithm and exponential (about an ulp each).
+template <int METHOD>
+__device__ __forceinline__ double step_factor64(double msq) {
+    constexpr double x = -0.5 / (METHOD == KT_BS ? 2 * BS_COLUMNS - 1 : 5);
+    return 0.9 * exp_fast(x * log_fast(msq));
+}
+
+// h multiplier after a rejected step: max(0.2, factor).
+template <int METHOD>
+__device__ __forceinline__ double reject_factor(double msq) {
+    if constexpr (fp64_control<METHOD>())
+        return fmax(0.2, step_factor64<METHOD>(msq));
+    else
+        return static_cast<double>(fmaxf(0.2f, step_factor<METHOD>(msq)));
+}
+
+// h multiplier after an accepted step: 5 for a negligible error (err below
+// 1e-10), else the factor clamped to [0.2, 5].
+template <int METHOD>
+__device__ __forceinline__ double accept_factor(double msq) {
+    if (!(msq >= 1e-20)) return 5.0;
+    if constexpr (fp64_control<METHOD>())
+        return fmin(5.0, fmax(0.2, step_factor64<METHOD>(msq)));
+    else
+        return static_cast<double>(fminf(5.0f, fmaxf(0.2f, step_factor<METHOD>(msq))));
+}
+
 // Mean square of err_i / sc_i over the five components.  The five
-// reciprocals come from one hardware reciprocal estimate of the product of
-// the scales (relative error ~5e-8: this number only steers the step size).
+// reciprocals come from one reciprocal of the product of the scales: the
+// hardware estimate (relative error ~5e-8: this number only steers the step
+// size), or with REFINED that estimate refined to about an ulp.
+template <bool REFINED = false>
 __device__ __forceinline__ double error_msq(const double er[5], const double sc[5]) {
     const double p01 = sc[0] * sc[1], p34 = sc[3] * sc[4];
     const double p012 = p01 * sc[2];
-    const double q = __builtin_amdgcn_rcp(p012 * p34);
+    const double q = REFINED ? rcp(p012 * p34) : __builtin_amdgcn_rcp(p012 * p34);
     const double q012 = q * p34;           // 1 / (sc0 sc1 sc2)
     const double q34 = q * p012;           // 1 / (sc3 sc4)
     const double q01 = q012 * sc[2];       // 1 / (sc0 sc1)

@@ -136,6 +136,8 @@ enum : int {
     F_EVSRC = 1 << 7,     // event being located is the source sphere
     F_USED32 = 1 << 24,   // mixed pass: some step used the FP32 mass part
     F_EVESC = 1 << 25,    // event being located is the celestial sphere
+    F_EV32 = 1 << 26,     // mixed pass: the step whose event is being located (and
+                          // then retaken) ran with the FP32 mass part
 };
 constexpr int NCROSS_SHIFT = 8;   // 8 bits: equatorial crossings outside the disk
 constexpr int EVIT_SHIFT = 16;    // 8 bits: trial steps of the current event
@@ -293,6 +295,28 @@ trace_kernel(const Hot hp) {
             fate = KT_FATE_MAXSTEPS;
         } else {
             const bool locating = (fl & F_LOCATE) != 0;
+            bool use32 = false;
+            if constexpr (MIXED) {
+                // The FP32 mass part runs wave-uniformly.  A lane locating an
+                // event, or retaking the step it lay in, must use the
+                // precision of that accepted step (its trial steps are steps
+                // of the same stepper, and the retake must reproduce the
+                // step bit for bit).  The lowest such lane sets the wave's
+                // precision and lanes that cannot use it sit this pass out;
+                // with no such lane the FP32 part runs when every stepping
+                // lane is beyond r_switch.
+                const bool pinned = (fl & (F_LOCATE | F_RETAKE)) != 0;
+                const bool ev32 = (fl & F_EV32) != 0;
+                const unsigned long long pin = __ballot(pinned);
+                if (pin != 0ull) {
+                    const int lead = __ffsll(pin) - 1;
+                    use32 = ((__ballot(pinned && ev32) >> lead) & 1ull) != 0ull;
+                } else {
+                    use32 = __all(y[0] >= hp.r_switch);
+                }
+                const bool fits = pinned ? (ev32 == use32) : (!use32 || y[0] >= hp.r_switch);
+                if (!fits) continue;
+            }
             const double hs = locating ? COLD(C_EVC) : h;
             double yn[5], kn[5], er[5];
             Diag dg;
@@ -300,9 +324,7 @@ trace_kernel(const Hot hp) {
             const double s0 = COLD(C_CS), c0 = COLD(C_CC);
             if constexpr (MIXED) {
                 const Spacetime32 sf{static_cast<float>(st.M), static_cast<float>(st.a), static_cast<float>(st.a2)};
-                // the FP32 mass part only when every stepping lane of the wave
-                // is beyond r_switch (a wave-uniform branch)
-                if (__all(y[0] >= hp.r_switch)) {
+                if (use32) {
                     dp45_step<true>(st, rc, y, k1, s0, c0, hs, yn, kn, er, &dg, &sf);
                     fl |= F_USED32;
                     evals32_acc += EVALS_PER_STEP;
@@ -385,18 +407,17 @@ trace_kernel(const Hot hp) {
                     double sc[5];
 #pragma unroll
                     for (int i = 0; i < 5; ++i) sc[i] = fma(hp.rtol, fmax(fabs(y[i]), fabs(yn[i])), hp.atol);
-                    const double msq = error_msq(er, sc);
+                    const double msq = error_msq<fp64_control<METHOD>()>(er, sc);
                     if (isnan(msq)) {
                         fate = KT_FATE_STEPFAIL;
                         accept = false;
                     } else if (msq > 1.0) {
-                        h *= static_cast<double>(fmaxf(0.2f, step_factor<METHOD>(msq)));
+                        h *= reject_factor<METHOD>(msq);
                         fl |= F_REJECTED;
                         accept = false;
                         if (h < 1e-12 * fmax(1.0, fabs(COLD(C_LAM)))) fate = KT_FATE_STEPFAIL;
                     } else {
-                        double fac = 5.0;
-                        if (msq >= 1e-20) fac = static_cast<double>(fminf(5.0f, fmaxf(0.2f, step_factor<METHOD>(msq))));
+                        double fac = accept_factor<METHOD>(msq);
                         if (fl & F_REJECTED) fac = fmin(fac, 1.0);
                         h_next = h * fac;
                     }
@@ -413,7 +434,7 @@ trace_kernel(const Hot hp) {
                     if ((li.feat & FEAT_DISK) && !(fl & F_SKIPDISK)) {
                         const double ga = y[1] - HALF_PI, gb = yn[1] - HALF_PI;
                         if (ga * gb < 0.0) {
-                            fl = (fl & ~(F_EVSRC | (0xff << EVIT_SHIFT))) | F_LOCATE;
+                            fl = (fl & ~(F_EVSRC | F_EV32 | (0xff << EVIT_SHIFT))) | F_LOCATE | (use32 ? F_EV32 : 0);
                             COLD(C_EVA) = 0.0;
                             COLD(C_EVFA) = ga;
                             COLD(C_EVB) = h;
@@ -441,7 +462,7 @@ trace_kernel(const Hot hp) {
                             if ((li.feat & FEAT_SRC) && !(fl & F_SRCDONE)) {
                                 if (y[0] < li.r_src && yn[0] >= li.r_src) {
                                     const double fa = y[0] - li.r_src, fb = yn[0] - li.r_src;
-                                    fl = (fl & ~(0xff << EVIT_SHIFT)) | F_EVSRC | F_LOCATE;
+                                    fl = (fl & ~(F_EV32 | (0xff << EVIT_SHIFT))) | F_EVSRC | F_LOCATE | (use32 ? F_EV32 : 0);
                                     COLD(C_EVA) = 0.0;
                                     COLD(C_EVFA) = fa;
                                     COLD(C_EVB) = h;
@@ -459,7 +480,7 @@ trace_kernel(const Hot hp) {
                                 if (yn[0] > li.r_esc && (li.feat & FEAT_SKY)) {
                                     // locate the crossing of the celestial sphere
                                     const double fa = y[0] - li.r_esc, fb = yn[0] - li.r_esc;
-                                    fl = (fl & ~(F_EVSRC | (0xff << EVIT_SHIFT))) | F_EVESC | F_LOCATE;
+                                    fl = (fl & ~(F_EVSRC | F_EV32 | (0xff << EVIT_SHIFT))) | F_EVESC | F_LOCATE | (use32 ? F_EV32 : 0);
                                     COLD(C_EVA) = 0.0;
                                     COLD(C_EVFA) = fa;
                                     COLD(C_EVB) = h;

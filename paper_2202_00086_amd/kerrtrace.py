@@ -63,7 +63,8 @@ class kt_integrator(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("h_fixed", C.c_double),
                 ("rtol", C.c_double), ("atol", C.c_double), ("h_init", C.c_double),
                 ("capture_buffer", C.c_double), ("r_escape", C.c_double),
-                ("h_budget", C.c_double), ("r_switch", C.c_double), ("max_steps", C.c_int64)]
+                ("h_budget", C.c_double), ("r_switch", C.c_double), ("max_steps", C.c_int64),
+                ("checkpoint_every", C.c_int32)]
 
 
 class kt_launch(C.Structure):
@@ -107,7 +108,7 @@ _lib.kt_workspace_bytes.restype = C.c_size_t
 _lib.kt_workspace_bytes_batch.argtypes = [C.c_int32, _P(kt_image), _P(kt_integrator)]
 _lib.kt_adjoint.argtypes = [_P(kt_camera), _P(kt_spacetime), _P(kt_disk), _P(kt_integrator), C.c_void_p,
                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                            C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
 _lib.kt_adjoint.restype = C.c_int
 _lib.kt_adjoint_workspace_bytes.argtypes = [_P(kt_camera), _P(kt_integrator)]
 _lib.kt_adjoint_workspace_bytes.restype = C.c_size_t
@@ -187,10 +188,11 @@ def kt_adjoint_workspace_bytes(camera, integ):
 
 
 def kt_adjoint(camera, spacetime, disk, integ, fate_ptr, r_hit_ptr, cot_ptr, grad_a_ptr, grad_incl_ptr,
-               grad_rin_ptr, stats_ptr, workspace_ptr, workspace_bytes, stream_ptr, n_steps_ptr=None):
+               grad_rin_ptr, stats_ptr, workspace_ptr, workspace_bytes, stream_ptr, n_steps_ptr=None,
+               grad_sum_ptr=None):
     return _lib.kt_adjoint(C.byref(camera), C.byref(spacetime), C.byref(disk), C.byref(integ), fate_ptr,
-                           r_hit_ptr, n_steps_ptr, cot_ptr, grad_a_ptr, grad_incl_ptr, grad_rin_ptr, stats_ptr,
-                           workspace_ptr, workspace_bytes, stream_ptr)
+                           r_hit_ptr, n_steps_ptr, cot_ptr, grad_a_ptr, grad_incl_ptr, grad_rin_ptr,
+                           grad_sum_ptr, stats_ptr, workspace_ptr, workspace_bytes, stream_ptr)
 
 
 def kt_init_rays(camera, spacetime, state_ptr, invalid_ptr, stream_ptr):
@@ -205,12 +207,13 @@ def make_structs(M=1.0, a=0.0, metric=0, q=0.0, r_obs=1000.0, incl=math.pi / 2, 
                  ny=64, method=DP45, precision=FP64, h_fixed=1.0 / 128, rtol=1e-12, atol=1e-12,
                  h_init=1.0, cap_buffer=0.01, r_escape=0.0, h_budget=1e-10, r_switch=300.0,
                  max_steps=1_000_000, disk_on=0, r_in=6.0, r_out=30.0, emis_q=2.0, rotation=0, l0=0.0,
-                 emis_model=0, src_on=0, r_src=1000.0, sky_on=0, grid_deg=6.0, line_deg=0.25):
+                 emis_model=0, src_on=0, r_src=1000.0, sky_on=0, grid_deg=6.0, line_deg=0.25,
+                 checkpoint_every=0):
     """C structs from keyword parameters (the same names the workloads use)."""
     cam = kt_camera(r_obs, incl, fov_x, fov_y, nx, ny)
     st = kt_spacetime(M, a, int(metric), q)
     integ = kt_integrator(method, precision, h_fixed, rtol, atol, h_init, cap_buffer, r_escape,
-                          h_budget, r_switch, int(max_steps))
+                          h_budget, r_switch, int(max_steps), int(checkpoint_every))
     disk = kt_disk(int(disk_on), r_in, r_out, emis_q, int(rotation), l0, int(emis_model))
     src = kt_source(int(src_on), r_src, int(sky_on), grid_deg, line_deg)
     return cam, st, disk, src, integ

@@ -19,8 +19,8 @@ the CPU oracle (oracle.Setup) accept these keyword names.
   qmetric_lensing(q)        the appendix's q-metric in the lensing setup.
   differentiable_disk       a = 0.7, i = 45 deg, 512x512 disk with the tapered
                             emissivity; disk_fit_target is its fit target.
-  heterogeneous_batch       256 seeded Kerr disk images: sides 64..1024 in
-                            steps of 64, a ~ U[0, 0.998], i ~ U[5, 85] deg,
+  heterogeneous_batch       256 seeded square Kerr disk images: sides 64..1024
+                            in steps of 64, a ~ U[0, 0.998], i ~ U[5, 85] deg,
                             r_obs log-uniform in [100, 1e4]M, +-35M, disk
                             from the prograde ISCO to 30M, I_em ~ r^-2.
 """
@@ -126,16 +126,20 @@ IMAGE_KEYS = ("M", "a", "metric", "q", "r_obs", "incl", "fov_x", "fov_y", "nx", 
               "emis_q", "rotation", "l0", "emis_model", "src_on", "r_src", "sky_on", "grid_deg", "line_deg")
 
 
-def heterogeneous_batch(n_images=256, seed=20220201, side_unit=64, side_steps=16, fov=35.0, rtol=1e-12):
+def heterogeneous_batch(n_images=256, seed=20220201, side_unit=64, side_steps=16, fov=35.0, rtol=1e-12,
+                        square=True):
     """(images, integ): `images` is a list of per-image dicts (IMAGE_KEYS),
-    `integ` the shared integrator dict.  Sides are side_unit * (1 + k) with k
-    uniform in [0, side_steps); nx and ny are drawn independently.  The
-    escape radius is 1.1 r_obs of each image (r_escape = 0 in `integ`)."""
+    `integ` the shared integrator dict.  Per image, in this order: the side
+    side_unit * (1 + k) with k uniform in [0, side_steps) (square images; with
+    square=False nx and ny are drawn one after the other, for ragged test
+    batches), a, the inclination and r_obs.  The 256-image default draws
+    105,156,608 rays.  The escape radius is 1.1 r_obs of each image
+    (r_escape = 0 in `integ`)."""
     rng = np.random.default_rng(seed)
     images = []
     for _ in range(n_images):
         nx = int(side_unit * (1 + rng.integers(0, side_steps)))
-        ny = int(side_unit * (1 + rng.integers(0, side_steps)))
+        ny = nx if square else int(side_unit * (1 + rng.integers(0, side_steps)))
         a = float(rng.uniform(0.0, 0.998))
         incl = math.radians(float(rng.uniform(5.0, 85.0)))
         r_obs = float(10.0 ** rng.uniform(2.0, 4.0))

@@ -87,3 +87,91 @@ def check_max_h(gpu, ora, key, mask, abs_floor=1e-13, rel=1e-2, budget=0.0):
         for q in (50, 90, 99):
             pa, pb = np.percentile(a, q), np.percentile(b, q)
             assert abs(pa - pb) <= 0.25 * max(pa, pb) + abs_floor, (key, q, pa, pb)
+
+
+def neighbours(pix, nx, ny):
+    """(pix[k], 8) ids of the 8-neighbours of each pixel, -1 outside the image."""
+    pix = np.asarray(pix, np.int64)
+    j, i = np.divmod(pix, nx)
+    out = []
+    for dj in (-1, 0, 1):
+        for di in (-1, 0, 1):
+            if dj or di:
+                jj, ii = j + dj, i + di
+                ok = (jj >= 0) & (jj < ny) & (ii >= 0) & (ii < nx)
+                out.append(np.where(ok, jj * nx + ii, -1))
+    return np.stack(out, 1)
+
+
+def sampled_parity(gpu, nx, ny, sample, trace, keys=(), rtol=1e-8, frac=1e-3, extra_rtol=None):
+    """The parity rules on a sample of a full-size image.
+
+    gpu: dict of full-image numpy arrays (fate, n_cross and the keys);
+    sample: pixel ids; trace(pix) -> oracle dict for those pixels.  The
+    oracle traces the sample, then the 8-neighbours of every sampled pixel
+    whose GPU 3x3 neighbourhood holds a fate or image-order boundary or
+    whose fates differ, so that the oracle's own neighbourhood decides
+    "within one pixel of a boundary" wherever one can lie.  Elsewhere the
+    GPU's uniform neighbourhood stands in for the oracle's, which can only
+    add pixels to the value check (a stricter test).
+
+    Returns (oracle sample dict, stats, mask of the sampled pixels whose
+    values were compared).  Asserts: fate mismatches only next
+    to an oracle boundary and at most frac of the sample; the keys within
+    rtol (extra_rtol: {key: (rtol, min |value|)} overrides) where fate and
+    image order agree, image order <= 1 and no oracle boundary is near."""
+    sample = np.asarray(sample, np.int64)
+    g_f = np.asarray(gpu["fate"]).ravel()
+    has_nc = "n_cross" in gpu
+    g_c = np.asarray(gpu["n_cross"]).ravel() if has_nc else np.zeros_like(g_f)
+    o = trace(sample.astype(np.int32))
+    o_c_s = o["n_cross"] if has_nc else np.zeros_like(o["fate"])
+    nb = neighbours(sample, nx, ny)
+    nbs = np.where(nb >= 0, nb, sample[:, None])  # clamp: outside counts as the pixel itself
+    g_near = ((g_f[nbs] != g_f[sample][:, None]) | (g_c[nbs] != g_c[sample][:, None])).any(1)
+    mism = g_f[sample] != o["fate"]
+    need = g_near | mism
+    # neighbour values: the oracle's where traced (the sample, then the
+    # needed neighbours), else the GPU's
+    img_f = g_f.astype(np.int16)
+    img_c = g_c.astype(np.int16)
+    img_f[sample] = o["fate"]
+    img_c[sample] = o_c_s
+    traced = np.zeros(g_f.size, bool)
+    traced[sample] = True
+    extra = np.unique(nb[need].ravel())
+    extra = extra[extra >= 0]
+    extra = extra[~traced[extra]]
+    if extra.size:
+        oe = trace(extra.astype(np.int32))
+        img_f[extra] = oe["fate"]
+        img_c[extra] = oe["n_cross"] if has_nc else 0
+    nf = img_f[nbs]
+    ncv = img_c[nbs]
+    o_near = ((nf != o["fate"][:, None]) | (ncv != o_c_s[:, None])).any(1)
+    bad = mism & ~o_near
+    assert not bad.any(), f"fate mismatches away from an oracle boundary at pixels {sample[bad][:10].tolist()}"
+    allowed = int(frac * sample.size)
+    assert mism.sum() <= allowed, f"{mism.sum()} fate mismatches > {allowed} ({frac:.1e} of {sample.size})"
+    ok = ~mism & ~o_near
+    if has_nc:
+        ok &= (g_c[sample] == o_c_s) & (o_c_s <= 1)
+    stats = {"sample": int(sample.size), "oracle_rays": int(sample.size + extra.size),
+             "fate_mismatches": int(mism.sum()), "compared": int(ok.sum())}
+    for key in keys:
+        tol, floor = (extra_rtol or {}).get(key, (rtol, 0.0))
+        a = np.asarray(gpu[key]).ravel()[sample][ok]
+        b = o[key][ok]
+        fa, fb = np.isfinite(a), np.isfinite(b)
+        assert (fa == fb).all(), f"{key}: finiteness differs at pixels {sample[ok][fa != fb][:10].tolist()}"
+        m = fa & (np.abs(b) > floor)
+        e = rel_err(a[m], b[m])
+        stats[key] = {"n": int(m.sum()), "max_rel_err": float(e.max()) if e.size else 0.0}
+        assert not e.size or e.max() <= tol, \
+            f"{key}: max rel err {e.max():.3e} > {tol:.1e} at pixel {sample[ok][m][np.argmax(e)]}"
+    return o, stats, ok
+
+
+def row_sample(nx, ny, every=16):
+    """Pixel ids of rows j = 0 mod every."""
+    return (np.arange(0, ny, every)[:, None] * nx + np.arange(nx)[None, :]).ravel()

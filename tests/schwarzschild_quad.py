@@ -84,3 +84,14 @@ def equator_crossing_angles(x, y, incl, n=3):
     if psi0 <= 0:
         psi0 += math.pi
     return [psi0 + k * math.pi for k in range(n)]
+
+
+def einstein_ring_radii(r0=1000.0, M=1.0):
+    """Image radii of the Einstein rings of a source at r_src = r0 directly
+    behind the hole, seen from r0: Psi(b) = (2k + 1) pi (k = 0, 1, 2) by the
+    orbit quadrature, b converted to the image radius rho = b sqrt(1 - 2M/r0)."""
+    out = []
+    for k, (lo, hi) in ((1, (6.0, 100.0)), (3, (5.1962, 6.0)), (5, (5.1961525, 5.1962))):
+        b = optimize.brentq(lambda v: swept_to_radius(v * M, r0, r0, M) - k * math.pi, lo, hi, xtol=1e-14)
+        out.append(b * M * math.sqrt(1.0 - 2.0 * M / r0))
+    return out

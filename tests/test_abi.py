@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared_functions():
         assert hasattr(lib, name), name
     assert set(K.EXPORTED) == set(_declared_functions())
-    assert K.kt_version() == 150
+    assert K.kt_version() == 200
 
 
 def test_struct_layouts_match_header():
@@ -52,7 +52,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(K.kt_spacetime) == 32
     assert C.sizeof(K.kt_disk) == 56
     assert C.sizeof(K.kt_source) == 40
-    assert C.sizeof(K.kt_integrator) == 8 + 8 * 8 + 8
+    assert C.sizeof(K.kt_integrator) == 8 + 8 * 8 + 8 + 8  # checkpoint_every padded to 8
     assert C.sizeof(K.kt_launch) == 20
     assert C.sizeof(K.kt_stats) == 12 * 8
     assert C.sizeof(K.kt_outputs) == 17 * 8
@@ -100,6 +100,9 @@ BAD = [
     dict(metric=1, q=0.5, method=0),
     dict(metric=1, q=0.5, precision=1),
     dict(sky_on=1, line_deg=float("inf")),
+    dict(checkpoint_every=48),                       # not a power of two
+    dict(checkpoint_every=4),                        # below 8
+    dict(checkpoint_every=2048),                     # above 1024
 ]
 
 
@@ -173,6 +176,11 @@ def test_workspace_bytes_zero_on_bad_camera():
     K, cam, st, disk, src, integ = _args(nx=65536, ny=32768)  # 2^31 rays
     assert K.kt_workspace_bytes(cam, integ) == 0
     assert K.kt_adjoint_workspace_bytes(cam, integ) == 0
+    K, cam, st, disk, src, integ = _args(checkpoint_every=96)
+    assert K.kt_adjoint_workspace_bytes(cam, integ) == 0
+    for every in (8, 64, 1024):
+        K, cam, st, disk, src, integ = _args(checkpoint_every=every)
+        assert K.kt_adjoint_workspace_bytes(cam, integ) > 0
 
 
 def _batch(images, **integ_kw):

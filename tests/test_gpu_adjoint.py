@@ -49,7 +49,7 @@ def test_adjoint_matches_oracle_finite_differences(torch_mod):
     nx = ny = 40
     params = W.differentiable_disk(n=nx)
     _announce("adjoint per-pixel", nx)
-    out, grads, stats = AG.adjoint_maps(**params)
+    out, grads, stats, _ = AG.adjoint_maps(**params)
     torch_mod.cuda.synchronize()
     st = stats.cpu().numpy()
     g = {k: v.cpu().numpy() for k, v in zip(KEYS, grads)}
@@ -159,7 +159,7 @@ def test_full_size_adjoint_sampled(torch_mod):
     n = 512
     params = W.differentiable_disk(n=n)
     _announce("adjoint full size sampled", n)
-    out, grads, stats = AG.adjoint_maps(**params)
+    out, grads, stats, _ = AG.adjoint_maps(**params)
     torch_mod.cuda.synchronize()
     st = stats.cpu().numpy()
     fate = out["fate"].cpu().numpy()
@@ -212,7 +212,7 @@ def test_random_disk_adjoint_matches_finite_differences(torch_mod, seed):
     params = _random_disk(seed)
     _announce("adjoint random disk", seed, {k: params[k] for k in ("a", "incl", "r_in", "r_out")},
               params.get("rotation", 0))
-    out, grads, stats = AG.adjoint_maps(**params)
+    out, grads, stats, _ = AG.adjoint_maps(**params)
     torch_mod.cuda.synchronize()
     st = stats.cpu().numpy()
     fate = out["fate"].cpu().numpy()
@@ -228,3 +228,101 @@ def test_random_disk_adjoint_matches_finite_differences(torch_mod, seed):
         a, b = g[k][m], fd[k][m]
         err = np.abs(a - b) / (np.abs(b) + 1e-3 * np.abs(b).max())
         assert err.max() < 1e-4, (k, err.max())
+
+
+def _adjoint_call(K, torch, r, out, cot, ws, nbytes, integ=None, steps=True, r_hit=None):
+    import ctypes as C
+    n = r.n
+    grads = [torch.full((n,), float("nan"), dtype=torch.float64, device="cuda:0") for _ in range(3)]
+    gsum = torch.full((3,), float("nan"), dtype=torch.float64, device="cuda:0")
+    stats = torch.zeros(4, dtype=torch.int64, device="cuda:0")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = K.kt_adjoint(r.cam, r.st, r.disk, integ or r.integ, out["fate"].data_ptr(),
+                      (r_hit if r_hit is not None else out["r_hit"]).data_ptr(), cot.data_ptr(),
+                      grads[0].data_ptr(), grads[1].data_ptr(), grads[2].data_ptr(), stats.data_ptr(),
+                      ws.data_ptr(), nbytes, stream, out["n_steps"].data_ptr() if steps else None,
+                      gsum.data_ptr())
+    assert rc == K.KT_OK, K.kt_last_error()
+    torch.cuda.synchronize()
+    return [g.cpu().numpy() for g in grads], gsum.cpu().numpy(), stats.cpu().numpy()
+
+
+def test_adjoint_image_sums_and_checkpoint_interval(torch_mod):
+    """grad_sum: the library's own sums of the three gradient maps, equal to
+    an exactly rounded sum of the maps to 1e-13 and bit-identical whatever
+    lanes ran the rays (with and without step counts).  The checkpoint
+    interval (8, 64 = default, 256 accepted steps) changes only what is
+    recomputed: the maps are bit-identical."""
+    import ctypes as C
+    import math as _m
+    torch = torch_mod
+    from paper_2202_00086_amd import kerrtrace as K
+    params = W.differentiable_disk(n=40)
+    _announce("adjoint sums and checkpoint intervals", 40)
+    r = K.Renderer(device="cuda:0", want=("fate", "r_hit", "g", "intensity", "n_cross", "n_steps"),
+                   stats=False, **params)
+    out = r.render()
+    cot = torch.linspace(-1.0, 2.0, r.n, dtype=torch.float64, device="cuda:0")
+    res = {}
+    for every in (8, 0, 256):
+        integ = K.make_structs(**dict(params, checkpoint_every=every))[4]
+        nbytes = K.kt_adjoint_workspace_bytes(r.cam, integ)
+        assert nbytes > 0
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+        for steps in (True, False):
+            res[(every, steps)] = _adjoint_call(K, torch, r, out, cot, ws, nbytes, integ, steps)
+    base_maps, base_sum, base_st = res[(0, True)]
+    assert base_st[1:].tolist() == [0, 0, 0] and base_st[0] > 300
+    for k in range(3):
+        want = _m.fsum(base_maps[k].tolist())
+        assert abs(base_sum[k] - want) <= 1e-13 * _m.fsum(abs(v) for v in base_maps[k].tolist()), (k, base_sum[k], want)
+    for key, (maps, sums, st) in res.items():
+        assert st.tolist() == base_st.tolist(), key
+        np.testing.assert_array_equal(sums.view(np.uint8), base_sum.view(np.uint8), err_msg=str(key))
+        for a, b in zip(maps, base_maps):
+            np.testing.assert_array_equal(a.view(np.uint8), b.view(np.uint8), err_msg=str(key))
+    bad = K.make_structs(**dict(params, checkpoint_every=48))[4]
+    assert K.kt_adjoint_workspace_bytes(r.cam, bad) == 0
+
+
+def test_adjoint_mismatch_is_counted_and_autograd_raises(torch_mod):
+    """A forward hit radius that the re-integration does not reproduce (one
+    pixel's r_hit nudged by an ulp-sized amount) is counted as a mismatch,
+    gets a zero gradient and drops out of grad_sum; DiskImage.backward
+    raises instead of returning such a gradient."""
+    torch = torch_mod
+    from paper_2202_00086_amd import autograd as AG
+    from paper_2202_00086_amd import kerrtrace as K
+    params = W.differentiable_disk(n=24)
+    _announce("adjoint mismatch", 24)
+    r = K.Renderer(device="cuda:0", want=("fate", "r_hit", "g", "intensity", "n_cross", "n_steps"),
+                   stats=False, **params)
+    out = r.render()
+    torch.cuda.synchronize()
+    cot = torch.ones(r.n, dtype=torch.float64, device="cuda:0")
+    nbytes = K.kt_adjoint_workspace_bytes(r.cam, r.integ)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    maps, sums, st = _adjoint_call(K, torch, r, out, cot, ws, nbytes)
+    disk = np.flatnonzero(out["fate"].cpu().numpy() == K.DISK)
+    k = int(disk[disk.size // 2])
+    r_hit = out["r_hit"].clone()
+    r_hit[k] = r_hit[k] * (1.0 + 1e-13)
+    maps2, sums2, st2 = _adjoint_call(K, torch, r, out, cot, ws, nbytes, r_hit=r_hit)
+    assert st2.tolist() == [st[0] - 1, 0, 0, 1]
+    for a, b in zip(maps, maps2):
+        assert b[k] == 0.0
+        keep = np.ones(r.n, bool)
+        keep[k] = False
+        np.testing.assert_array_equal(a[keep], b[keep])
+    with pytest.raises(K.KtError, match="not reproducing"):
+        AG.check_adjoint_stats(torch.tensor(st2))
+    AG.check_adjoint_stats(torch.tensor(st))
+    # through autograd: nudge the renderer's stored r_hit before backward
+    a = torch.tensor(params["a"], dtype=torch.float64, requires_grad=True)
+    i = torch.tensor(params["incl"], dtype=torch.float64, requires_grad=True)
+    rin = torch.tensor(params["r_in"], dtype=torch.float64, requires_grad=True)
+    fixed = {kk: v for kk, v in params.items() if kk not in ("a", "incl", "r_in")}
+    I, fate, _ = AG.disk_image(a, i, rin, **fixed)
+    I.grad_fn.renderer.out["r_hit"][k] *= 1.0 + 1e-13
+    with pytest.raises(K.KtError, match="not reproducing"):
+        I.sum().backward()

@@ -78,7 +78,7 @@ def _compare_with_singles(K, br, g, images, integ):
 def test_batch_equals_single_renders(K):
     """Twelve seeded Kerr disk images, sides 8..64, spins, inclinations and
     distances all different, in one launch."""
-    images, integ = W.heterogeneous_batch(n_images=12, seed=7, side_unit=8, side_steps=8)
+    images, integ = W.heterogeneous_batch(n_images=12, seed=7, side_unit=8, side_steps=8, square=False)
     _announce("batch vs single, 12 disk images", [(i["nx"], i["ny"]) for i in images])
     br, g = batch_render(K, images, integ)
     assert (g["fate"] <= K.DISK).all() and (g["fate"] == K.DISK).any()
@@ -102,7 +102,7 @@ def test_batch_with_source_and_ring_equals_single_renders(K):
 
 
 def test_batch_launch_shapes_are_bit_identical(K):
-    images, integ = W.heterogeneous_batch(n_images=6, seed=11, side_unit=16, side_steps=4)
+    images, integ = W.heterogeneous_batch(n_images=6, seed=11, side_unit=16, side_steps=4, square=False)
     _announce("batch launch shapes")
     _, ref = batch_render(K, images, integ)
     for ln in [K.kt_launch(1, 128, 0, 1), K.kt_launch(1, 64, 1, 8), K.kt_launch(0, 256, 0, 32),
@@ -118,7 +118,7 @@ def test_batch_mixed_precision(K):
     """Mixed batch at |H|_rel budget 1e-10: every ray meets the budget, rays
     re-run in FP64 equal the FP64 batch bit for bit, and the others keep the
     FP64 fate rule and agree on the disk observables to 1e-6."""
-    images, integ = W.heterogeneous_batch(n_images=10, seed=5, side_unit=12, side_steps=6)
+    images, integ = W.heterogeneous_batch(n_images=10, seed=5, side_unit=12, side_steps=6, square=False)
     _announce("batch mixed 1e-10")
     br, ref = batch_render(K, images, integ)
     _, g = batch_render(K, images, dict(integ, precision=K.MIXED, h_budget=1e-10, r_switch=300.0))
@@ -137,65 +137,62 @@ def test_batch_mixed_precision(K):
         assert e.max() < 1e-6, (key, e.max())
 
 
-def _neighbourhoods(rng, im, per_image):
-    """Sample pixel ids of one image and their clamped 3x3 neighbourhoods."""
-    nx, ny = im["nx"], im["ny"]
-    pix = np.sort(rng.choice(nx * ny, size=min(per_image, nx * ny), replace=False))
-    j, i = np.divmod(pix, nx)
-    nb = []
-    for dj in (-1, 0, 1):
-        for di in (-1, 0, 1):
-            nb.append(np.clip(j + dj, 0, ny - 1) * nx + np.clip(i + di, 0, nx - 1))
-    return pix.astype(np.int32), np.stack(nb, 1)
-
-
 def test_full_heterogeneous_batch_sampled(K):
-    """The 256-image workload in the default launch configuration: per image a
-    fixed sample of pixels against the oracle, stats over all 69M rays."""
+    """The 256-image workload (105,156,608 rays) in the default launch
+    configuration: per image a fixed 1% sample of pixels against the oracle
+    under the parity rules (the oracle's own 3x3 neighbourhood wherever a
+    boundary can lie; r_hit, g and intensity to 1e-8), fate mismatches at
+    most 0.1% of the whole sample; stats and the constraint over all rays."""
     import torch
     images, integ = W.heterogeneous_batch()
     want = ("fate", "r_hit", "g", "intensity", "max_rel_h", "n_cross", "n_evals")
-    _announce("heterogeneous batch 256 images sampled")
+    _announce("heterogeneous batch 256 images, 1% sample each")
     br = K.BatchRenderer(images, device="cuda:0", want=want, **integ)
+    assert br.n == 105_156_608
     br.render()
     torch.cuda.synchronize()
+    fate = br.out["fate"].cpu().numpy()
+    ncross = br.out["n_cross"].cpu().numpy()
     rng = np.random.default_rng(2202)
-    checked = disk = 0
+    total = mism = compared = disk = 0
     for k, im in enumerate(images):
-        pix, nb = _neighbourhoods(rng, im, 6)
+        n = im["nx"] * im["ny"]
         f = br.first[k]
-        idx = torch.from_numpy(np.concatenate([pix, nb.ravel()]).astype(np.int64) + f).to("cuda:0")
-        gv = {key: br.out[key].index_select(0, idx).cpu().numpy() for key in want}
-        ns = pix.size
-        o = O.trace_pixels(O.Setup(**W.image_params(im, integ)), pix)
-        nbf = gv["fate"][ns:].reshape(ns, 9)
-        near = (nbf != nbf[:, 4:5]).any(1)
-        same = gv["fate"][:ns] == o["fate"]
-        assert (same | near).all(), (k, pix[~(same | near)])
-        ok = same & ~near & (o["fate"] == K.DISK) & (gv["n_cross"][:ns] == o["n_cross"]) & (o["n_cross"] <= 1)
+        sample = np.sort(rng.choice(n, size=max(16, n // 100), replace=False))
+        g = {"fate": fate[f:f + n], "n_cross": ncross[f:f + n]}
+        idx = torch.from_numpy(sample + f).to("cuda:0")
         for key in ("r_hit", "g", "intensity"):
-            if ok.any():
-                e = P.rel_err(gv[key][:ns][ok], o[key][ok])
-                assert e.max() < 1e-8, (k, key, e.max())
-        checked += ns
-        disk += int(ok.sum())
-    print(f"[batch sampled] {checked} pixels, {disk} disk values compared", flush=True)
-    assert disk > 100
+            full = np.full(n, np.nan)
+            full[sample] = br.out[key].index_select(0, idx).cpu().numpy()
+            g[key] = full
+        setup = O.Setup(**W.image_params(im, integ))
+        o, st_p, ok = P.sampled_parity(g, im["nx"], im["ny"], sample, lambda pix: O.trace_pixels(setup, pix),
+                                       keys=("r_hit", "g", "intensity"), frac=1.0)
+        total += st_p["sample"]
+        mism += st_p["fate_mismatches"]
+        compared += st_p["compared"]
+        disk += st_p["r_hit"]["n"]
+    print(f"[batch sampled] {total} pixels, {mism} fate mismatches, {compared} compared, {disk} disk values",
+          flush=True)
+    assert mism <= 1e-3 * total
+    assert disk > 100000
     st = K.read_stats(br.out)
     assert st.rays == br.n == sum(i["nx"] * i["ny"] for i in images)
     assert sum(st.fate_count) == br.n
     assert st.evals == int(br.out["n_evals"].to(torch.int64).sum().item())
     h = br.out["max_rel_h"]
-    h_max = float(h[~torch.isnan(h)].max().item())
-    print(f"[batch sampled] max |H|_rel over the batch {h_max:.3e}", flush=True)
-    assert h_max < 1e-8
+    h = h[~torch.isnan(h)]
+    h_max = float(h.max().item())
+    h_999 = float(torch.quantile(h[::64].float(), 0.999).item())
+    print(f"[batch sampled] |H|_rel over the batch: max {h_max:.3e}, p99.9 {h_999:.3e}", flush=True)
+    assert h_999 < 1e-10 and h_max < 1e-8
 
 
 def test_autotune_picks_the_fastest_candidate(K):
     """The built-in candidate set on a small batch: every candidate timed,
     the fastest returned, and the outputs left by the tuner equal a plain
     render (FP64 results do not depend on the launch shape)."""
-    images, integ = W.heterogeneous_batch(n_images=6, seed=11, side_unit=16, side_steps=4)
+    images, integ = W.heterogeneous_batch(n_images=6, seed=11, side_unit=16, side_steps=4, square=False)
     _announce("autotune default set")
     br, ref = batch_render(K, images, integ)
     best, times = br.autotune(repeats=1)

@@ -39,7 +39,7 @@ def test_captured_render_replays_equal_eager(K, case):
         params = dict(W.kerr_disk(a=0.9, incl_deg=60.0, n=40, r_in=W.isco(0.9)), src_on=1, r_src=1000.0)
         r = K.Renderer(device="cuda:0", **params)
     else:
-        images, integ = W.heterogeneous_batch(n_images=5, seed=3, side_unit=8, side_steps=4)
+        images, integ = W.heterogeneous_batch(n_images=5, seed=3, side_unit=8, side_steps=4, square=False)
         r = K.BatchRenderer(images, device="cuda:0", **integ)
     _announce("graph capture", case)
     r.render()

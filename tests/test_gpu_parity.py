@@ -189,25 +189,23 @@ def test_invalid_pixels(K):
 
 
 @pytest.mark.parametrize("a", [0.9, 0.5, 0.998])
-def test_full_size_kerr_ring_sampled(K, a):
+def test_full_size_kerr_ring_rows(K, a):
     """1024x1024 at each spin of the workload, in the launch configuration the
-    benchmark times: a fixed sample of pixels against the oracle traced one
-    by one."""
+    benchmark times: every pixel of rows j = 0 mod 16 (65,536 rays) against
+    the oracle, with the oracle's own 3x3 neighbourhood wherever a boundary
+    can lie, under the parity rules (fate mismatches only next to a
+    boundary and at most 0.1% of the sample; deflection to 1e-8, the angle to
+    the source to 1e-7 where it exceeds 1e-6)."""
     params = W.kerr_ring(a, n=1024)
-    _announce("kerr_ring_1024 sampled", a)
+    _announce("kerr_ring_1024 rows j%16==0", a)
     g = gpu_render(K, params)
-    rng = np.random.default_rng(2022)
-    pix = np.sort(rng.choice(1024 * 1024, size=400, replace=False)).astype(np.int32)
-    o = ora_render(params, pix)
-    img_fate = g["fate"].reshape(1024, 1024)
-    near = P.boundary_mask(img_fate).ravel()[pix]
-    same = g["fate"][pix] == o["fate"]
-    assert (same | near).all()
-    ok = same & ~near
-    for key in ("deflection", "psi"):
-        e = P.rel_err(g[key][pix][ok], o[key][ok])
-        e = e[np.isfinite(e) & (np.abs(o[key][ok]) > 1e-6)]
-        assert np.max(e) < 1e-8 if key == "deflection" else np.max(e) < 1e-7, key
+    sample = P.row_sample(1024, 1024, 16)
+    o, st_p, ok = P.sampled_parity(g, 1024, 1024, sample, lambda pix: ora_render(params, pix),
+                                   keys=("deflection", "psi"), extra_rtol={"psi": (1e-7, 1e-6)})
+    print(f"[kerr_ring_1024 a={a}] {st_p}", flush=True)
+    assert st_p["deflection"]["n"] > 40000
+    gs = {k: g[k][sample] for k in ("max_rel_h", "max_abs_h")}
+    P.check_max_h(gs, o, "max_rel_h", ok, budget=1e-10)
     st = g["stats"]
     assert st.rays == 1024 * 1024 and sum(st.fate_count) == 1024 * 1024
     assert st.evals == g["n_evals"].astype(np.int64).sum()
@@ -227,28 +225,23 @@ def test_full_size_kerr_ring_sampled(K, a):
         assert h[worst] < 1e-10  # the benchmarked image meets the budget everywhere
 
 
-def test_full_size_schwarzschild_disk_sampled(K):
+def test_full_size_schwarzschild_disk_rows(K):
     """2048x2048 Schwarzschild disk (i = 80 deg, 6..30M, +-35M) at full size
-    in the default launch: a fixed sample of pixels against the oracle traced
-    one by one (hit radius, redshift, intensity to 1e-8 away from fate and
-    image-order boundaries); the mixed form at budget 1e-10 keeps every ray
-    within budget and its FP64 re-runs equal the FP64 render bit for bit."""
+    in the default launch: every pixel of rows j = 0 mod 16 (131,072 rays)
+    against the oracle under the parity rules (hit radius, redshift and
+    intensity to 1e-8 away from fate and image-order boundaries); the mixed
+    form at budget 1e-10 keeps every ray within budget and its FP64 re-runs
+    equal the FP64 render bit for bit."""
     n = 2048
     params = W.schwarzschild_disk(n=n)
-    _announce("schwarzschild_disk_2048 sampled")
+    _announce("schwarzschild_disk_2048 rows j%16==0")
     g = gpu_render(K, params)
-    rng = np.random.default_rng(80)
-    pix = np.sort(rng.choice(n * n, size=3000, replace=False)).astype(np.int32)
-    o = ora_render(params, pix)
-    near = (P.boundary_mask(g["fate"].reshape(n, n)) | P.boundary_mask(g["n_cross"].reshape(n, n))).ravel()[pix]
-    same = g["fate"][pix] == o["fate"]
-    assert (same | near).all()
-    ok = same & ~near & (o["fate"] == O.DISK) & (o["n_cross"] <= 1)
-    assert ok.sum() > 250
-    np.testing.assert_array_equal(g["n_cross"][pix][ok], o["n_cross"][ok])
-    for key in ("r_hit", "g", "intensity"):
-        e = P.rel_err(g[key][pix][ok], o[key][ok])
-        assert np.max(e) < 1e-8, (key, np.max(e))
+    sample = P.row_sample(n, n, 16)
+    o, st_p, ok = P.sampled_parity(g, n, n, sample, lambda pix: ora_render(params, pix),
+                                   keys=("r_hit", "g", "intensity"))
+    print(f"[disk 2048] {st_p}", flush=True)
+    assert st_p["r_hit"]["n"] > 20000
+    P.check_max_h({"max_rel_h": g["max_rel_h"][sample]}, o, "max_rel_h", ok, budget=1e-10)
     st = g["stats"]
     assert st.rays == n * n and sum(st.fate_count) == n * n
     assert np.nanmax(g["max_rel_h"]) < 1e-10
@@ -342,3 +335,36 @@ def test_polar_rays_wind_through_the_axis(K):
         s = O.Setup(**params)
         tr, _ = O.trace_one(s, 0.0, O.pixel_xy(s, 0, 30)[1])
         assert tr[:, 2].min() < 0.0 or tr[:, 2].max() > math.pi
+
+
+def test_resolved_einstein_ring(K):
+    """a = 0, i = 60 deg, +-60M at 256x256, so that the primary Einstein ring
+    of the source behind the hole (image radius 46.188M by the orbit
+    quadrature) is resolved: every pixel against the oracle under the
+    parity rules (deflection to 1e-8), the ring flags equal the oracle's
+    flags of its own deflection map away from the shadow edge, and every
+    flag lies within one pixel of a quadrature ring radius, all around the
+    primary ring."""
+    from tests import schwarzschild_quad as SQ
+    n, fov = 256, 60.0
+    params = dict(W.kerr_ring(0.0, n=n), fov_x=fov, fov_y=fov)
+    _announce("resolved ring", n, fov)
+    g = gpu_render(K, params)
+    o = ora_render(params)
+    P.check_fates(g["fate"], o["fate"], n, n)
+    m = P.value_mask(g, o, n, n)
+    P.check_values(g, o, "deflection", m, rtol=1e-8)
+    dx = 2 * fov / n
+    x = -fov + (np.arange(n) + 0.5) * dx
+    rho = np.hypot(x[None, :], x[:, None]).ravel()
+    radii = np.array(SQ.einstein_ring_radii())
+    ring_o = O.ring_flags(n, n, o["deflection"])
+    away = rho > radii[1] + 2 * dx
+    np.testing.assert_array_equal(g["ring"][away], ring_o[away])
+    flagged = g["ring"].astype(bool)
+    dist = np.abs(rho[:, None] - radii[None, :]).min(1)
+    assert (dist[flagged] <= dx * (1 + 1e-9)).all(), dist[flagged].max() / dx
+    ang = np.degrees(np.arctan2(np.repeat(x, n), np.tile(x, n)))
+    prim = flagged & (np.abs(rho - radii[0]) <= dx)
+    assert np.unique(((ang[prim] + 180.0) // 5).astype(int)).size == 72
+    print(f"[resolved ring] {prim.sum()} primary-ring flags, {flagged.sum()} in all", flush=True)

@@ -75,11 +75,9 @@ def test_random_configuration(K, k):
         d = m & (o["fate"] == O.DISK)
         for key in ("r_hit", "g", "intensity"):
             P.check_values(g, o, key, d, rtol=1e-8)
-    if p.get("src_on") and p["method"] != K.BS:
-        # Bulirsch-Stoer's long steps make the swept angle step-placement
-        # sensitive beyond this tolerance (its own test calibrates it)
+    if p.get("src_on"):
         e = m & np.isfinite(o["deflection"])
-        P.check_values(g, o, "deflection", e, rtol=1e-7)
+        P.check_values(g, o, "deflection", e, rtol=1e-8)
     # the constraint: same size on both sides where the rays agree
     h_g, h_o = g["max_rel_h"][m], o["max_rel_h"][m]
     ok = np.isfinite(h_g) & np.isfinite(h_o)

@@ -49,21 +49,21 @@ def test_scheme_kerr_ring_parity(K, name, method):
     P.check_fates(g["fate"], o["fate"], 64, 48, min_allowed=2)
     m = P.value_mask(g, o, 64, 48)
     # The swept angle is a sum of arcs between accepted positions, so it
-    # depends on where the steps land.  The kernel's step factor is FP32
-    # (step ends differ at ~1e-7), so the tolerance is 10x the oracle's own
-    # change when its first step moves by 1e-7: ~4e-14 for the Runge-Kutta
-    # pairs (hundreds of short steps), up to ~1e-5 for Bulirsch-Stoer's few
-    # long ones.
+    # depends on where the steps land: the oracle's own change when its
+    # first step moves by 1e-7 is printed for scale (~4e-14 for the
+    # Runge-Kutta pairs, up to ~1e-5 for Bulirsch-Stoer's few long steps).
+    # The kernel's step control keeps the step ends at rounding level of the
+    # oracle's (in FP64 for Bulirsch-Stoer), so the rule's 1e-8 holds for
+    # every scheme.
     o2 = O.trace_pixels(O.Setup(**dict(params, h_init=params["h_init"] * (1 + 1e-7))))
     same = m & (o2["fate"] == o["fate"]) & np.isfinite(o["deflection"])
     sens = {k: float(np.max(P.rel_err(o2[k][same & np.isfinite(o[k])], o[k][same & np.isfinite(o[k])])))
             for k in ("deflection", "psi")}
-    tol = {k: max(1e-8, 10.0 * v) for k, v in sens.items()}
     print(f"[{name}] step-placement sensitivity {sens}", flush=True)
-    assert tol["deflection"] < 1e-3
-    P.check_values(g, o, "deflection", m, rtol=tol["deflection"])
+    err = P.check_values(g, o, "deflection", m, rtol=1e-8)
     ok = m & np.isfinite(o["psi"]) & (o["psi"] > 1e-6)
-    P.check_values(g, o, "psi", ok, rtol=max(1e-7, tol["psi"]))
+    err_psi = P.check_values(g, o, "psi", ok, rtol=1e-7)
+    print(f"[{name}] deflection max rel err {err:.2e}, psi {err_psi:.2e}", flush=True)
     # every ray within the scheme's own level (the oracle's p99 at this
     # tolerance is 2.5e-9, 3.4e-10 and 2.2e-11 for RKF45, CK45 and BS), and
     # the distributions' percentiles agree
@@ -94,7 +94,7 @@ def test_scheme_batch_and_launch_shapes_bit_identical(K, name, method):
     """Each scheme's batch instantiation equals its single renders, and its
     outputs do not depend on the launch shape."""
     import torch
-    images, integ = W.heterogeneous_batch(n_images=4, seed=3, side_unit=8, side_steps=4)
+    images, integ = W.heterogeneous_batch(n_images=4, seed=3, side_unit=8, side_steps=4, square=False)
     integ = dict(integ, method=method, rtol=1e-10, atol=1e-10)
     _announce("scheme batch", name)
     br = K.BatchRenderer(images, device="cuda:0", **integ)

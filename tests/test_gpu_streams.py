@@ -29,7 +29,7 @@ def _host(out):
 
 
 def _renderers(K):
-    images, integ = W.heterogeneous_batch(n_images=6, seed=11, side_unit=8, side_steps=5)
+    images, integ = W.heterogeneous_batch(n_images=6, seed=11, side_unit=8, side_steps=5, square=False)
     return [K.Renderer(device="cuda:0", **dict(W.kerr_disk(a=0.7, incl_deg=75.0, n=96, r_in=W.isco(0.7)),
                                                src_on=1, r_src=1000.0)),
             K.Renderer(device="cuda:0", **W.qmetric_lensing(q=0.3, n=64)),

@@ -39,6 +39,9 @@ def test_heterogeneous_batch_is_seeded_and_in_range():
     assert im1 == im2 and len(im1) == 256
     sides = np.array([[i["nx"], i["ny"]] for i in im1])
     assert sides.min() == 64 and sides.max() == 1024 and (sides % 64 == 0).all()
+    # one square side per image, drawn before a, i and r_obs
+    assert (sides[:, 0] == sides[:, 1]).all()
+    assert int((sides[:, 0] * sides[:, 1]).sum()) == 105_156_608
     a = np.array([i["a"] for i in im1])
     incl = np.degrees([i["incl"] for i in im1])
     r = np.array([i["r_obs"] for i in im1])
@@ -52,3 +55,17 @@ def test_heterogeneous_batch_is_seeded_and_in_range():
     p = W.image_params(im1[3], integ)
     assert p["r_escape"] == 1.1 * im1[3]["r_obs"] and p["nx"] == im1[3]["nx"]
     assert W.heterogeneous_batch(seed=1)[0] != im1
+
+
+def test_heterogeneous_batch_draw_order():
+    """Side, then a, inclination and r_obs, per image, from one generator."""
+    rng = np.random.default_rng(20220201)
+    ref = []
+    for _ in range(3):
+        side = 64 * (1 + int(rng.integers(0, 16)))
+        ref.append((side, float(rng.uniform(0.0, 0.998)), math.radians(float(rng.uniform(5.0, 85.0))),
+                    float(10.0 ** rng.uniform(2.0, 4.0))))
+    im, _ = W.heterogeneous_batch(n_images=3)
+    assert [(i["nx"], i["a"], i["incl"], i["r_obs"]) for i in im] == ref
+    ragged, _ = W.heterogeneous_batch(n_images=40, seed=7, side_unit=8, side_steps=8, square=False)
+    assert any(i["nx"] != i["ny"] for i in ragged)
