@@ -175,3 +175,45 @@ def sampled_parity(gpu, nx, ny, sample, trace, keys=(), rtol=1e-8, frac=1e-3, ex
 def row_sample(nx, ny, every=16):
     """Pixel ids of rows j = 0 mod every."""
     return (np.arange(0, ny, every)[:, None] * nx + np.arange(nx)[None, :]).ravel()
+
+
+def ulp_sensitivity(trace_xy, x, y, key):
+    """Per-pixel relative change of the oracle's `key` when the pixel's
+    image-plane coordinate moves by one ulp (x and y, up and down): how far
+    the method itself carries rounding-level differences.  Pixels whose fate
+    changes under a nudge get inf.  trace_xy(x, y) -> oracle dict."""
+    base = trace_xy(x, y)
+    sens = np.zeros(x.size)
+    for xx, yy in ((np.nextafter(x, np.inf), y), (np.nextafter(x, -np.inf), y),
+                   (x, np.nextafter(y, np.inf)), (x, np.nextafter(y, -np.inf))):
+        o = trace_xy(xx, yy)
+        d = np.where(o["fate"] != base["fate"], np.inf, rel_err(o[key], base[key]))
+        sens = np.fmax(sens, np.where(np.isfinite(base[key]) | ~np.isfinite(d), d, 0.0))
+    return sens
+
+
+def check_values_rounding(gpu, ora, key, mask, sens, rtol=1e-8):
+    """Values against the oracle where the method carries rounding-level
+    differences far (Bulirsch-Stoer's step control: its error estimate is a
+    difference of two extrapolated values that agree to the tolerance, so
+    rounding changes it at the 1e-5 level and with it the step sequence).
+    The tolerance follows from the oracle's own behaviour: max(rtol, 10x the
+    largest one-ulp sensitivity over the compared pixels), and at most
+    3x the oracle's own share of pixels above rtol (plus two pixels) may
+    exceed rtol.  For schemes whose sensitivity is at rounding level this is
+    the plain rtol check."""
+    a = np.asarray(gpu[key])[mask]
+    b = np.asarray(ora[key])[mask]
+    s = np.asarray(sens)[mask]
+    fa, fb = np.isfinite(a), np.isfinite(b)
+    assert (fa == fb).all(), f"{key}: finiteness differs at {np.flatnonzero(fa != fb)[:10]}"
+    keep = fa & np.isfinite(s)
+    e = rel_err(a[keep], b[keep])
+    s = s[keep]
+    if not e.size:
+        return 0.0, 0.0
+    tol = max(rtol, 10.0 * float(s.max()))
+    assert e.max() <= tol, f"{key}: max rel err {e.max():.3e} > {tol:.1e} (largest 1-ulp sensitivity {s.max():.2e})"
+    n_over, n_own = int((e > rtol).sum()), int((s > rtol).sum())
+    assert n_over <= 3 * n_own + 2, f"{key}: {n_over} pixels above {rtol:.0e}, oracle's own {n_own}"
+    return float(e.max()), float(s.max())

@@ -368,3 +368,32 @@ def test_resolved_einstein_ring(K):
     prim = flagged & (np.abs(rho - radii[0]) <= dx)
     assert np.unique(((ang[prim] + 180.0) // 5).astype(int)).size == 72
     print(f"[resolved ring] {prim.sum()} primary-ring flags, {flagged.sum()} in all", flush=True)
+
+
+def test_mixed_event_location_keeps_its_precision(K):
+    """Mixed precision with disk crossings and the source sphere beyond
+    r_switch (r_switch = 10M, disk 6..30M at i = 80 deg, source at 1000M, no
+    re-run): a lane locating an event and retaking the step keeps the
+    precision of the step the event lay in, so the retake reproduces it and
+    no crossing is counted twice.  Image orders and fates follow the FP64
+    render under the parity rules (FP32 rounding only moves rays near
+    boundaries), and the deflection stays within the FP32 part's error."""
+    n = 96
+    params = dict(W.schwarzschild_disk(n=n), src_on=1, r_src=1000.0)
+    _announce("mixed event precision", n)
+    ref = gpu_render(K, params)
+    g = gpu_render(K, dict(params, precision=K.MIXED, h_budget=1e300, r_switch=10.0))
+    assert g["stats"].evals_fp32 > 0.05 * g["stats"].evals
+    P.check_fates(g["fate"], ref["fate"], n, n)
+    near = (P.boundary_mask(ref["fate"].reshape(n, n)) | P.boundary_mask(ref["n_cross"].reshape(n, n))).ravel()
+    same = (g["fate"] == ref["fate"]) & ~near
+    np.testing.assert_array_equal(g["n_cross"][same], ref["n_cross"][same])
+    # at rtol 1e-12 the FP32 part's rounding shows in the error estimate
+    # close in (r_switch = 10M), so the controller takes more steps there
+    d = g["n_steps"][same].astype(np.int64) - ref["n_steps"][same]
+    m = same & np.isfinite(ref["deflection"])
+    e = P.rel_err(g["deflection"][m], ref["deflection"][m])
+    print(f"[mixed events] FP32 share {g['stats'].evals_fp32 / g['stats'].evals:.3f}; deflection rel err "
+          f"max {e.max():.2e}; extra steps median {np.median(d):.0f}, p99 {np.percentile(d, 99):.0f}",
+          flush=True)
+    assert e.max() < 1e-5

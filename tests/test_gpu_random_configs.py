@@ -77,7 +77,16 @@ def test_random_configuration(K, k):
             P.check_values(g, o, key, d, rtol=1e-8)
     if p.get("src_on"):
         e = m & np.isfinite(o["deflection"])
-        P.check_values(g, o, "deflection", e, rtol=1e-8)
+        if p["method"] == K.BS:
+            # the step sequence carries rounding far (see the scheme tests):
+            # the tolerance follows from the oracle's own one-ulp sensitivity
+            s = O.Setup(**p)
+            xy = np.array([O.pixel_xy(s, q % nx, q // nx) for q in range(nx * ny)])
+            sens = P.ulp_sensitivity(lambda x, y: O.trace_xy(s, x, y), xy[:, 0].copy(), xy[:, 1].copy(),
+                                     "deflection")
+            P.check_values_rounding(g, o, "deflection", e, sens, rtol=1e-8)
+        else:
+            P.check_values(g, o, "deflection", e, rtol=1e-8)
     # the constraint: same size on both sides where the rays agree
     h_g, h_o = g["max_rel_h"][m], o["max_rel_h"][m]
     ok = np.isfinite(h_g) & np.isfinite(h_o)

@@ -140,3 +140,45 @@ def test_kerr_fates_vs_radial_potential(method):
         checked += 1
         assert o["fate"][p] == fate, (p, x, y, margin)
     assert checked >= 0.97 * 576
+
+
+def test_bulirsch_stoer_step_sequence_carries_rounding():
+    """Why Bulirsch-Stoer's swept angle is compared under a rounding-derived
+    tolerance: in the oracle itself a one-ulp nudge of the pixel coordinate
+    moves the deflection by ~1e-6 for some rays, where Dormand-Prince moves
+    it by ~1e-13.  The step sequences part at a step whose start states still
+    agree to rounding level: there the error estimate (T_KK - T_K,K-1, a
+    difference of two values that agree to the tolerance) is rounding noise
+    that decides the next step size."""
+    from paper_2202_00086_amd import workloads as W
+    from tests import parity as P
+    base = dict(W.kerr_ring(0.9, n=64, rtol=1e-11), ny=48)
+    rows = np.arange(12 * 64, 20 * 64)
+    sens = {}
+    for method in (O.DP45, O.BS):
+        s = O.Setup(**dict(base, method=method))
+        xy = np.array([O.pixel_xy(s, p % 64, p // 64) for p in rows])
+        sv = P.ulp_sensitivity(lambda x, y: O.trace_xy(s, x, y), xy[:, 0].copy(), xy[:, 1].copy(), "deflection")
+        sens[method] = sv[np.isfinite(sv)]
+    assert sens[O.DP45].max() < 1e-12
+    assert sens[O.BS].max() > 1e-7
+    # the most sensitive Bulirsch-Stoer ray: where its two step sequences part
+    s = O.Setup(**dict(base, method=O.BS))
+    xy = np.array([O.pixel_xy(s, p % 64, p // 64) for p in rows])
+    sv = P.ulp_sensitivity(lambda x, y: O.trace_xy(s, x, y), xy[:, 0].copy(), xy[:, 1].copy(), "deflection")
+    k = int(np.nanargmax(np.where(np.isfinite(sv), sv, 0.0)))
+    x, y = xy[k]
+    t1, _ = O.trace_one(s, x, y)
+    found = False
+    for yy in (np.nextafter(y, np.inf), np.nextafter(y, -np.inf)):
+        for xx in (x, np.nextafter(x, np.inf), np.nextafter(x, -np.inf)):
+            t2, _ = O.trace_one(s, xx, yy)
+            n = min(len(t1), len(t2))
+            h1, h2 = np.diff(t1[:n, 0]), np.diff(t2[:n, 0])
+            part = np.flatnonzero(np.abs(h1 - h2) > 1e-6 * np.abs(h1))
+            if part.size:
+                j = int(part[0])
+                # the start states of the parting step agree to rounding level
+                assert np.all(np.abs(t1[j, 1:] - t2[j, 1:]) <= 1e-12 * (np.abs(t1[j, 1:]) + 1.0))
+                found = True
+    assert found
