@@ -27,6 +27,17 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
+}  // namespace
+
+namespace kt {
+int set_error(int code, const char* msg) {
+    std::snprintf(g_err, sizeof g_err, "%s", msg);
+    return code;
+}
+}  // namespace kt
+
+namespace {
+
 bool finite_all(std::initializer_list<double> v) {
     for (double x : v)
         if (!std::isfinite(x)) return false;
@@ -276,7 +287,7 @@ bool is_mixed(const kt_integrator* integ) { return integ->precision == KT_MIXED;
 // The launch sequence shared by single and batch renders.  `table` holds the
 // validated images with their `first` offsets; for one image it travels in
 // Params and the device table is the workspace copy of img0.
-int render_images(const std::vector<kt::Image>& table, int64_t n_rays, const kt_integrator* integ,
+int render_images(const kt::Image* table, int32_t n_images, int64_t n_rays, const kt_integrator* integ,
                   const kt_outputs* out, void* workspace, size_t workspace_bytes, void* hip_stream,
                   const kt_launch* launch) {
     kt_launch ln{1, 256, 0, 4, KT_ORDER_RING};
@@ -289,9 +300,9 @@ int render_images(const std::vector<kt::Image>& table, int64_t n_rays, const kt_
     if (ln.order != KT_ORDER_RING && ln.order != KT_ORDER_ROWS)
         return fail(KT_EINVAL, "launch order must be KT_ORDER_RING or KT_ORDER_ROWS");
 
-    const int32_t n_images = static_cast<int32_t>(table.size());
     const bool batch = n_images > 1;
-    const kt::WsLayout w = kt::ws_layout(static_cast<size_t>(n_rays), table.size(), batch, is_mixed(integ));
+    const kt::WsLayout w =
+        kt::ws_layout(static_cast<size_t>(n_rays), static_cast<size_t>(n_images), batch, is_mixed(integ));
     if (!workspace) return fail(KT_EINVAL, "workspace must not be NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
         return fail(KT_EINVAL, "workspace must be 256-byte aligned");
@@ -348,7 +359,7 @@ int render_images(const std::vector<kt::Image>& table, int64_t n_rays, const kt_
     p.batch = ln.batch;
     p.from_list = 0;
 
-    if (batch && kt::launch_upload_images(table.data(), n_images, reinterpret_cast<kt::Image*>(ws + w.images),
+    if (batch && kt::launch_upload_images(table, n_images, reinterpret_cast<kt::Image*>(ws + w.images),
                                           hip_stream))
         return fail(KT_EDEVICE, "image table upload failed: %s", hipGetErrorString(hipGetLastError()));
     if (kt::launch_ws_init(p, hip_stream))
@@ -427,6 +438,20 @@ int make_table(int32_t n_images, const kt_image* images, const kt_integrator* in
 
 }  // namespace
 
+namespace kt {
+int validate_single(const kt_camera* camera, const kt_spacetime* spacetime, const kt_disk* disk,
+                    const kt_source* source, const kt_integrator* integ, const kt_outputs* out, Image* im) {
+    g_err[0] = 0;
+    int rc = validate_common(camera, spacetime);
+    if (rc) return rc;
+    if (!integ || !out) return fail(KT_EINVAL, "integ and out must not be NULL");
+    if ((rc = validate_integ(integ)) || (rc = validate_outputs(out))) return rc;
+    if ((rc = make_image(camera, spacetime, disk, source, integ, out->ring != nullptr, *im))) return rc;
+    im->first = 0;
+    return KT_OK;
+}
+}  // namespace kt
+
 extern "C" {
 
 const char* kt_last_error(void) { return g_err; }
@@ -472,15 +497,11 @@ int kt_render_ex(const kt_camera* camera, const kt_spacetime* spacetime, const k
                  const kt_source* source, const kt_integrator* integ, const kt_outputs* out,
                  void* workspace, size_t workspace_bytes, void* hip_stream, const kt_launch* launch) {
     g_err[0] = 0;
-    int rc = validate_common(camera, spacetime);
+    kt::Image im;  // one image: no host allocation on this path
+    int rc = kt::validate_single(camera, spacetime, disk, source, integ, out, &im);
     if (rc) return rc;
-    if (!integ || !out) return fail(KT_EINVAL, "integ and out must not be NULL");
-    if ((rc = validate_integ(integ)) || (rc = validate_outputs(out))) return rc;
-    std::vector<kt::Image> table(1);
-    if ((rc = make_image(camera, spacetime, disk, source, integ, out->ring != nullptr, table[0]))) return rc;
-    table[0].first = 0;
     const int64_t n = static_cast<int64_t>(camera->nx) * camera->ny;
-    return render_images(table, n, integ, out, workspace, workspace_bytes, hip_stream, launch);
+    return render_images(&im, 1, n, integ, out, workspace, workspace_bytes, hip_stream, launch);
 }
 
 int kt_render(const kt_camera* camera, const kt_spacetime* spacetime, const kt_disk* disk,
@@ -500,7 +521,7 @@ int kt_render_batch(int32_t n_images, const kt_image* images, const kt_integrato
     std::vector<kt::Image> table;
     int64_t n = 0;
     if ((rc = make_table(n_images, images, integ, out->ring != nullptr, table, &n))) return rc;
-    return render_images(table, n, integ, out, workspace, workspace_bytes, hip_stream, launch);
+    return render_images(table.data(), n_images, n, integ, out, workspace, workspace_bytes, hip_stream, launch);
 }
 
 size_t kt_adjoint_workspace_bytes(const kt_camera* camera, const kt_integrator* integ) {
@@ -622,11 +643,12 @@ int kt_autotune_batch(int32_t n_images, const kt_image* images, const kt_integra
     }
     int best_i = -1;
     float best_ms = 0.0f;
-    rc = render_images(table, n, integ, out, workspace, workspace_bytes, hip_stream, &cand[0]);
+    rc = render_images(table.data(), n_images, n, integ, out, workspace, workspace_bytes, hip_stream, &cand[0]);
     for (size_t i = 0; rc == KT_OK && i < cand.size(); ++i) {
         if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(KT_EDEVICE, "hipEventRecord failed"); break; }
         for (int r = 0; r < repeats && rc == KT_OK; ++r)
-            rc = render_images(table, n, integ, out, workspace, workspace_bytes, hip_stream, &cand[i]);
+            rc = render_images(table.data(), n_images, n, integ, out, workspace, workspace_bytes, hip_stream,
+                               &cand[i]);
         if (rc) break;
         float ms = 0.0f;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||

@@ -209,6 +209,14 @@ inline AdjLayout adj_layout(size_t n_rays, int64_t max_steps, int ck_shift) {
     return w;
 }
 
+// Leave msg for kt_last_error() on this host thread and return code (kt_api.cpp).
+int set_error(int code, const char* msg);
+
+// The argument checks of a single-image render; fills the image's table
+// entry.  Returns KT_OK or the error code (message left as for a render).
+int validate_single(const kt_camera* camera, const kt_spacetime* spacetime, const kt_disk* disk,
+                    const kt_source* source, const kt_integrator* integ, const kt_outputs* out, Image* im);
+
 // Host-side launchers (kt_trace.hip, kt_adjoint.hip).
 int launch_adjoint(const AdjParams& p, void* stream);
 int launch_ws_init(const Params& p, void* stream);  // also copies p into the workspace
