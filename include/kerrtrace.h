@@ -223,6 +223,26 @@ int kt_render_ex(const kt_camera *camera, const kt_spacetime *spacetime, const k
 /* Workspace size in bytes for this camera and integrator (0 on bad input). */
 size_t kt_workspace_bytes(const kt_camera *camera, const kt_integrator *integ);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation:
+   kt_render_ex with the library's own scratch array of
+   KT_NOALLOC_SCRATCH_BYTES in place of the workspace argument.  It calls no
+   allocating routine.  The array is a file-scope device array: each GPU the
+   library runs on holds one copy until the process ends.  The caller still
+   owns and passes every output.
+   Limit: renders whose kt_workspace_bytes() exceeds KT_NOALLOC_SCRATCH_BYTES
+   (about 4.7M FP64 rays, 3.5M with KT_MIXED; a 2048^2 FP64 image fits)
+   return KT_ENOMEM with a message, before any device work.
+   Every call on one GPU shares that GPU's array and leaves its contents
+   behind (the render clears what must start at zero with its own kernels):
+   calls that overlap on one GPU -- from two host threads, or on two streams
+   without ordering between them -- race.  Other arguments, results and
+   errors as for kt_render_ex. */
+#define KT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int kt_render_noalloc(const kt_camera *camera, const kt_spacetime *spacetime, const kt_disk *disk,
+                      const kt_source *source, const kt_integrator *integ, const kt_outputs *out,
+                      void *hip_stream, const kt_launch *launch);
+
 /* One image of a batch: its own camera, spacetime, disk and source.  Disk
    and source are disabled with enabled = 0. */
 typedef struct kt_image {

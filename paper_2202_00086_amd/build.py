@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkerrtrace.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("kt_trace.hip", "kt_adjoint.hip", "kt_api.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("kt_trace.hip", "kt_adjoint.hip", "kt_noalloc.hip", "kt_api.cpp")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

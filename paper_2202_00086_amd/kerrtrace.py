@@ -1,6 +1,6 @@
 """Python binding of libkerrtrace.so (the C ABI in include/kerrtrace.h).
 
-The functions kt_render, kt_render_ex, kt_render_batch, kt_autotune_batch,
+The functions kt_render, kt_render_ex, kt_render_noalloc, kt_render_batch, kt_autotune_batch,
 kt_adjoint, kt_workspace_bytes, kt_adjoint_workspace_bytes,
 kt_workspace_bytes_batch, kt_init_rays, kt_last_error and kt_version mirror
 the C entry points one to one and only marshal arguments: every step of the ray tracing runs in the HIP kernels of
@@ -96,6 +96,9 @@ _lib.kt_render.argtypes = [_P(kt_camera), _P(kt_spacetime), _P(kt_disk), _P(kt_s
 _lib.kt_render.restype = C.c_int
 _lib.kt_render_ex.argtypes = _lib.kt_render.argtypes + [_P(kt_launch)]
 _lib.kt_render_ex.restype = C.c_int
+_lib.kt_render_noalloc.argtypes = [_P(kt_camera), _P(kt_spacetime), _P(kt_disk), _P(kt_source),
+                                   _P(kt_integrator), _P(kt_outputs), C.c_void_p, _P(kt_launch)]
+_lib.kt_render_noalloc.restype = C.c_int
 _lib.kt_render_batch.argtypes = [C.c_int32, _P(kt_image), _P(kt_integrator), _P(kt_outputs), C.c_void_p,
                                  C.c_size_t, C.c_void_p, _P(kt_launch)]
 _lib.kt_render_batch.restype = C.c_int
@@ -120,7 +123,7 @@ _lib.kt_last_error.restype = C.c_char_p
 _lib.kt_version.argtypes = []
 _lib.kt_version.restype = C.c_int
 
-EXPORTED = ("kt_render", "kt_render_ex", "kt_render_batch", "kt_autotune_batch", "kt_adjoint",
+EXPORTED = ("kt_render", "kt_render_ex", "kt_render_noalloc", "kt_render_batch", "kt_autotune_batch", "kt_adjoint",
             "kt_workspace_bytes", "kt_workspace_bytes_batch", "kt_adjoint_workspace_bytes", "kt_init_rays",
             "kt_last_error", "kt_version")
 AUTOTUNE_DEFAULT_COUNT = 20
@@ -158,6 +161,15 @@ def kt_render_ex(camera, spacetime, disk, source, integ, outputs, workspace_ptr,
     return _lib.kt_render_ex(C.byref(camera), C.byref(spacetime), _ref(disk), _ref(source),
                              C.byref(integ), C.byref(outputs), workspace_ptr, workspace_bytes,
                              stream_ptr, _ref(launch))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # KT_NOALLOC_SCRATCH_BYTES
+
+
+def kt_render_noalloc(camera, spacetime, disk, source, integ, outputs, stream_ptr, launch=None):
+    """kt_render_ex on the library's own scratch array (no workspace)."""
+    return _lib.kt_render_noalloc(C.byref(camera), C.byref(spacetime), _ref(disk), _ref(source),
+                                  C.byref(integ), C.byref(outputs), stream_ptr, _ref(launch))
 
 
 def kt_workspace_bytes_batch(images, integ):

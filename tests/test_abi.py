@@ -31,7 +31,7 @@ def _declared_functions():
 
 def test_header_declares_expected_entry_points():
     assert _declared_functions() == sorted(
-        ["kt_render", "kt_render_ex", "kt_render_batch", "kt_autotune_batch", "kt_adjoint",
+        ["kt_render", "kt_render_ex", "kt_render_noalloc", "kt_render_batch", "kt_autotune_batch", "kt_adjoint",
          "kt_workspace_bytes", "kt_workspace_bytes_batch", "kt_adjoint_workspace_bytes", "kt_init_rays",
          "kt_last_error", "kt_version"])
 

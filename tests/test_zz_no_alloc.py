@@ -1,0 +1,75 @@
+"""kt_render_noalloc (the render on the library's own scratch array, for
+callers that cannot allocate) through the C ABI against kt_render_ex with a
+caller's workspace: two calls in a row, the second with a smaller image,
+every output bit for bit; a render too large for the array is refused before
+any device work."""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2202_00086_amd import workloads as W
+
+_KEYS = ("fate", "r_hit", "g", "intensity", "max_abs_h", "max_rel_h", "psi", "deflection", "theta_f", "phi_f",
+         "n_cross", "ring", "n_steps", "n_evals")
+
+
+def _announce(*what):
+    print("[gpu-case]", *what, flush=True)
+    sys.stdout.flush()
+
+
+def _host(out):
+    return {k: v.cpu().numpy() for k, v in out.items() if k != "stats"}
+
+
+@pytest.mark.gpu
+def test_noalloc_equals_workspace_render():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2202_00086_amd import kerrtrace as K
+    stream = torch.cuda.current_stream()
+    # FP64 (bit-identical for any launch), then a smaller image, then the
+    # mixed form at budget 0, which sends every ray that used the FP32 part
+    # back through the FP64 pass and so equals the FP64 render bit for bit
+    # (exercising the fallback list in the scratch array)
+    disk = dict(W.kerr_ring(0.9, n=160), disk_on=1, r_in=W.isco(0.9), r_out=30.0)
+    small = dict(W.kerr_ring(0.5, n=72), ny=40)
+    mixed = dict(W.kerr_ring(0.9, n=96), disk_on=1, r_in=W.isco(0.9), r_out=30.0)
+    cases = [(disk, disk), (small, small),
+             (dict(mixed, precision=K.MIXED, h_budget=0.0, r_switch=300.0), mixed)]
+    for params, ref_params in cases:
+        _announce("noalloc", params["a"], params["nx"], params["ny"], params.get("precision", 0))
+        ref = K.Renderer(device="cuda:0", **ref_params)
+        want = _host(ref.render())
+        st_ref = bytes(ref.out["stats"].cpu().numpy())
+        cam, st, dk, src, integ = K.make_structs(**params)
+        got = K.alloc_outputs(ref.n, torch.device("cuda:0"), ref.want)
+        # stale values in the outputs must all be overwritten
+        for v in got.values():
+            v.fill_(0xFF if v.dtype == torch.uint8 else 7)
+        rc = K.kt_render_noalloc(cam, st, dk, src, integ, K.outputs_struct(got), C.c_void_p(stream.cuda_stream))
+        assert rc == K.KT_OK, K.kt_last_error()
+        torch.cuda.synchronize()
+        g = _host(got)
+        for k in _KEYS:
+            if k in want:
+                np.testing.assert_array_equal(g[k].view(np.uint8), want[k].view(np.uint8), err_msg=k)
+        if params is ref_params:
+            assert bytes(got["stats"].cpu().numpy()) == st_ref
+        else:
+            sg, sr = K.read_stats(got), K.read_stats(ref.out)
+            assert sg.fallback_rays > 0 and sg.evals_fp32 > 0
+            assert list(sg.fate_count) == list(sr.fate_count)
+
+
+def test_noalloc_refuses_renders_beyond_its_array():
+    """Validation and the size check run on the host: no GPU needed."""
+    from paper_2202_00086_amd import kerrtrace as K
+    cam, st, disk, src, integ = K.make_structs(**W.kerr_ring(0.9, n=4096))
+    assert K.kt_workspace_bytes(cam, integ) > K.NOALLOC_SCRATCH_BYTES
+    out = K.kt_outputs()
+    out.fate = 0x1000  # never dereferenced: the size check fails first
+    assert K.kt_render_noalloc(cam, st, disk, src, integ, out, None) == K.KT_ENOMEM
+    assert "scratch" in K.kt_last_error()
