@@ -30,26 +30,42 @@ if ROOT not in sys.path:
 
 METRIC = "rays/s & RK stage-evals/s, 1024² Kerr a=0.9; mixed vs FP64 at |H|≤1e-10"
 
-# Algorithmic FP64 work, counted on the formulas the method evaluates
-# (+, -, x, /, sqrt = 1; FMA = 2; sincos, atan2, pow = 2), independent of how
-# the kernel computes them (e.g. three reciprocals count 3 even though the
-# kernel derives them from one):
-#   Hamiltonian RHS in Carter form                              58 per evaluation
-#   per Dormand-Prince step (six evaluations): stage sums and
-#   error estimate 290, error norm and step-size control 37,
-#   constraint diagnostics 7                                   334 per step
-#   swept angle between successive positions (source on)        22 per step
-RHS_FLOP = 58
-STEP_FLOP = 290 + 37 + 7
-ARC_FLOP = 22
+# Algorithmic FP64 work per unit, counted mechanically: a counting scalar
+# runs a plain Carter-form reference of each unit (tests/flopcount/, checked
+# against the oracle by tests/test_flop_count.py, which also pins these
+# numbers).  +, -, x, / and sqrt count 1, sin and cos 1 each, pow and atan2 2.
+#   rhs      Hamilton's equations in Carter's form              per evaluation
+#   diag     H and |H|_rel from the evaluation's intermediates   per accepted step
+#   stages   Dormand-Prince stage states 2..7 (26 coefficients)  per attempted step
+#   error    the embedded error estimate (6 weights)             per attempted step
+#   control  RMS error norm and the new step size                per attempted step
+#   arc      swept angle between accepted positions (source on)  per accepted step
+#   q_rhs, q_diag   the same two units for the appendix's q-metric
+FLOP_UNITS = {"rhs": 53, "diag": 5, "stages": 230, "error": 60, "control": 30, "arc": 26, "q_rhs": 75,
+              "q_diag": 8}
+# the earlier hand count and the survey's estimate, printed for comparison
+FLOP_PER_EVAL_HAND_COUNT = 58 + (290 + 37 + 7 + 22) / 6.0
+FLOP_PER_EVAL_SURVEY_ESTIMATE = 150.0
+
+
+def flop_per_launch(evals, attempts6, accepted, src_on, qmetric=False):
+    """Algorithmic FLOP of a Dormand-Prince launch: evals RHS evaluations,
+    attempts6 the evaluations spent in step attempts (evals minus each ray's
+    first, FSAL seed, evaluation; six per attempt, trial steps of event
+    location included) and `accepted` accepted steps.  With the source on,
+    every accepted step is priced with an arc (a slight overcount: the few
+    steps after the source sphere take none)."""
+    u = FLOP_UNITS
+    attempts = attempts6 / 6.0
+    rhs, diag = (u["q_rhs"], u["q_diag"]) if qmetric else (u["rhs"], u["diag"])
+    return (evals * rhs + attempts * (u["stages"] + u["error"] + u["control"])
+            + accepted * (diag + (u["arc"] if src_on else 0)))
+
+
 PEAK_FP64_VECTOR = 78.6e12  # MI355X FP64 vector, FLOP/s
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "trace_kernel_kerr_ring_1024_a0.9_counters.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_00086_amd", "csrc", f)
                   for f in ("kt_device.h", "kt_elem.h", "kt_ray.h", "kt_internal.h", "kt_trace.hip")]
-
-
-def flop_per_eval(src_on):
-    return RHS_FLOP + (STEP_FLOP + (ARC_FLOP if src_on else 0)) / 6.0
 
 
 def kernel_source_hash():
@@ -82,32 +98,90 @@ def traffic_from_profile():
         return None
 
 
-def cpu_baseline(params, rows_every=16):
-    """The oracle, as it stands, on rows j = 0 mod rows_every of the image."""
-    import numpy as np
-
-    import oracle as O
+def _threads():
     try:
         n_avail = len(os.sched_getaffinity(0))
     except AttributeError:
         n_avail = os.cpu_count() or 1
-    threads = min(n_avail, int(os.environ.get("OMP_NUM_THREADS", n_avail)))
-    nx, ny = params["nx"], params["ny"]
-    pix = (np.arange(0, ny, rows_every)[:, None] * nx + np.arange(nx)[None, :]).ravel().astype(np.int32)
-    t0 = time.perf_counter()
-    o = O.trace_pixels(O.Setup(**params), pix, threads=threads)
-    dt = time.perf_counter() - t0
-    model = None
+    return min(n_avail, int(os.environ.get("OMP_NUM_THREADS", n_avail))), n_avail
+
+
+def host_cpu():
+    """What the host reports about its CPU (a virtual machine may name only
+    the family)."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+            for ln in f:
+                if ":" in ln:
+                    k, v = (x.strip() for x in ln.split(":", 1))
+                    if k in ("model name", "cpu family", "model", "stepping", "cpu MHz") and k not in info:
+                        info[k] = v
+                    if k == "flags" and "flags" not in info:
+                        info["flags"] = " ".join(f for f in v.split() if f.startswith(("avx", "fma")))
     except OSError:
         pass
-    return {"value": pix.size / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
-            "cpu_model": model, "cpus_visible": n_avail,
-            "sample": f"rows j = 0 mod {rows_every} of the same image ({pix.size} rays, "
-                      f"{dt:.1f} s wall on {threads} threads; plain C FP64 oracle, -O2, OpenMP)",
-            "stage_evals_per_s": float(o["n_evals"].astype(np.int64).sum()) / dt}
+    return info
+
+
+def oracle_image(params, pix=None, threads=0):
+    import oracle as O
+    t0 = time.perf_counter()
+    o = O.trace_pixels(O.Setup(**params), pix, threads=threads)
+    return o, time.perf_counter() - t0
+
+
+def cpu_baseline(params, gpu_out=None, single_rows_every=64):
+    """The oracle, as it stands, on the host cores: (i) the whole image on
+    every core it may use (the `value`), with the parity of the GPU image
+    against it; (ii) one thread on rows j = 0 mod single_rows_every, with
+    the whole image's time extrapolated from it."""
+    import numpy as np
+
+    threads, n_avail = _threads()
+    nx, ny = params["nx"], params["ny"]
+    o, dt = oracle_image(params, threads=threads)
+    res = {"value": nx * ny / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+           "sample": f"the whole {nx}x{ny} image ({nx * ny} rays) in {dt:.1f} s wall on {threads} threads "
+                     f"(plain C FP64 oracle, -O2, OpenMP dynamic 64)",
+           "stage_evals_per_s": float(o["n_evals"].astype(np.int64).sum()) / dt,
+           "cpus_visible": n_avail, "cpu": host_cpu()}
+    pix = (np.arange(0, ny, single_rows_every)[:, None] * nx + np.arange(nx)[None, :]).ravel().astype(np.int32)
+    o1, dt1 = oracle_image(params, pix, threads=1)
+    res["single_thread"] = {"rays_per_s": pix.size / dt1, "sample": f"rows j = 0 mod {single_rows_every} "
+                            f"({pix.size} rays) in {dt1:.1f} s on 1 thread",
+                            "whole_image_s_extrapolated": dt1 * nx * ny / pix.size}
+    if gpu_out is not None:
+        res["gpu_parity_whole_image"] = image_parity(gpu_out, o, nx, ny, ("deflection", "psi"))
+    return res, o
+
+
+def image_parity(gpu_out, o, nx, ny, keys):
+    """The parity rules of the test suite on a whole image: fate mismatches
+    (and how many sit next to an oracle boundary), and the largest relative
+    error of each key where fates and image order agree, order <= 1 and no
+    boundary is within one pixel."""
+    import numpy as np
+
+    from tests import parity as P
+    g = {k: v.cpu().numpy() for k, v in gpu_out.items() if k != "stats"}
+    mism = g["fate"] != o["fate"]
+    near = P.boundary_mask(o["fate"].reshape(ny, nx)).ravel()
+    m = P.value_mask(g, o, nx, ny)
+    res = {"rays": nx * ny, "fate_mismatches": int(mism.sum()),
+           "fate_mismatches_away_from_boundary": int((mism & ~near).sum()), "values_compared": int(m.sum())}
+    for k in keys:
+        a, b = g[k][m], o[k][m]
+        ok = np.isfinite(a) & np.isfinite(b) & (np.abs(b) > 1e-6)
+        e = P.rel_err(a[ok], b[ok])
+        res[k] = {"max_rel_err": float(e.max()) if e.size else 0.0, "p99": float(np.percentile(e, 99)) if e.size else 0.0}
+    return res
+
+
+def error_vs_oracle(out, o, nx, ny, keys):
+    """Max and p99 relative error per output of a (mixed) render against the
+    FP64 oracle's image, on pixels where the parity rules compare values."""
+    return image_parity(out, o, nx, ny, keys)
 
 
 def run_form(K, torch, params, steps, warmup, launch=None):
@@ -127,13 +201,30 @@ def run_form(K, torch, params, steps, warmup, launch=None):
     launch_ms = [a.elapsed_time(b) for a, b in ev]
     st = K.read_stats(r.out)
     n = r.n
-    return {"wall_s": wall, "ms_per_step": 1e3 * wall / steps,
-            "launch_ms": sum(launch_ms) / len(launch_ms), "launch_ms_min": min(launch_ms),
-            "rays": n, "evals": int(st.evals), "evals_fp32": int(st.evals_fp32),
-            "fallback_rays": int(st.fallback_rays), "fates": [int(c) for c in st.fate_count[:6]],
-            "max_rel_h": float(r.out["max_rel_h"].max().item()),
-            "p999_rel_h": float(torch.quantile(r.out["max_rel_h"].float()[::16], 0.999).item()),
-            "out": r.out}
+    res = {"wall_s": wall, "ms_per_step": 1e3 * wall / steps,
+           "launch_ms": sum(launch_ms) / len(launch_ms), "launch_ms_min": min(launch_ms),
+           "rays": n, "evals": int(st.evals), "evals_fp32": int(st.evals_fp32),
+           "fallback_rays": int(st.fallback_rays), "fates": [int(c) for c in st.fate_count[:6]],
+           "out": r.out}
+    res.update(h_stats(torch, r.out["max_rel_h"]))
+    if "n_steps" in r.out:
+        res["steps_accepted"] = int(r.out["n_steps"].to(torch.int64).sum().item())
+    return res
+
+
+def h_stats(torch, h):
+    """Max, p99.9 and the count over 1e-10 of max |H|_rel (NaN rays skipped)."""
+    h = h[~torch.isnan(h)]
+    return {"max_rel_h": float(h.max().item()),
+            "p999_rel_h": float(torch.quantile(h[::max(1, h.numel() // 4000000)].float(), 0.999).item()),
+            "rays_over_1e-10": int((h > 1e-10).sum().item())}
+
+
+def launch_flop(st, steps_accepted, src_on, qmetric=False):
+    """Algorithmic FLOP of one render from its statistics (every ray but the
+    invalid ones spends one evaluation seeding its first step)."""
+    valid = int(st.rays) - int(st.fate_count[5])
+    return flop_per_launch(int(st.evals), int(st.evals) - valid, steps_accepted, src_on, qmetric)
 
 
 def error_vs(torch, test, ref, keys=("deflection", "psi")):
@@ -150,7 +241,7 @@ def error_vs(torch, test, ref, keys=("deflection", "psi")):
     return res
 
 
-BATCH_WANT = ("fate", "r_hit", "g", "intensity", "max_rel_h", "used_fp64", "n_cross")
+BATCH_WANT = ("fate", "r_hit", "g", "intensity", "max_rel_h", "used_fp64", "n_cross", "n_steps")
 
 
 def _time(torch, fn, steps):
@@ -202,7 +293,8 @@ def run_f4_forms(K, torch, W, steps):
     a = 0.95.  Per image: time, rays/s, stage-evals/s, evaluations per ray,
     max |H|_rel and the fate histogram."""
     res = {}
-    for name, p in (("lensing_1024_a0.98", W.lensing(a=0.98, n=1024)),
+    for name, p in (("resolved_ring_1024_a0_fov60", dict(W.kerr_ring(0.0, n=1024), fov_x=60.0, fov_y=60.0)),
+                    ("lensing_1024_a0.98", W.lensing(a=0.98, n=1024)),
                     ("lensing_1024_flat", W.lensing(a=0.0, n=1024, M=0.0)),
                     ("qmetric_lensing_1024_q0.5", W.qmetric_lensing(q=0.5, n=1024)),
                     ("thin_disk_l0_2048x1024_a0.95", W.thin_disk_l0(a=0.95))):
@@ -212,14 +304,36 @@ def run_f4_forms(K, torch, W, steps):
         st = K.read_stats(r.out)
         hr = r.out["max_rel_h"][r.out["fate"] <= K.DISK]
         hr = hr[~torch.isnan(hr)]
-        kerr_dp45 = p.get("metric", 0) == 0
+        steps_acc = int(r.out["n_steps"].to(torch.int64).sum().item())
+        flop = launch_flop(st, steps_acc, bool(p.get("src_on")), qmetric=p.get("metric", 0) == 1)
         res[name] = {"ms_per_image": 1e3 * t, "rays_per_s": r.n / t, "stage_evals_per_s": st.evals / t,
-                     "evals_per_ray": st.evals / r.n,
-                     "alu_frac": st.evals / t * flop_per_eval(src_on=False) / PEAK_FP64_VECTOR if kerr_dp45 else None,
+                     "evals_per_ray": st.evals / r.n, "alu_frac": flop / t / PEAK_FP64_VECTOR,
+                     "flop_per_eval": flop / st.evals,
                      "max_rel_h": float(hr.max().item()) if hr.numel() else None,
                      "fates": [int(c) for c in st.fate_count[:6]]}
+        if "ring" in r.out and name.startswith("resolved_ring"):
+            res[name].update(ring_report(torch, r.out, p))
         del r
     return res
+
+
+def ring_report(torch, out, p):
+    """Ring flags of the resolved-ring image against the Schwarzschild orbit
+    quadrature's ring radii: how many flags, and the largest distance (in
+    pixels) of a flag from the nearest ring radius."""
+    import numpy as np
+
+    from tests import schwarzschild_quad as SQ
+    n, fov = p["nx"], p["fov_x"]
+    dx = 2 * fov / n
+    x = -fov + (np.arange(n) + 0.5) * dx
+    rho = np.hypot(x[None, :], x[:, None]).ravel()
+    radii = np.array(SQ.einstein_ring_radii(p["r_obs"]))
+    ring = out["ring"].cpu().numpy().astype(bool)
+    dist = np.abs(rho[ring][:, None] - radii[None, :]).min(1) / dx
+    prim = int((np.abs(rho[ring] - radii[0]) <= dx).sum())
+    return {"ring_radii_quadrature": radii.tolist(), "ring_flags": int(ring.sum()), "primary_ring_flags": prim,
+            "max_flag_distance_px": float(dist.max()) if dist.size else None}
 
 
 def run_adjoint_form(K, torch, W, steps):
@@ -285,8 +399,10 @@ def run_batch_forms(K, torch, W, steps):
     br.render()
     t = _time(torch, br.render, steps)
     st = K.read_stats(br.out)
+    flop = launch_flop(st, int(br.out["n_steps"].to(torch.int64).sum().item()), src_on=False)
     res["batch_fp64"] = {"rays_per_s": n / t, "stage_evals_per_s": st.evals / t, "ms_per_step": 1e3 * t,
-                         "alu_frac": st.evals / t * flop_per_eval(src_on=False) / PEAK_FP64_VECTOR}
+                         "alu_frac": flop / t / PEAK_FP64_VECTOR, "flop_per_eval": flop / st.evals}
+    res["batch_fp64"].update(h_stats(torch, br.out["max_rel_h"]))
     ref = {k: v for k, v in br.out.items()}
     singles = [K.Renderer(device="cuda:0", want=BATCH_WANT, stats=False, **W.image_params(im, integ))
                for im in images]
@@ -297,6 +413,7 @@ def run_batch_forms(K, torch, W, steps):
     t = _time(torch, per_image, max(1, steps // 2))
     res["per_image_fp64"] = {"rays_per_s": n / t, "ms_per_step": 1e3 * t,
                              "launches": len(images), "launch": "default (persistent, block 256, batch 4, ring-first order)"}
+    res["per_image_fp64"].update(h_stats(torch, torch.cat([r.out["max_rel_h"] for r in singles])))
     del singles
     bm = K.BatchRenderer(images, device="cuda:0", want=BATCH_WANT, launch=best,
                          **dict(integ, precision=K.MIXED, h_budget=1e-10, r_switch=300.0))
@@ -304,16 +421,98 @@ def run_batch_forms(K, torch, W, steps):
     t = _time(torch, bm.render, steps)
     sm = K.read_stats(bm.out)
     h = bm.out["max_rel_h"]
+    used64 = bm.out["used_fp64"].bool()
     res["batch_mixed_budget1e-10"] = {
         "rays_per_s": n / t, "stage_evals_per_s": sm.evals / t, "ms_per_step": 1e3 * t,
         "r_switch": 300.0, "h_budget": 1e-10, "fallback_fraction": sm.fallback_rays / n,
         "fp32_eval_fraction": sm.evals_fp32 / max(1, sm.evals),
-        "max_rel_h": float(h[~torch.isnan(h)].max().item()),
+        # rays over the budget after the re-run: all are FP64 results (re-run,
+        # or never in FP32), the method's own level at rtol 1e-12
+        "over_budget_after_rerun": int(((h > 1e-10) & ~torch.isnan(h)).sum().item()),
+        "over_budget_rerun_rays": int(((h > 1e-10) & used64).sum().item()),
         "error_vs_fp64": error_vs(torch, bm.out, ref, keys=("r_hit", "g", "intensity"))}
+    res["batch_mixed_budget1e-10"].update(h_stats(torch, h))
     # the workload's own comparison: the mixed batched launch against
     # per-image FP64 launches, and against the FP64 batched launch
     res["mixed_batch_over_per_image_fp64"] = (n / t) / res["per_image_fp64"]["rays_per_s"]
     res["mixed_batch_over_fp64_batch"] = (n / t) / res["batch_fp64"]["rays_per_s"]
+    return res
+
+
+# FP64 at the loosest tolerance whose p99.9 |H|_rel stays within 1e-10 on the
+# headline image (the equal-accuracy FP64 line; `--only mixed` sweeps it),
+# and the r_switch the mixed form runs with.
+RTOL_EQUAL_ACCURACY = 6e-12
+MIXED_R_SWITCH = 300.0
+
+
+def form_entry(f, extra=None):
+    e = {"rays_per_s": f["rays"] / (f["ms_per_step"] / 1e3), "stage_evals_per_s": f["evals"] / (f["ms_per_step"] / 1e3),
+         "ms_per_step": f["ms_per_step"], "max_rel_h": f["max_rel_h"], "p999_rel_h": f["p999_rel_h"],
+         "rays_over_1e-10": f["rays_over_1e-10"]}
+    if f["evals_fp32"] or f["fallback_rays"]:
+        e.update(fallback_fraction=f["fallback_rays"] / f["rays"], fp32_eval_fraction=f["evals_fp32"] / max(1, f["evals"]))
+    e.update(extra or {})
+    return e
+
+
+def run_mixed_sweep(K, torch, W, steps):
+    """The precision forms on the headline image: FP64 over a grid of
+    tolerances between 1e-12 and 1e-11 (the loosest whose p99.9 |H|_rel is
+    within 1e-10 is the equal-accuracy FP64 line), and the mixed form over
+    r_switch in {20, 50, 100, 300}M at budget 1e-10 and without re-run, plus
+    one looser budget.  Each form states its error per output against the
+    FP64 oracle's whole image under the parity rules' value mask."""
+    import numpy as np
+    params = W.kerr_ring(0.9, n=1024, rtol=1e-12)
+    nx = ny = 1024
+    o_full, _ = oracle_image(params, threads=_threads()[0])
+
+    def vs_oracle(out):
+        return error_vs_oracle(out, o_full, nx, ny, ("deflection", "psi"))
+
+    res = {"rtol_grid": {}, "mixed": {}}
+    best = None
+    for rtol in np.geomspace(1e-12, 1e-11, 8):
+        f = run_form(K, torch, dict(params, rtol=float(rtol), atol=float(rtol)), steps, 1)
+        res["rtol_grid"][f"{rtol:.3e}"] = form_entry(f, {"error_vs_fp64_oracle": vs_oracle(f["out"])})
+        if f["p999_rel_h"] <= 1e-10:
+            best = float(rtol)
+    res["rtol_equal_accuracy"] = best
+    for r_switch in (20.0, 50.0, 100.0, 300.0):
+        for budget, tag in ((1e-10, "budget1e-10"), (1e300, "no_rerun")):
+            f = run_form(K, torch, dict(params, precision=K.MIXED, h_budget=budget, r_switch=r_switch), steps, 1)
+            res["mixed"][f"r_switch{r_switch:g}_{tag}"] = form_entry(f, {"error_vs_fp64_oracle": vs_oracle(f["out"])})
+    for budget in (1e-9,):
+        f = run_form(K, torch, dict(params, precision=K.MIXED, h_budget=budget, r_switch=MIXED_R_SWITCH), steps, 1)
+        res["mixed"][f"r_switch{MIXED_R_SWITCH:g}_budget{budget:g}"] = form_entry(
+            f, {"error_vs_fp64_oracle": vs_oracle(f["out"])})
+    return res
+
+
+def run_cpu_legs(K, torch, W, steps):
+    """The oracle on the host cores beyond the default line: the 2048^2
+    Schwarzschild disk in full, and a fixed 1% sample of every image of the
+    256-image batch (extrapolated to the whole batch)."""
+    import numpy as np
+    threads, _ = _threads()
+    res = {"threads": threads, "cpu": host_cpu()}
+    pd = W.schwarzschild_disk(n=2048)
+    _, dt = oracle_image(pd, threads=threads)
+    res["schwarzschild_disk_2048_whole"] = {"rays": 2048 * 2048, "s": dt, "rays_per_s": 2048 * 2048 / dt}
+    images, integ = W.heterogeneous_batch()
+    rng = np.random.default_rng(1)
+    tot = n_all = 0
+    t_all = 0.0
+    for im in images:
+        n = im["nx"] * im["ny"]
+        pix = np.sort(rng.choice(n, size=max(1, n // 100), replace=False)).astype(np.int32)
+        _, dt = oracle_image(W.image_params(im, integ), pix, threads=threads)
+        t_all += dt
+        tot += pix.size
+        n_all += n
+    res["heterogeneous_batch_1pct"] = {"rays": tot, "s": t_all, "rays_per_s": tot / t_all,
+                                       "whole_batch_s_extrapolated": t_all * n_all / tot, "batch_rays": n_all}
     return res
 
 
@@ -327,16 +526,20 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (three times), "
                          "to calibrate HBM byte counters")
-    ap.add_argument("--only", choices=("batch", "adjoint", "images", "integrators"), default=None,
+    ap.add_argument("--only", choices=("batch", "adjoint", "images", "integrators", "mixed", "cpu"), default=None,
                     help="run one extra form alone and print its JSON (for profiling); no headline line")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported: this build measures one GPU (rays are "
+              "independent, so more GPUs would each trace a share of the pixels)", file=sys.stderr)
+        sys.exit(2)
     if args.only:
         import torch
 
         from paper_2202_00086_amd import kerrtrace as K
         from paper_2202_00086_amd import workloads as W
         run = {"batch": run_batch_forms, "adjoint": run_adjoint_form, "images": run_f4_forms,
-               "integrators": run_scheme_forms}[args.only]
+               "integrators": run_scheme_forms, "mixed": run_mixed_sweep, "cpu": run_cpu_legs}[args.only]
         print(json.dumps({args.only: run(K, torch, W, max(1, args.steps))}), flush=True)
         return
     if args.copy_calibration:
@@ -349,10 +552,6 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": n, "copies": 3}), flush=True)
         return
-    if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported: the ray tracer runs on one GPU "
-              "(rays are independent; see the sharding notes in the design document)", file=sys.stderr)
-        sys.exit(2)
 
     import torch
 
@@ -365,52 +564,55 @@ def main():
     rays_per_s = main_form["rays"] / secs
     evals_per_s = main_form["evals"] / secs
 
-    fpe = flop_per_eval(src_on=True)
-    flop = main_form["evals"] * fpe
-    achieved = flop / (main_form["launch_ms"] / 1e3)
+    st = K.read_stats(main_form["out"])
+    flop = launch_flop(st, main_form["steps_accepted"], src_on=True)
+    launch_s = main_form["launch_ms"] / 1e3
+    achieved = flop / launch_s
     traffic = traffic_from_profile()
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
-                "flop_per_eval": fpe, "evals_per_launch": main_form["evals"],
+                "flop_per_launch": flop, "flop_per_eval": flop / main_form["evals"],
+                "flop_basis": "counted: Carter-form reference per unit x the launch's evaluations, attempts "
+                              "and accepted steps",
+                "frac_other_bases": {
+                    "hand_count_117.3_per_eval": main_form["evals"] * FLOP_PER_EVAL_HAND_COUNT / launch_s / PEAK_FP64_VECTOR,
+                    "survey_estimate_150_per_eval": main_form["evals"] * FLOP_PER_EVAL_SURVEY_ESTIMATE / launch_s / PEAK_FP64_VECTOR},
+                "evals_per_launch": main_form["evals"], "steps_accepted_per_launch": main_form["steps_accepted"],
                 "launch_ms": main_form["launch_ms"]}
+
+    cb = o_full = None
+    if not args.no_cpu:
+        cb, o_full = cpu_baseline(params, main_form["out"])
 
     forms = {}
     if not args.no_forms:
         k = max(3, args.steps // 4)
-        p11 = W.kerr_ring(0.9, n=1024, rtol=1e-11)
-        f = run_form(K, torch, p11, k, 1)
-        forms["fp64_rtol1e-11"] = {"rays_per_s": f["rays"] / (f["ms_per_step"] / 1e3),
-                                   "stage_evals_per_s": f["evals"] / (f["ms_per_step"] / 1e3),
-                                   "ms_per_step": f["ms_per_step"], "max_rel_h": f["max_rel_h"],
-                                   "p999_rel_h": f["p999_rel_h"],
-                                   "error_vs_fp64_rtol1e-12": error_vs(torch, f["out"], main_form["out"])}
+        nx = ny = 1024
+
+        def vs_oracle(out):
+            return error_vs_oracle(out, o_full, nx, ny, ("deflection", "psi")) if o_full is not None else None
+        for rtol, name in ((1e-11, "fp64_rtol1e-11"), (RTOL_EQUAL_ACCURACY, "fp64_equal_accuracy")):
+            if rtol is None:
+                continue
+            f = run_form(K, torch, dict(params, rtol=rtol, atol=rtol), k, 1)
+            forms[name] = form_entry(f, {"rtol": rtol, "error_vs_fp64_rtol1e-12": error_vs(torch, f["out"], main_form["out"]),
+                                         "error_vs_fp64_oracle": vs_oracle(f["out"])})
         for budget, name in ((1e-10, "mixed_budget1e-10"), (1e300, "mixed_no_fallback")):
-            pm = dict(params, precision=K.MIXED, h_budget=budget, r_switch=300.0)
+            pm = dict(params, precision=K.MIXED, h_budget=budget, r_switch=MIXED_R_SWITCH)
             f = run_form(K, torch, pm, k, 1)
-            forms[name] = {"rays_per_s": f["rays"] / (f["ms_per_step"] / 1e3),
-                           "stage_evals_per_s": f["evals"] / (f["ms_per_step"] / 1e3),
-                           "ms_per_step": f["ms_per_step"], "r_switch": 300.0, "h_budget": budget,
-                           "fallback_fraction": f["fallback_rays"] / f["rays"],
-                           "fp32_eval_fraction": f["evals_fp32"] / max(1, f["evals"]),
-                           "max_rel_h": f["max_rel_h"], "p999_rel_h": f["p999_rel_h"],
-                           "error_vs_fp64": error_vs(torch, f["out"], main_form["out"])}
+            forms[name] = form_entry(f, {"r_switch": MIXED_R_SWITCH, "h_budget": budget,
+                                         "error_vs_fp64": error_vs(torch, f["out"], main_form["out"]),
+                                         "error_vs_fp64_oracle": vs_oracle(f["out"])})
 
         # the 2048^2 Schwarzschild disk: FP64 against the mixed form, with the
         # mixed form's error per output
         pd = W.schwarzschild_disk(n=2048)
         fd = run_form(K, torch, pd, k, 1)
-        forms["disk_2048_fp64"] = {"rays_per_s": fd["rays"] / (fd["ms_per_step"] / 1e3),
-                                   "stage_evals_per_s": fd["evals"] / (fd["ms_per_step"] / 1e3),
-                                   "ms_per_step": fd["ms_per_step"], "max_rel_h": fd["max_rel_h"],
-                                   "fates": fd["fates"]}
-        fm = run_form(K, torch, dict(pd, precision=K.MIXED, h_budget=1e-10, r_switch=300.0), k, 1)
-        forms["disk_2048_mixed_budget1e-10"] = {
-            "rays_per_s": fm["rays"] / (fm["ms_per_step"] / 1e3),
-            "stage_evals_per_s": fm["evals"] / (fm["ms_per_step"] / 1e3),
-            "ms_per_step": fm["ms_per_step"], "r_switch": 300.0, "h_budget": 1e-10,
-            "fallback_fraction": fm["fallback_rays"] / fm["rays"],
-            "fp32_eval_fraction": fm["evals_fp32"] / max(1, fm["evals"]), "max_rel_h": fm["max_rel_h"],
-            "error_vs_fp64": error_vs(torch, fm["out"], fd["out"], keys=("r_hit", "g", "intensity"))}
+        forms["disk_2048_fp64"] = form_entry(fd, {"fates": fd["fates"]})
+        fm = run_form(K, torch, dict(pd, precision=K.MIXED, h_budget=1e-10, r_switch=MIXED_R_SWITCH), k, 1)
+        forms["disk_2048_mixed_budget1e-10"] = form_entry(fm, {
+            "r_switch": MIXED_R_SWITCH, "h_budget": 1e-10,
+            "error_vs_fp64": error_vs(torch, fm["out"], fd["out"], keys=("r_hit", "g", "intensity"))})
         del fd, fm
 
     batch = schemes = adjoint = images = None
@@ -428,9 +630,10 @@ def main():
                       "rays": main_form["rays"], "precision": "fp64", "integrator": "dp45"},
            "stage_evals_per_s": evals_per_s, "evals_per_ray": main_form["evals"] / main_form["rays"],
            "max_rel_h": main_form["max_rel_h"], "p999_rel_h": main_form["p999_rel_h"],
+           "rays_over_1e-10": main_form["rays_over_1e-10"],
            "fates": main_form["fates"], "roofline": roofline,
-           "form_note": "value is the FP64 form that meets max |H|_rel <= 1e-10; the FP64 "
-                        "rtol 1e-11 and mixed-precision forms are in 'forms'",
+           "form_note": "value is the FP64 form at rtol 1e-12; the other FP64 tolerances and the mixed-precision "
+                        "forms are in 'forms'",
            "kernel_source_sha256": kernel_source_hash(),
            "paper_context": {"value": 1e3, "unit": "rays/s", "kind": "order of magnitude, not a target",
                              "note": "the paper states that its serial Fortran code traces 1024^2 geodesics in "
@@ -447,8 +650,7 @@ def main():
         out["adjoint"] = adjoint
     if images:
         out["images"] = images
-    if not args.no_cpu:
-        cb = cpu_baseline(params)
+    if cb is not None:
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
