@@ -144,8 +144,10 @@ __device__ __forceinline__ RayConst make_ray_const(const Spacetime& st, double E
 // By-products of an RHS evaluation used at accepted states.
 struct Diag {
     double H;       // Hamiltonian
-    double rel;     // |2 Sigma H| / (sum of |terms| of 2 Sigma H)
+    double Kabs;    // |2 Sigma H| (|2H| for the q-metric)
+    double D;       // the sum of the magnitudes of its terms: |H|_rel = Kabs / D
     double s, c;    // sin, cos of theta
+    __device__ double rel() const { return Kabs * rcp(D); }
 };
 
 // ---------------------------------------------------------------------------
@@ -206,7 +208,8 @@ __device__ __forceinline__ void rhs_sc(const Spacetime& st, const RayConst& rc, 
     if (WANT_DIAG) {
         const double D = fma(Del, pr2, fma(pth, pth, fma(T, T, WWd)));
         dg->H = 0.5 * H2;
-        dg->rel = fabs(K) * rcp(D);
+        dg->Kabs = fabs(K);
+        dg->D = D;
         dg->s = s;
         dg->c = c;
     }
@@ -351,7 +354,8 @@ __device__ __forceinline__ void rhs_q(const QSpacetime& st, const RayConst& rc, 
     if (WANT_DIAG) {
         const double K = (tA - tG) + (tB + tC);
         dg->H = 0.5 * K;
-        dg->rel = fabs(K) * rcp(tG + tA + tB + tC);
+        dg->Kabs = fabs(K);
+        dg->D = tG + tA + tB + tC;
         dg->s = s;
         dg->c = c;
     }
@@ -478,7 +482,8 @@ __device__ __forceinline__ void rhs_split(const Spacetime& st, const Spacetime32
         const double K = fma(Del, pr2, fma(pth, pth, fma(T, T, -WWd)));
         const double D = fma(Del, pr2, fma(pth, pth, fma(T, T, WWd)));
         dg->H = 0.5 * K * inv_Sig;
-        dg->rel = fabs(K) * rcp(D);
+        dg->Kabs = fabs(K);
+        dg->D = D;
         dg->s = s;
         dg->c = c;
     }

@@ -171,11 +171,17 @@ __device__ __forceinline__ void take_step(const ST& st, const RayConst& rc, cons
     }
 }
 
-template <int METHOD, int PREC, bool BATCH, bool QMET = false>
+// FEAT >= 0 fixes the image's features (FEAT_* bits) at compile time, so the
+// event tests of absent features vanish from the step loop; FEAT_DYN reads
+// them from the launch (single images) or the lane's image (batches).
+constexpr int FEAT_DYN = -1;
+
+template <int METHOD, int PREC, bool BATCH, bool QMET = false, int FEAT = FEAT_DYN>
 __global__ void __launch_bounds__(BLOCK_MAX) __attribute__((amdgpu_waves_per_eu(KT_WAVES_PER_EU)))
 trace_kernel(const Hot hp) {
     static_assert(!(QMET && (BATCH || METHOD == KT_RK4_S || PREC != KT_FP64)),
                   "the q-metric runs single images with the adaptive FP64 schemes");
+    static_assert(FEAT == FEAT_DYN || !BATCH, "batches read each image's features");
     constexpr int EVALS_PER_STEP = evals_per_step<METHOD>();
     constexpr bool ADAPTIVE = (METHOD != KT_RK4_S);
     constexpr bool S_TIME = (METHOD == KT_RK4_S);
@@ -285,7 +291,7 @@ trace_kernel(const Hot hp) {
             rhs<true, S_TIME>(st, rc, y, k1, &dg);
             nevals = 1;
             COLD(C_MAXABS) = fabs(dg.H);
-            COLD(C_MAXREL) = dg.rel;
+            COLD(C_MAXREL) = dg.rel();
             COLD(C_LAM) = 0.0;
             COLD(C_PSI) = 0.0;
             COLD(C_CS) = dg.s;
@@ -426,12 +432,16 @@ trace_kernel(const Hot hp) {
                     if (!(fl & F_RETAKE)) {
                         ++nsteps;
                         COLD(C_MAXABS) = fmax(COLD(C_MAXABS), fabs(dg.H));
-                        COLD(C_MAXREL) = fmax(COLD(C_MAXREL), dg.rel);
+                        // |H|_rel = Kabs / D: the quotient is taken only when
+                        // it raises the running maximum (Kabs > max D)
+                        const double mr = COLD(C_MAXREL);
+                        if (dg.Kabs > mr * dg.D) COLD(C_MAXREL) = dg.rel();
                     }
                     fl &= ~F_RETAKE;
                     bool locate = false;
                     // thin disk: sign change of theta - pi/2 over the step
-                    if ((li.feat & FEAT_DISK) && !(fl & F_SKIPDISK)) {
+                    const int32_t feat = FEAT >= 0 ? FEAT : li.feat;
+                    if ((feat & FEAT_DISK) && !(fl & F_SKIPDISK)) {
                         const double ga = y[1] - HALF_PI, gb = yn[1] - HALF_PI;
                         if (ga * gb < 0.0) {
                             fl = (fl & ~(F_EVSRC | F_EV32 | (0xff << EVIT_SHIFT))) | F_LOCATE | (use32 ? F_EV32 : 0);
@@ -459,7 +469,7 @@ trace_kernel(const Hot hp) {
                             thf = yn[1];
                             phf = yn[2];
                         } else {
-                            if ((li.feat & FEAT_SRC) && !(fl & F_SRCDONE)) {
+                            if ((feat & FEAT_SRC) && !(fl & F_SRCDONE)) {
                                 if (y[0] < li.r_src && yn[0] >= li.r_src) {
                                     const double fa = y[0] - li.r_src, fb = yn[0] - li.r_src;
                                     fl = (fl & ~(F_EV32 | (0xff << EVIT_SHIFT))) | F_EVSRC | F_LOCATE | (use32 ? F_EV32 : 0);
@@ -477,7 +487,7 @@ trace_kernel(const Hot hp) {
                                 }
                             }
                             if (!locate) {
-                                if (yn[0] > li.r_esc && (li.feat & FEAT_SKY)) {
+                                if (yn[0] > li.r_esc && (feat & FEAT_SKY)) {
                                     // locate the crossing of the celestial sphere
                                     const double fa = y[0] - li.r_esc, fb = yn[0] - li.r_esc;
                                     fl = (fl & ~(F_EVSRC | F_EV32 | (0xff << EVIT_SHIFT))) | F_EVESC | F_LOCATE | (use32 ? F_EV32 : 0);
@@ -867,12 +877,33 @@ static Hot make_hot(const Params& p) {
     return hp;
 }
 
+// The single-image Dormand-Prince FP64 kernel with the image's features
+// fixed at compile time (every other form reads them at run time).
+template <int FEAT>
+static void launch_dp45_feat(const Hot& hp, int grid, int block, hipStream_t s) {
+    hipLaunchKernelGGL((trace_kernel<KT_DP45, KT_FP64, false, false, FEAT>), dim3(grid), dim3(block), 0, s, hp);
+}
+
 template <int METHOD, int PREC>
 static void launch_variant(const Params& p, const Hot& hp, int grid, int block, hipStream_t s) {
     if constexpr (PREC == KT_FP64 && METHOD != KT_RK4_S) {
         if (p.img0.metric == KT_METRIC_Q) {
             hipLaunchKernelGGL((trace_kernel<METHOD, PREC, false, true>), dim3(grid), dim3(block), 0, s, hp);
             return;
+        }
+    }
+    if constexpr (METHOD == KT_DP45 && PREC == KT_FP64) {
+        if (p.n_images == 1) {
+            switch (hp.feat & 7) {
+            case 0: launch_dp45_feat<0>(hp, grid, block, s); return;
+            case 1: launch_dp45_feat<1>(hp, grid, block, s); return;
+            case 2: launch_dp45_feat<2>(hp, grid, block, s); return;
+            case 3: launch_dp45_feat<3>(hp, grid, block, s); return;
+            case 4: launch_dp45_feat<4>(hp, grid, block, s); return;
+            case 5: launch_dp45_feat<5>(hp, grid, block, s); return;
+            case 6: launch_dp45_feat<6>(hp, grid, block, s); return;
+            default: launch_dp45_feat<7>(hp, grid, block, s); return;
+            }
         }
     }
     if (p.n_images > 1)
