@@ -267,7 +267,7 @@ def run_scheme_forms(K, torch, W, steps):
     for wname, make in (("hamiltonian_norm_map_625", lambda m: W.hamiltonian_norm_map(625, method=m)),
                         ("kerr_ring_1024_a0.9", lambda m: dict(W.kerr_ring(0.9, n=1024, rtol=1e-12), method=m))):
         row = {}
-        for m in (K.DP45, K.RKF45, K.CK45, K.BS):
+        for m in (K.DP45, K.RKF45, K.CK45, K.BS, K.BS_RAT):
             r = K.Renderer(device="cuda:0", want=SCHEME_WANT, **make(m))
             r.render()
             t = _time(torch, r.render, steps)

@@ -59,7 +59,9 @@ extern "C" {
 #define KT_RKF45 2  /* Runge-Kutta-Fehlberg 4(5), adaptive, 4th order propagated (Sect. 3.1) */
 #define KT_CK45 3   /* Cash-Karp 5(4), adaptive, 5th order propagated (Sect. 3.1) */
 #define KT_BS 4     /* Bulirsch-Stoer: modified midpoint with 2, 4, .., 10 substeps,
-                       Aitken-Neville extrapolation (order 10), adaptive (Sect. 3.1) */
+                       Aitken-Neville (polynomial) extrapolation (order 10), adaptive (Sect. 3.1) */
+#define KT_BS_RAT 5 /* Bulirsch-Stoer as KT_BS with rational-function extrapolation
+                       (the Stoer-Bulirsch recursion, Sect. 3.1) */
 
 /* arithmetic of the RHS */
 #define KT_FP64 0
@@ -133,7 +135,7 @@ typedef struct kt_source {
 #define KT_SKY_LINE 5    /* on a graticule line */
 
 typedef struct kt_integrator {
-    int32_t method;         /* KT_RK4_S, KT_DP45, KT_RKF45, KT_CK45 or KT_BS */
+    int32_t method;         /* KT_RK4_S, KT_DP45, KT_RKF45, KT_CK45, KT_BS or KT_BS_RAT */
     int32_t precision;      /* KT_FP64 or KT_MIXED */
     double h_fixed;         /* RK4_S step in s, > 0 */
     double rtol, atol;      /* tolerances of the adaptive methods, > 0 */

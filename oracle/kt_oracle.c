@@ -403,18 +403,57 @@ static void erk6_step(const erk6_tableau *t, field_fn f, const void *ctx, int n,
     f(yn, kn, ctx);
 }
 
-/* Bulirsch-Stoer step: Gragg's modified midpoint rule over [0, h] with
-   n_k = 2k substeps (k = 1..BS_K), each chain started from y, then
-   Aitken-Neville polynomial extrapolation of the chain ends to zero substep
-   size in the variable (h/n_k)^2 (the midpoint rule's error expansion is
-   even in the substep for even n_k).  The step returns the last diagonal
-   entry T[K][K] (order 2K) and e = T[K][K] - T[K][K-1].  Evaluations:
-   n_k - 1 per chain (k1 = f(y) starts every chain) plus f at the result
-   for the next step: BS_K^2 + 1. */
-static void bs_step(field_fn f, const void *ctx, int n, const double *y, const double *k1, double h,
-                    double *yn, double *kn, double *e)
+/* Extrapolation of chain ends to zero substep size.  Row k of the tableau
+   holds T[k][0] = f[k], the chain end with n_k = 2 (k + 1) substeps, and its
+   extrapolations T[k][j] (j = 1..k), each from T[k][j-1] and the row above.
+   With x_k = (1/n_k)^2 (the modified midpoint rule's error expansion is even
+   in the substep for even n_k), evaluated at x = 0:
+     polynomial (Aitken-Neville):
+       T[k][j] = T[k][j-1] + (T[k][j-1] - T[k-1][j-1]) / ((n_k/n_{k-j})^2 - 1);
+     rational (Stoer and Bulirsch's recursion for rational interpolation,
+     with T[k-1][-1] = 0):
+       d = T[k][j-1] - T[k-1][j-1],
+       T[k][j] = T[k][j-1] + d / ((n_k/n_{k-j})^2 (1 - d / (T[k][j-1] - T[k-1][j-2])) - 1).
+   Where a denominator of the rational form vanishes the entry is taken as
+   T[k][j-1] (no correction). */
+void ko_bs_extrapolate(int32_t rational, int32_t K, const double *f, double *row)
 {
-    double T[BS_K][BS_K][NMAX];
+    double T[8][8];
+    for (int k = 0; k < K; ++k) {
+        const double nk = 2 * (k + 1);
+        T[k][0] = f[k];
+        for (int j = 1; j <= k; ++j) {
+            const double nkj = 2 * (k - j + 1);
+            const double ratio = (nk * nk) / (nkj * nkj);
+            const double d = T[k][j - 1] - T[k - 1][j - 1];
+            if (!rational) {
+                T[k][j] = T[k][j - 1] + d / (ratio - 1.0);
+            } else {
+                const double below = j >= 2 ? T[k - 1][j - 2] : 0.0;
+                const double din = T[k][j - 1] - below;
+                double upd = 0.0;
+                if (din != 0.0) {
+                    const double den = ratio * (1.0 - d / din) - 1.0;
+                    if (den != 0.0) upd = d / den;
+                }
+                T[k][j] = T[k][j - 1] + upd;
+            }
+        }
+    }
+    for (int j = 0; j < K; ++j) row[j] = T[K - 1][j];
+}
+
+/* Bulirsch-Stoer step: Gragg's modified midpoint rule over [0, h] with
+   n_k = 2k substeps (k = 1..BS_K), each chain started from y, then the chain
+   ends extrapolated to zero substep size (ko_bs_extrapolate: polynomial, or
+   rational with `rational` set), component by component.  The step returns
+   the last diagonal entry T[K][K] (order 2K) and e = T[K][K] - T[K][K-1].
+   Evaluations: n_k - 1 per chain (k1 = f(y) starts every chain) plus f at
+   the result for the next step: BS_K^2 + 1. */
+static void bs_step(int rational, field_fn f, const void *ctx, int n, const double *y, const double *k1,
+                    double h, double *yn, double *kn, double *e)
+{
+    double ends[NMAX][BS_K];
     for (int k = 0; k < BS_K; ++k) {
         const int ns = 2 * (k + 1);
         const double hs = h / ns;
@@ -431,17 +470,13 @@ static void bs_step(field_fn f, const void *ctx, int n, const double *y, const d
                 zc[i] = znext;
             }
         }
-        for (int i = 0; i < n; ++i) T[k][0][i] = zc[i];
-        for (int j = 1; j <= k; ++j) {
-            const double nk = ns, nkj = 2 * (k - j + 1);
-            const double ratio = (nk * nk) / (nkj * nkj);
-            for (int i = 0; i < n; ++i)
-                T[k][j][i] = T[k][j - 1][i] + (T[k][j - 1][i] - T[k - 1][j - 1][i]) / (ratio - 1.0);
-        }
+        for (int i = 0; i < n; ++i) ends[i][k] = zc[i];
     }
     for (int i = 0; i < n; ++i) {
-        yn[i] = T[BS_K - 1][BS_K - 1][i];
-        e[i] = T[BS_K - 1][BS_K - 1][i] - T[BS_K - 1][BS_K - 2][i];
+        double row[BS_K];
+        ko_bs_extrapolate(rational, BS_K, ends[i], row);
+        yn[i] = row[BS_K - 1];
+        e[i] = row[BS_K - 1] - row[BS_K - 2];
     }
     f(yn, kn, ctx);
 }
@@ -478,7 +513,8 @@ static int step_any(int32_t method, field_fn f, const void *ctx, int n, const do
         erk6_step(&CK45, f, ctx, n, y, k1, h, yn, kn, e);
         return 6;
     case KO_BS:
-        bs_step(f, ctx, n, y, k1, h, yn, kn, e);
+    case KO_BS_RAT:
+        bs_step(method == KO_BS_RAT, f, ctx, n, y, k1, h, yn, kn, e);
         return BS_K * BS_K + 1;
     default:
         rk4_step(f, ctx, n, y, k1, h, yn, kn);
@@ -490,7 +526,7 @@ static int step_any(int32_t method, field_fn f, const void *ctx, int n, const do
 /* Exponent of the step-size controller: 1 / (order of the error estimate + 1). */
 static double controller_exponent(int32_t method)
 {
-    return method == KO_BS ? 1.0 / (2 * BS_K - 1) : 1.0 / 5;
+    return (method == KO_BS || method == KO_BS_RAT) ? 1.0 / (2 * BS_K - 1) : 1.0 / 5;
 }
 
 static void harmonic_field(const double *y, double *dy, const void *ctx)

@@ -41,7 +41,8 @@ extern "C" {
 #define KO_DP45 1  /* Dormand-Prince 5(4), adaptive, FSAL */
 #define KO_RKF45 2 /* Runge-Kutta-Fehlberg 4(5), adaptive, 4th order propagated */
 #define KO_CK45 3  /* Cash-Karp 5(4), adaptive, 5th order propagated */
-#define KO_BS 4    /* Bulirsch-Stoer: modified midpoint n = 2,4,..,10, extrapolated (order 10) */
+#define KO_BS 4    /* Bulirsch-Stoer: modified midpoint n = 2,4,..,10, polynomial extrapolation (order 10) */
+#define KO_BS_RAT 5 /* Bulirsch-Stoer with rational-function extrapolation (Bulirsch & Stoer 1966) */
 
 typedef struct {
     /* spacetime: Kerr (M, a) or the q-metric (M, q) */
@@ -200,6 +201,13 @@ int ko_one_step(int32_t method, int32_t problem, double h, const double *y0, dou
 /* The Butcher tableau of KO_RKF45 or KO_CK45: A row-major 6x6, the weights
    of the propagated and of the embedded solution. */
 void ko_tableau(int32_t method, double A[36], double b_prop[6], double b_emb[6]);
+
+/* Extrapolation of Bulirsch-Stoer chain ends to zero substep: f[k] is the
+   modified-midpoint value with n_k = 2 (k + 1) substeps, k = 0..K-1 (1 <= K
+   <= 8); writes the tableau's last row T[K-1][0..K-1] (its last entry is
+   the extrapolated value).  rational = 0: Aitken-Neville polynomials in
+   (1/n)^2; 1: Stoer-Bulirsch rational functions in (1/n)^2. */
+void ko_bs_extrapolate(int32_t rational, int32_t K, const double *f, double *row);
 
 #ifdef __cplusplus
 }

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("KT_ORACLE_LIB") or os.path.join(HERE, "libkt_oracle.so")
 
 ESCAPED, CAPTURED, DISK, MAXSTEPS, STEPFAIL, INVALID = range(6)
-RK4_S, DP45, RKF45, CK45, BS = 0, 1, 2, 3, 4
+RK4_S, DP45, RKF45, CK45, BS, BS_RAT = 0, 1, 2, 3, 4, 5
 SKY_NONE, SKY_GREEN, SKY_RED, SKY_BLUE, SKY_YELLOW, SKY_LINE = range(6)
 KERR, QMETRIC = 0, 1
 BS_COLUMNS = 5
@@ -134,6 +134,7 @@ def lib():
         L.ko_one_step.argtypes = [C.c_int32, C.c_int32, C.c_double, dp, dp, dp]
         L.ko_one_step.restype = C.c_int
         L.ko_tableau.argtypes = [C.c_int32, dp, dp, dp]
+        L.ko_bs_extrapolate.argtypes = [C.c_int32, C.c_int32, dp, dp]
         L.ko_sky_code.argtypes = [C.c_double] * 4
         L.ko_sky_code.restype = C.c_int
         L.ko_disk_omega.argtypes = [C.c_double] * 3 + [C.c_int32, C.c_double]
@@ -332,3 +333,13 @@ def tableau(method):
     A, bp, be = np.zeros(36), np.zeros(6), np.zeros(6)
     lib().ko_tableau(method, _dptr(A), _dptr(bp), _dptr(be))
     return A.reshape(6, 6), bp, be
+
+
+def bs_extrapolate(values, rational=False):
+    """Last tableau row of the Bulirsch-Stoer extrapolation of chain ends
+    values[k] (n_k = 2 (k + 1) substeps) to zero substep; row[-1] is the
+    extrapolated value."""
+    f = np.ascontiguousarray(values, dtype=np.float64)
+    row = np.zeros(f.size)
+    lib().ko_bs_extrapolate(1 if rational else 0, f.size, _dptr(f), _dptr(row))
+    return row

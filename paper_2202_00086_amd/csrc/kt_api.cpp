@@ -178,7 +178,7 @@ void camera_constant_derivs(const kt_camera* cam, const kt_spacetime* st, double
 }
 
 int validate_integ(const kt_integrator* integ) {
-    if (integ->method < KT_RK4_S || integ->method > KT_BS)
+    if (integ->method < KT_RK4_S || integ->method > KT_BS_RAT)
         return fail(KT_EINVAL, "unknown integrator method %d", integ->method);
     if (integ->precision != KT_FP64 && integ->precision != KT_MIXED)
         return fail(KT_EINVAL, "unknown precision %d", integ->precision);

@@ -661,21 +661,26 @@ __device__ __forceinline__ void erk6_step(const ST& st, const RayConst& rc, cons
 // Bulirsch-Stoer extrapolation (the third scheme of Sect. 3.1).  For
 // k = 1..BS_COLUMNS the modified midpoint chain with n_k = 2k substeps
 // across [0, h] starts from y; its end is extrapolated to zero substep size
-// with the earlier chains' ends by Aitken-Neville in (h/n_k)^2, one tableau
-// row at a time kept in place.  The last diagonal entry (order 2K) is the
-// step's result; the error vector is its difference to the entry before it.
-// Chains span the whole step, so every evaluation takes sin/cos of theta
-// from theta itself.  K^2 + 1 RHS evaluations.
+// with the earlier chains' ends, in x = (1/n_k)^2, one tableau row at a time
+// kept in place: by Aitken-Neville polynomials, or (RATIONAL) by Stoer and
+// Bulirsch's recursion for rational functions,
+//   T[k][j] = T[k][j-1] + d / (rho (1 - d / (T[k][j-1] - T[k-1][j-2])) - 1),
+//   d = T[k][j-1] - T[k-1][j-1],  rho = (n_k / n_(k-j))^2,  T[k-1][-1] = 0,
+// with no correction where a denominator vanishes.  The last diagonal entry
+// (order 2K) is the step's result; the error vector is its difference to the
+// entry before it.  Chains span the whole step, so every evaluation takes
+// sin/cos of theta from theta itself.  K^2 + 1 RHS evaluations.
 // ---------------------------------------------------------------------------
 constexpr int BS_COLUMNS = 5;
 
-// 1 / ((n_k / n_(k-j))^2 - 1) with n = 2k, k = 1..BS_COLUMNS (as indices k, j
-// from 0): the Aitken-Neville weights.
-constexpr double bs_weight(int k, int j) {
-    return 1.0 / (static_cast<double>((k + 1) * (k + 1)) / static_cast<double>((k - j + 1) * (k - j + 1)) - 1.0);
+// (n_k / n_(k-j))^2 with n = 2k, k = 1..BS_COLUMNS (as indices k, j from 0),
+// and the Aitken-Neville weight 1 / (that - 1).
+constexpr double bs_ratio2(int k, int j) {
+    return static_cast<double>((k + 1) * (k + 1)) / static_cast<double>((k - j + 1) * (k - j + 1));
 }
+constexpr double bs_weight(int k, int j) { return 1.0 / (bs_ratio2(k, j) - 1.0); }
 
-template <class ST>
+template <bool RATIONAL = false, class ST>
 __device__ __forceinline__ void bs_step(const ST& st, const RayConst& rc, const double y[5],
                                         const double k1[5], double h, double yn[5], double kn[5],
                                         double err[5], Diag* dg) {
@@ -702,15 +707,26 @@ __device__ __forceinline__ void bs_step(const ST& st, const RayConst& rc, const 
                 zc[i] = zn;
             }
         }
-        // Aitken-Neville: T[k][j] = T[k][j-1] + (T[k][j-1] - T[k-1][j-1]) w(k, j)
+        // row k from row k - 1, in place: `carry` is T[k][j-1], `below` the
+        // overwritten T[k-1][j-2]
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
             double carry = zc[i];
+            double below = 0.0;
 #pragma unroll
             for (int j = 1; j <= k; ++j) {
                 const double old = T[j - 1][i];
                 T[j - 1][i] = carry;
-                carry = fma(carry - old, bs_weight(k, j), carry);
+                const double d = carry - old;
+                if constexpr (RATIONAL) {
+                    const double din = carry - below;
+                    const double den = fma(bs_ratio2(k, j), fma(-d, rcp(din), 1.0), -1.0);
+                    const double upd = d * rcp(den);
+                    carry = (din != 0.0 && den != 0.0) ? carry + upd : carry;
+                    below = old;
+                } else {
+                    carry = fma(d, bs_weight(k, j), carry);
+                }
             }
             T[k][i] = carry;
         }

@@ -42,11 +42,11 @@ __device__ __forceinline__ bool camera_state(const Image& im, int32_t pix, doubl
 // 2K - 2 for Bulirsch-Stoer with K columns).
 template <int METHOD>
 constexpr int evals_per_step() {
-    return METHOD == KT_RK4_S ? 4 : METHOD == KT_BS ? BS_COLUMNS * BS_COLUMNS + 1 : 6;
+    return METHOD == KT_RK4_S ? 4 : (METHOD == KT_BS || METHOD == KT_BS_RAT) ? BS_COLUMNS * BS_COLUMNS + 1 : 6;
 }
 template <int METHOD>
 constexpr float controller_exponent() {
-    return METHOD == KT_BS ? 1.0f / (2 * BS_COLUMNS - 1) : 0.2f;
+    return (METHOD == KT_BS || METHOD == KT_BS_RAT) ? 1.0f / (2 * BS_COLUMNS - 1) : 0.2f;
 }
 
 // Whether the step-size control runs entirely in FP64.  For the Runge-Kutta
@@ -58,7 +58,7 @@ constexpr float controller_exponent() {
 // FP64 clamps.
 template <int METHOD>
 constexpr bool fp64_control() {
-    return METHOD == KT_BS;
+    return METHOD == KT_BS || METHOD == KT_BS_RAT;
 }
 
 // Step-size factor 0.9 err^(-1/(q+1)) from the mean-square error msq = err^2,
@@ -73,7 +73,7 @@ __device__ __forceinline__ float step_factor(double msq) {
 // own logarithm and exponential (about an ulp each).
 template <int METHOD>
 __device__ __forceinline__ double step_factor64(double msq) {
-    constexpr double x = -0.5 / (METHOD == KT_BS ? 2 * BS_COLUMNS - 1 : 5);
+    constexpr double x = -0.5 / ((METHOD == KT_BS || METHOD == KT_BS_RAT) ? 2 * BS_COLUMNS - 1 : 5);
     return 0.9 * exp_fast(x * log_fast(msq));
 }
 

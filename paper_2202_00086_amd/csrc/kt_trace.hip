@@ -163,7 +163,9 @@ __device__ __forceinline__ void take_step(const ST& st, const RayConst& rc, cons
     } else if constexpr (METHOD == KT_CK45) {
         erk6_step<CashKarp45>(st, rc, y, k1, s0, c0, h, yn, kn, er, dg);
     } else if constexpr (METHOD == KT_BS) {
-        bs_step(st, rc, y, k1, h, yn, kn, er, dg);
+        bs_step<false>(st, rc, y, k1, h, yn, kn, er, dg);
+    } else if constexpr (METHOD == KT_BS_RAT) {
+        bs_step<true>(st, rc, y, k1, h, yn, kn, er, dg);
     } else {
         rk4s_step(st, rc, y, k1, h, yn, kn, dg);
 #pragma unroll
@@ -925,6 +927,7 @@ int launch_trace(const Params& p, int grid, int block, void* stream) {
     case KT_RKF45: launch_variant<KT_RKF45, KT_FP64>(p, hp, grid, block, s); break;
     case KT_CK45: launch_variant<KT_CK45, KT_FP64>(p, hp, grid, block, s); break;
     case KT_BS: launch_variant<KT_BS, KT_FP64>(p, hp, grid, block, s); break;
+    case KT_BS_RAT: launch_variant<KT_BS_RAT, KT_FP64>(p, hp, grid, block, s); break;
     default: launch_variant<KT_RK4_S, KT_FP64>(p, hp, grid, block, s); break;
     }
     return check_launch();
@@ -967,6 +970,7 @@ int trace_max_blocks_per_cu(const Params& p, int block) {
     case KT_RKF45: e = occupancy_variant<KT_RKF45, KT_FP64>(p, &nb, block); break;
     case KT_CK45: e = occupancy_variant<KT_CK45, KT_FP64>(p, &nb, block); break;
     case KT_BS: e = occupancy_variant<KT_BS, KT_FP64>(p, &nb, block); break;
+    case KT_BS_RAT: e = occupancy_variant<KT_BS_RAT, KT_FP64>(p, &nb, block); break;
     default: e = occupancy_variant<KT_RK4_S, KT_FP64>(p, &nb, block); break;
     }
     return (e == hipSuccess && nb > 0) ? nb : 1;

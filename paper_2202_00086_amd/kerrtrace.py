@@ -22,8 +22,8 @@ LIB_PATH = os.environ.get("KERRTRACE_LIB") or os.path.join(HERE, "libkerrtrace.s
 
 KT_OK, KT_EINVAL, KT_EDEVICE, KT_ENOMEM = 0, -1, -2, -3
 ESCAPED, CAPTURED, DISK, MAXSTEPS, STEPFAIL, INVALID = range(6)
-RK4_S, DP45, RKF45, CK45, BS = 0, 1, 2, 3, 4
-METHOD_NAMES = {RK4_S: "rk4_s", DP45: "dp45", RKF45: "rkf45", CK45: "ck45", BS: "bs"}
+RK4_S, DP45, RKF45, CK45, BS, BS_RAT = 0, 1, 2, 3, 4, 5
+METHOD_NAMES = {RK4_S: "rk4_s", DP45: "dp45", RKF45: "rkf45", CK45: "ck45", BS: "bs", BS_RAT: "bs_rat"}
 FP64, MIXED = 0, 1
 
 if not os.path.exists(LIB_PATH):

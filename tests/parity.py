@@ -197,11 +197,13 @@ def check_values_rounding(gpu, ora, key, mask, sens, rtol=1e-8):
     differences far (Bulirsch-Stoer's step control: its error estimate is a
     difference of two extrapolated values that agree to the tolerance, so
     rounding changes it at the 1e-5 level and with it the step sequence).
-    The tolerance follows from the oracle's own behaviour: max(rtol, 10x the
-    largest one-ulp sensitivity over the compared pixels), and at most
-    3x the oracle's own share of pixels above rtol (plus two pixels) may
-    exceed rtol.  For schemes whose sensitivity is at rounding level this is
-    the plain rtol check."""
+    The tolerance follows from the oracle's own behaviour, sens being its
+    per-pixel one-ulp sensitivity (four nudges: a sample, which can miss a
+    pixel's sensitivity): each pixel within max(rtol, 10 S, 2 sens), S the
+    99.9th percentile of the image's sensitivities, and at most 3x the
+    oracle's own count of pixels above rtol (plus two) above rtol.  For
+    schemes whose sensitivity is at rounding level this is the plain rtol
+    check.  Returns (max error, S)."""
     a = np.asarray(gpu[key])[mask]
     b = np.asarray(ora[key])[mask]
     s = np.asarray(sens)[mask]
@@ -212,8 +214,11 @@ def check_values_rounding(gpu, ora, key, mask, sens, rtol=1e-8):
     s = s[keep]
     if not e.size:
         return 0.0, 0.0
-    tol = max(rtol, 10.0 * float(s.max()))
-    assert e.max() <= tol, f"{key}: max rel err {e.max():.3e} > {tol:.1e} (largest 1-ulp sensitivity {s.max():.2e})"
+    S = float(np.quantile(s, 0.999))
+    tol = np.maximum(max(rtol, 10.0 * S), 2.0 * s)
+    bad = e > tol
+    assert not bad.any(), (f"{key}: {bad.sum()} pixels beyond their rounding tolerance, worst rel err "
+                           f"{e[bad].max():.3e} (own sensitivity {s[bad][np.argmax(e[bad])]:.2e}, image p99.9 {S:.2e})")
     n_over, n_own = int((e > rtol).sum()), int((s > rtol).sum())
     assert n_over <= 3 * n_own + 2, f"{key}: {n_over} pixels above {rtol:.0e}, oracle's own {n_own}"
-    return float(e.max()), float(s.max())
+    return float(e.max()), S

@@ -67,7 +67,7 @@ def test_qmetric_lensing_parity(K, q):
     print(f"[q-metric {q}] max direction difference {dmax:.2e}; fates {np.bincount(g['fate']).tolist()}", flush=True)
 
 
-@pytest.mark.parametrize("method", [2, 3, 4])
+@pytest.mark.parametrize("method", [2, 3, 4, 5])
 def test_qmetric_other_schemes(K, method):
     nx, ny = 32, 32
     params = dict(W.qmetric_lensing(q=0.5, n=nx, rtol=1e-11), method=method)

@@ -13,7 +13,7 @@ from tests import parity as P
 
 pytestmark = pytest.mark.gpu
 
-SCHEMES = [("rkf45", 2), ("ck45", 3), ("bs", 4)]
+SCHEMES = [("rkf45", 2), ("ck45", 3), ("bs", 4), ("bs_rat", 5)]
 
 
 def _announce(*what):
@@ -67,10 +67,11 @@ def test_scheme_kerr_ring_parity(K, name, method):
     print(f"[{name}] deflection max rel err {err:.2e} (1-ulp sensitivity {smax:.2e}), psi {err_psi:.2e}",
           flush=True)
     # every ray within the scheme's own level (the oracle's p99 at this
-    # tolerance is 2.5e-9, 3.4e-10 and 2.2e-11 for RKF45, CK45 and BS), and
+    # tolerance is 2.5e-9, 3.4e-10, 2.2e-11 and 3.2e-11 for RKF45, CK45 and BS
+    # with polynomial and rational extrapolation), and
     # the distributions' percentiles agree
-    P.check_max_h(g, o, "max_rel_h", m, budget={2: 1e-8, 3: 2e-9, 4: 2e-10}[method])
-    per = {2: 6, 3: 6, 4: O.BS_COLUMNS ** 2 + 1}[method]
+    P.check_max_h(g, o, "max_rel_h", m, budget={2: 1e-8, 3: 2e-9, 4: 2e-10, 5: 5e-10}[method])
+    per = {2: 6, 3: 6, 4: O.BS_COLUMNS ** 2 + 1, 5: O.BS_COLUMNS ** 2 + 1}[method]
     assert (g["n_evals"] >= per * g["n_steps"]).all()
     assert g["stats"].evals == g["n_evals"].astype(np.int64).sum()
 

@@ -62,7 +62,7 @@ def _rates(method, problem, T, ns):
 
 
 @pytest.mark.parametrize("method, order, ns", [(O.RKF45, 4, (16, 32, 64)), (O.CK45, 5, (8, 16, 32)),
-                                               (O.BS, 10, (1, 2, 3, 4))])
+                                               (O.BS, 10, (1, 2, 3, 4)), (O.BS_RAT, 10, (1, 2, 3, 4))])
 def test_fixed_step_convergence(method, order, ns):
     r, e = _rates(method, 0, 2.0, ns)
     assert all(abs(x - order) < 0.3 for x in r), (r, e)
@@ -70,7 +70,8 @@ def test_fixed_step_convergence(method, order, ns):
 
 @pytest.mark.parametrize("method, order, ns, tol", [(O.RKF45, 4, (32, 64, 128), 0.4),
                                                     (O.CK45, 5, (16, 32, 64), 0.4),
-                                                    (O.BS, 10, (5, 6, 7, 8), 0.6)])
+                                                    (O.BS, 10, (5, 6, 7, 8), 0.6),
+                                                    (O.BS_RAT, 10, (3, 4, 5, 6), 0.9)])
 def test_fixed_step_convergence_nonlinear(method, order, ns, tol):
     """y' = y^2 to t = 1/2 (y = 2); Bulirsch-Stoer approaches its order from
     below here (9.5 ... 9.8 before rounding takes over)."""
@@ -79,7 +80,8 @@ def test_fixed_step_convergence_nonlinear(method, order, ns, tol):
 
 
 @pytest.mark.parametrize("method, hs", [(O.RKF45, (0.2, 0.1, 0.05)), (O.CK45, (0.2, 0.1, 0.05)),
-                                        (O.DP45, (0.2, 0.1, 0.05)), (O.BS, (1.5, 1.0, 0.5))])
+                                        (O.DP45, (0.2, 0.1, 0.05)), (O.BS, (1.5, 1.0, 0.5)),
+                                        (O.BS_RAT, (1.5, 1.0, 0.5))])
 def test_error_estimate_is_the_local_error(method, hs):
     """e = y_prop - y_emb; the lower-order solution's true local error equals
     +-e to leading order, so the mismatch relative to |e| falls with h."""
@@ -98,11 +100,12 @@ def test_error_estimate_is_the_local_error(method, hs):
 
 
 def test_evaluations_per_step():
-    for m, n in [(O.DP45, 6), (O.RKF45, 6), (O.CK45, 6), (O.BS, O.BS_COLUMNS ** 2 + 1), (O.RK4_S, 4)]:
+    for m, n in [(O.DP45, 6), (O.RKF45, 6), (O.CK45, 6), (O.BS, O.BS_COLUMNS ** 2 + 1),
+                 (O.BS_RAT, O.BS_COLUMNS ** 2 + 1), (O.RK4_S, 4)]:
         assert O.one_step(m, 0, 0.1, [0.0, 1.0])[2] == n
 
 
-@pytest.mark.parametrize("method", [O.RKF45, O.CK45, O.BS])
+@pytest.mark.parametrize("method", [O.RKF45, O.CK45, O.BS, O.BS_RAT])
 @pytest.mark.parametrize("x,y", [(-2.0, 1.87), (-1.25, 3.75)])
 def test_caption_rays_invariants(method, x, y):
     """The caption rays (a = 0.98, r0 = 100) with each scheme at rtol 1e-12:
@@ -119,11 +122,11 @@ def test_caption_rays_invariants(method, x, y):
     Q0 = _carter_q(0.98, traj[0, 2], traj[0, 5], E, L)
     Q = np.array([_carter_q(0.98, t[2], t[5], E, L) for t in traj])
     assert np.abs(Q - Q0).max() < 1e-7 * max(1.0, abs(Q0))
-    per = O.BS_COLUMNS ** 2 + 1 if method == O.BS else 6
+    per = O.BS_COLUMNS ** 2 + 1 if method in (O.BS, O.BS_RAT) else 6
     assert res["n_evals"] >= per * res["n_steps"]
 
 
-@pytest.mark.parametrize("method", [O.RKF45, O.CK45, O.BS])
+@pytest.mark.parametrize("method", [O.RKF45, O.CK45, O.BS, O.BS_RAT])
 def test_kerr_fates_vs_radial_potential(method):
     """a = 0.9, i = 60 deg, r0 = 1000M, +-12M at 24x24: every pixel that is
     not near-critical has the fate the radial potential predicts."""
@@ -182,3 +185,65 @@ def test_bulirsch_stoer_step_sequence_carries_rounding():
                 assert np.all(np.abs(t1[j, 1:] - t2[j, 1:]) <= 1e-12 * (np.abs(t1[j, 1:]) + 1.0))
                 found = True
     assert found
+
+
+
+# ---------------------------------------------------------------------------
+# The extrapolation step itself (Sect. 3.1's Bulirsch-Stoer: Richardson
+# extrapolation of modified-midpoint chains to zero substep).  Data that is
+# exactly a polynomial, or a rational function, of x = (1/n)^2 of the degree
+# the tableau spans is extrapolated exactly by the matching form.
+# ---------------------------------------------------------------------------
+
+def _x(K):
+    return np.array([1.0 / (2 * (k + 1)) ** 2 for k in range(K)])
+
+
+def test_polynomial_extrapolation_is_exact_on_polynomials():
+    rng = np.random.default_rng(5)
+    for K in (2, 3, 5):
+        c = rng.uniform(-3, 3, K)           # degree K - 1 in x
+        x = _x(K)
+        f = sum(c[i] * x ** i for i in range(K))
+        row = O.bs_extrapolate(f)
+        assert row[-1] == pytest.approx(c[0], abs=2e-13)
+        assert row[0] == f[-1]
+
+
+@pytest.mark.parametrize("K, num, den", [(3, (1.0, 2.0), (1.0, 3.0)),
+                                         (5, (2.0, -1.5, 0.7), (1.0, 4.0, -2.5)),
+                                         (5, (0.5, 3.0, 1.0), (1.0, -0.8, 6.0))])
+def test_rational_extrapolation_is_exact_on_rational_functions(K, num, den):
+    """K points span a rational function of numerator and denominator degree
+    (K - 1)/2 each; its value at x = 0 is recovered exactly, where the
+    polynomial form is off."""
+    x = _x(K)
+    f = np.polyval(num[::-1], x) / np.polyval(den[::-1], x)
+    want = num[0] / den[0]
+    assert O.bs_extrapolate(f, rational=True)[-1] == pytest.approx(want, abs=1e-12)
+    assert abs(O.bs_extrapolate(f)[-1] - want) > 1e-9
+
+
+def test_rational_extrapolation_degenerate_denominators():
+    """Equal chain ends (a vanishing inner denominator) extrapolate to that
+    value; the two forms agree on constants."""
+    for f in (np.full(5, 2.5), np.zeros(5)):
+        assert O.bs_extrapolate(f, rational=True)[-1] == f[0]
+        assert O.bs_extrapolate(f)[-1] == f[0]
+
+
+def test_rational_and_polynomial_schemes_differ_but_agree_to_tolerance():
+    """On a caption ray the two extrapolations take different step sequences
+    and meet the celestial sphere (its crossing located) at the same place
+    to within the scheme's global error."""
+    res = {}
+    for m in (O.BS, O.BS_RAT):
+        s = O.Setup(a=0.98, r_obs=100.0, incl=math.pi / 2, method=m, rtol=1e-12, atol=1e-12, r_escape=1000.0,
+                    sky_on=1)
+        traj, r = O.trace_one(s, -1.25, 3.75)
+        res[m] = (traj, r)
+    assert res[O.BS][1]["n_steps"] != res[O.BS_RAT][1]["n_steps"] or \
+        not np.array_equal(res[O.BS][0][:, 0], res[O.BS_RAT][0][:, 0])
+    assert res[O.BS][1]["fate"] == res[O.BS_RAT][1]["fate"] == O.ESCAPED
+    for k in ("theta_f", "phi_f"):
+        assert res[O.BS][1][k] == pytest.approx(res[O.BS_RAT][1][k], rel=1e-7)
