@@ -516,6 +516,21 @@ def run_cpu_legs(K, torch, W, steps):
     return res
 
 
+def run_render(K, torch, W, steps, workload):
+    """One workload rendered `steps` times in the default launch (for
+    profiling a single kernel form)."""
+    if workload == "batch":
+        images, integ = W.heterogeneous_batch()
+        r = K.BatchRenderer(images, device="cuda:0", want=BATCH_WANT, **integ)
+    else:
+        params = {"ring": W.kerr_ring(0.9, n=1024), "disk": W.schwarzschild_disk(n=2048),
+                  "qmetric": W.qmetric_lensing(q=0.5, n=1024)}[workload]
+        r = K.Renderer(device="cuda:0", **params)
+    t = _time(torch, r.render, steps)
+    st = K.read_stats(r.out)
+    return {"workload": workload, "rays": r.n, "ms_per_render": 1e3 * t, "evals": int(st.evals)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -526,8 +541,10 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (three times), "
                          "to calibrate HBM byte counters")
-    ap.add_argument("--only", choices=("batch", "adjoint", "images", "integrators", "mixed", "cpu"), default=None,
-                    help="run one extra form alone and print its JSON (for profiling); no headline line")
+    ap.add_argument("--only", choices=("batch", "adjoint", "images", "integrators", "mixed", "cpu", "render"),
+                    default=None, help="run one extra form alone and print its JSON (for profiling); no headline line")
+    ap.add_argument("--workload", choices=("ring", "disk", "qmetric", "batch"), default="ring",
+                    help="with --only render: the workload rendered --steps times")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this build measures one GPU (rays are "
@@ -538,6 +555,9 @@ def main():
 
         from paper_2202_00086_amd import kerrtrace as K
         from paper_2202_00086_amd import workloads as W
+        if args.only == "render":
+            print(json.dumps({"render": run_render(K, torch, W, max(1, args.steps), args.workload)}), flush=True)
+            return
         run = {"batch": run_batch_forms, "adjoint": run_adjoint_form, "images": run_f4_forms,
                "integrators": run_scheme_forms, "mixed": run_mixed_sweep, "cpu": run_cpu_legs}[args.only]
         print(json.dumps({args.only: run(K, torch, W, max(1, args.steps))}), flush=True)
