@@ -98,6 +98,12 @@ def traffic_from_profile():
         return None
 
 
+def progress(msg):
+    """One line on stderr per finished piece of work, so a long run shows
+    where it is."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _threads():
     try:
         n_avail = len(os.sched_getaffinity(0))
@@ -476,6 +482,7 @@ def run_mixed_sweep(K, torch, W, steps):
     for rtol in np.geomspace(1e-12, 1e-11, 8):
         f = run_form(K, torch, dict(params, rtol=float(rtol), atol=float(rtol)), steps, 1)
         res["rtol_grid"][f"{rtol:.3e}"] = form_entry(f, {"error_vs_fp64_oracle": vs_oracle(f["out"])})
+        progress(f"fp64 rtol {rtol:.3e}: p99.9 |H|_rel {f['p999_rel_h']:.3g}")
         if f["p999_rel_h"] <= 1e-10:
             best = float(rtol)
     res["rtol_equal_accuracy"] = best
@@ -483,6 +490,7 @@ def run_mixed_sweep(K, torch, W, steps):
         for budget, tag in ((1e-10, "budget1e-10"), (1e300, "no_rerun")):
             f = run_form(K, torch, dict(params, precision=K.MIXED, h_budget=budget, r_switch=r_switch), steps, 1)
             res["mixed"][f"r_switch{r_switch:g}_{tag}"] = form_entry(f, {"error_vs_fp64_oracle": vs_oracle(f["out"])})
+            progress(f"mixed r_switch {r_switch:g} {tag}: {f['ms_per_step']:.3f} ms")
     for budget in (1e-9,):
         f = run_form(K, torch, dict(params, precision=K.MIXED, h_budget=budget, r_switch=MIXED_R_SWITCH), steps, 1)
         res["mixed"][f"r_switch{MIXED_R_SWITCH:g}_budget{budget:g}"] = form_entry(
@@ -500,6 +508,7 @@ def run_cpu_legs(K, torch, W, steps):
     pd = W.schwarzschild_disk(n=2048)
     _, dt = oracle_image(pd, threads=threads)
     res["schwarzschild_disk_2048_whole"] = {"rays": 2048 * 2048, "s": dt, "rays_per_s": 2048 * 2048 / dt}
+    progress(f"oracle: 2048^2 disk in {dt:.1f} s")
     images, integ = W.heterogeneous_batch()
     rng = np.random.default_rng(1)
     tot = n_all = 0
@@ -580,6 +589,7 @@ def main():
 
     params = W.kerr_ring(0.9, n=1024, rtol=1e-12)
     main_form = run_form(K, torch, params, args.steps, args.warmup)
+    progress(f"headline form: {main_form['ms_per_step']:.3f} ms per render")
     secs = main_form["ms_per_step"] / 1e3
     rays_per_s = main_form["rays"] / secs
     evals_per_s = main_form["evals"] / secs
@@ -603,6 +613,7 @@ def main():
     cb = o_full = None
     if not args.no_cpu:
         cb, o_full = cpu_baseline(params, main_form["out"])
+        progress("cpu baseline done")
 
     forms = {}
     if not args.no_forms:
@@ -615,11 +626,13 @@ def main():
             if rtol is None:
                 continue
             f = run_form(K, torch, dict(params, rtol=rtol, atol=rtol), k, 1)
+            progress(f"form {name} done")
             forms[name] = form_entry(f, {"rtol": rtol, "error_vs_fp64_rtol1e-12": error_vs(torch, f["out"], main_form["out"]),
                                          "error_vs_fp64_oracle": vs_oracle(f["out"])})
         for budget, name in ((1e-10, "mixed_budget1e-10"), (1e300, "mixed_no_fallback")):
             pm = dict(params, precision=K.MIXED, h_budget=budget, r_switch=MIXED_R_SWITCH)
             f = run_form(K, torch, pm, k, 1)
+            progress(f"form {name} done")
             forms[name] = form_entry(f, {"r_switch": MIXED_R_SWITCH, "h_budget": budget,
                                          "error_vs_fp64": error_vs(torch, f["out"], main_form["out"]),
                                          "error_vs_fp64_oracle": vs_oracle(f["out"])})
@@ -634,13 +647,18 @@ def main():
             "r_switch": MIXED_R_SWITCH, "h_budget": 1e-10,
             "error_vs_fp64": error_vs(torch, fm["out"], fd["out"], keys=("r_hit", "g", "intensity"))})
         del fd, fm
+        progress("disk forms done")
 
     batch = schemes = adjoint = images = None
     if not args.no_forms:
         batch = run_batch_forms(K, torch, W, max(2, args.steps // 8))
+        progress("batch forms done")
         schemes = run_scheme_forms(K, torch, W, max(2, args.steps // 8))
+        progress("integrator forms done")
         adjoint = run_adjoint_form(K, torch, W, max(2, args.steps // 8))
+        progress("adjoint form done")
         images = run_f4_forms(K, torch, W, max(2, args.steps // 8))
+        progress("image forms done")
 
     out = {"metric": METRIC, "value": rays_per_s, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": main_form["ms_per_step"], "higher_is_better": True,
