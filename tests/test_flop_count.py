@@ -1,7 +1,7 @@
 """The algorithmic FLOP count used for the roofline, counted mechanically.
 
 tests/flopcount/ holds a counting scalar (flop.h) and a plain Carter-form
-reference of the per-unit arithmetic (carter_ref.h).  The reference's
+reference of the per-unit arithmetic (hotpath_ref.h).  The reference's
 right-hand side and constraint diagnostics are checked here against the
 oracle (so the counted computation is the method's), and its per-unit
 counts must equal the constants bench.py prices a launch with.  The oracle

@@ -1,9 +1,9 @@
 """Seeded random camera configurations (valid inputs only) on the GPU
 against the oracle, element by element: spins of either sign, inclinations
 near the poles and in between, observer distances, fields of view, ragged
-resolutions, tolerances, the four adaptive schemes, Keplerian and
-constant-l0 disks with power-law or tapered emissivity, and the point
-source."""
+resolutions, tolerances, the adaptive schemes (eight more configurations
+with rational Bulirsch-Stoer), Keplerian and constant-l0 disks with
+power-law or tapered emissivity, and the point source."""
 import sys
 
 import numpy as np
@@ -16,14 +16,14 @@ from tests import parity as P
 pytestmark = pytest.mark.gpu
 
 
-def _config(rng, retrograde=False):
+def _config(rng, retrograde=False, method=None):
     a = float(rng.uniform(-0.998, -0.05)) if retrograde else float(rng.uniform(0.0, 0.998))
     band = int(rng.integers(3))
     incl = float((rng.uniform(0.05, 0.3), rng.uniform(0.3, 2.84), rng.uniform(2.84, 3.09))[band])
     r_obs = float(10 ** rng.uniform(1.5, 3.0))
     fov = float(rng.uniform(4.0, 25.0))
     nx, ny = (int(v) for v in rng.integers(3, 41, size=2))
-    method = int(rng.choice([1, 2, 3, 4]))
+    method = int(rng.choice([1, 2, 3, 4])) if method is None else method
     rtol = float(rng.choice([1e-10, 1e-11, 1e-12]))
     p = dict(M=1.0, a=a, r_obs=r_obs, incl=incl, fov_x=fov, fov_y=fov * float(rng.uniform(0.5, 1.5)), nx=nx,
              ny=ny, method=method, rtol=rtol, atol=rtol, h_init=1.0, cap_buffer=0.01, r_escape=0.0,
@@ -44,6 +44,9 @@ def _config(rng, retrograde=False):
 CONFIGS = ([_config(np.random.default_rng(7000 + k)) for k in range(40)] +
            [_config(np.random.default_rng(7500 + k), retrograde=True) for k in range(8)])
 N_CASES = len(CONFIGS)
+# rational Bulirsch-Stoer (method 5) on eight more, two of them retrograde
+RAT_CONFIGS = [_config(np.random.default_rng(7800 + k), retrograde=k >= 6, method=5) for k in range(8)]
+ALL_CONFIGS = CONFIGS + RAT_CONFIGS
 
 
 @pytest.fixture(scope="module")
@@ -54,10 +57,10 @@ def K():
     return kerrtrace
 
 
-@pytest.mark.parametrize("k", range(N_CASES))
+@pytest.mark.parametrize("k", range(len(ALL_CONFIGS)))
 def test_random_configuration(K, k):
     import torch
-    p = CONFIGS[k]
+    p = ALL_CONFIGS[k]
     nx, ny = p["nx"], p["ny"]
     print(f"[gpu-case] random config {k}: {p}", flush=True)
     sys.stdout.flush()
@@ -77,7 +80,7 @@ def test_random_configuration(K, k):
             P.check_values(g, o, key, d, rtol=1e-8)
     if p.get("src_on"):
         e = m & np.isfinite(o["deflection"])
-        if p["method"] == K.BS:
+        if p["method"] in (K.BS, K.BS_RAT):
             # the step sequence carries rounding far (see the scheme tests):
             # the tolerance follows from the oracle's own one-ulp sensitivity
             s = O.Setup(**p)
