@@ -400,7 +400,7 @@ def run_batch_forms(K, torch, W, steps):
                        "DP45 rtol=atol=1e-12",
            "rays": n, "autotuned_launch": {"block": best.block, "blocks_per_cu": best.blocks_per_cu,
                                            "batch": best.batch},
-           "autotune_probe": "every 8th image (32 images), 20 built-in shapes, 1 repeat"}
+           "autotune_probe": "every 8th image (32 images), 30 built-in shapes, 1 repeat"}
     br = K.BatchRenderer(images, device="cuda:0", want=BATCH_WANT, launch=best, **integ)
     br.render()
     t = _time(torch, br.render, steps)

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define KT_VERSION_NUMBER 200
+#define KT_VERSION_NUMBER 201
 
 /* return codes */
 #define KT_OK 0
@@ -151,7 +151,14 @@ typedef struct kt_integrator {
 } kt_integrator;
 
 /* Launch shape.  Pass NULL for the defaults: persistent, block 256,
-   blocks_per_cu 0, batch 4, KT_ORDER_RING. */
+   blocks_per_cu 0, batch 4, KT_ORDER_RING.
+   The trace kernels exist in two builds with bit-identical outputs: one for
+   2 waves per SIMD and one for 3 (fewer registers, a few more instructions
+   per step).  A persistent launch runs the 3-wave build when its shape asks
+   for 3 or more waves per SIMD (blocks_per_cu * block >= 768), or, with
+   blocks_per_cu 0, when the render has at least 10 rays per lane of a
+   3-wave grid (about 2M rays on 256 CUs); then blocks_per_cu 0 means the
+   3-wave build's occupancy.  Other launches run the 2-wave build. */
 typedef struct kt_launch {
     int32_t persistent;     /* 1: persistent waves refill lanes from a global ticket;
                                0: one ray per lane, no refill */
@@ -280,7 +287,7 @@ int kt_render_batch(int32_t n_images, const kt_image *images, const kt_integrato
 size_t kt_workspace_bytes_batch(int32_t n_images, const kt_image *images,
                                 const kt_integrator *integ);
 
-#define KT_AUTOTUNE_DEFAULT_COUNT 20
+#define KT_AUTOTUNE_DEFAULT_COUNT 30
 
 /* Launch-shape autotuner.  Renders the batch (the probe workload: pass a
    representative subset of a large batch to keep this short) once untimed
@@ -289,7 +296,7 @@ size_t kt_workspace_bytes_batch(int32_t n_images, const kt_image *images,
    per SIMD are chosen through blocks_per_cu (blocks_per_cu * block / 256
    waves per SIMD).  candidates == NULL with n_candidates == 0 selects the
    built-in set of KT_AUTOTUNE_DEFAULT_COUNT shapes: persistent, block
-   {128, 256} x 1 or 2 waves per SIMD x ticket batch {4, 8, 16, 32, 64}.
+   {128, 256} x 1, 2 or 3 waves per SIMD x ticket batch {4, 8, 16, 32, 64}.
    times_ms (may be NULL) receives the mean milliseconds per render of each
    candidate, in order.  Synchronises hip_stream; the outputs hold the last
    render's results.  repeats lies in [1, 100].  Other arguments as for

@@ -60,6 +60,21 @@ int device_cus() {
     return cache[dev];
 }
 
+// Which build of the trace kernels a launch runs (both give the same
+// outputs bit for bit).  The 3-wave form (kt_trace_w3.hip) steps ~7% faster,
+// but each ray takes longer in wall time, so the end of a persistent launch,
+// which waits for the last rays, grows; it pays once every lane of a 3-wave
+// grid has about ten rays or more to trace, and it is the only form that
+// can run a launch shape of 3 or more waves per SIMD.
+constexpr int64_t W3_MIN_RAYS_PER_LANE = 10;
+
+bool three_wave_form(const kt_launch& ln, int64_t n_rays) {
+    if (!ln.persistent) return false;
+    if (ln.blocks_per_cu > 0) return static_cast<int64_t>(ln.blocks_per_cu) * ln.block >= 3 * 256;
+    const int64_t lanes = static_cast<int64_t>(device_cus()) * 4 * 3 * 64;
+    return n_rays >= W3_MIN_RAYS_PER_LANE * lanes;
+}
+
 double horizon(const kt_spacetime* st) {
     if (st->metric == KT_METRIC_Q) return 2.0 * st->M;
     return st->M + std::sqrt(st->M * st->M - st->a * st->a);
@@ -367,16 +382,19 @@ int render_images(const kt::Image* table, int32_t n_images, int64_t n_rays, cons
     if (p.perm && kt::launch_order(p, hip_stream))
         return fail(KT_EDEVICE, "dispatch order launch failed: %s", hipGetErrorString(hipGetLastError()));
     const int64_t lane_grid = (n_rays + ln.block - 1) / ln.block;
+    const bool w3 = three_wave_form(ln, n_rays);
     int grid;
     if (p.persistent) {
-        const int per_cu = ln.blocks_per_cu > 0 ? ln.blocks_per_cu : kt::trace_max_blocks_per_cu(p, ln.block);
+        const int per_cu = ln.blocks_per_cu > 0 ? ln.blocks_per_cu
+                           : w3                 ? kt_w3::trace_max_blocks_per_cu(p, ln.block)
+                                                : kt::trace_max_blocks_per_cu(p, ln.block);
         grid = device_cus() * per_cu;
         if (grid > lane_grid) grid = static_cast<int>(lane_grid);
     } else {
         grid = static_cast<int>(lane_grid);
     }
     if (grid < 1) grid = 1;
-    if (kt::launch_trace(p, grid, ln.block, hip_stream))
+    if ((w3 ? kt_w3::launch_trace : kt::launch_trace)(p, grid, ln.block, hip_stream))
         return fail(KT_EDEVICE, "trace kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
     if (p.precision == KT_MIXED) {
         // re-run every ray over the |H|_rel budget in FP64, from a compacted
@@ -385,7 +403,7 @@ int render_images(const kt::Image* table, int32_t n_images, int64_t n_rays, cons
             return fail(KT_EDEVICE, "fallback list launch failed: %s", hipGetErrorString(hipGetLastError()));
         int grid2 = ln.persistent ? grid : static_cast<int>(lane_grid);
         if (grid2 < 1) grid2 = 1;
-        if (kt::launch_trace_fallback(p, grid2, ln.block, hip_stream))
+        if ((w3 ? kt_w3::launch_trace_fallback : kt::launch_trace_fallback)(p, grid2, ln.block, hip_stream))
             return fail(KT_EDEVICE, "fallback trace launch failed: %s", hipGetErrorString(hipGetLastError()));
     }
     if ((out->r_hit || out->g || out->intensity) && kt::launch_disk_obs(p, hip_stream))
@@ -624,7 +642,7 @@ int kt_autotune_batch(int32_t n_images, const kt_image* images, const kt_integra
         cand.assign(candidates, candidates + n_candidates);
     } else {
         for (int block : {128, 256})
-            for (int waves : {1, 2})
+            for (int waves : {1, 2, 3})
                 for (int batch : {4, 8, 16, 32, 64})
                     cand.push_back(kt_launch{1, block, waves * 256 / block, batch, KT_ORDER_RING});
     }

@@ -234,3 +234,12 @@ int launch_init_rays(const Params& p, double* state, uint8_t* invalid, void* str
 int trace_max_blocks_per_cu(const Params& p, int block);
 
 }  // namespace kt
+
+// The same trace kernels built for 3 waves per SIMD (kt_trace_w3.hip): the
+// default for renders of many rays per lane, and for launch shapes of 3 or
+// more waves per SIMD.  Their outputs equal the 2-wave kernels' bit for bit.
+namespace kt_w3 {
+int launch_trace(const kt::Params& p, int grid, int block, void* stream);
+int launch_trace_fallback(const kt::Params& p, int grid, int block, void* stream);
+int trace_max_blocks_per_cu(const kt::Params& p, int block);
+}  // namespace kt_w3

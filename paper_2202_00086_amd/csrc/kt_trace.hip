@@ -22,11 +22,23 @@
 #include "kt_ray.h"
 #include "kt_sort.h"
 
+// The file is compiled twice.  As itself it defines every kernel of the
+// render in namespace kt, with the trace kernels built for 2 waves per SIMD.
+// kt_trace_w3.hip includes it again with KT_TRACE_ONLY set: only the trace
+// kernels and their launchers, in namespace kt_w3, built for 3 waves per SIMD
+// and compiled without machine loop-invariant code motion (see there).
 #ifndef KT_WAVES_PER_EU
 #define KT_WAVES_PER_EU 2
 #endif
+#ifndef KT_TRACE_NS
+#define KT_TRACE_NS kt
+#endif
+#ifndef KT_TRACE_ONLY
+#define KT_TRACE_ONLY 0
+#endif
 
-namespace kt {
+namespace KT_TRACE_NS {
+using namespace kt;
 
 // Great-circle angle between the directions (theta1, phi1) and
 // (theta2, phi1 + dphi), given sin/cos of the thetas: atan2(|n1 x n2|, n1.n2).
@@ -559,6 +571,7 @@ trace_kernel(const Hot hp) {
     }
 }
 
+#if !KT_TRACE_ONLY
 // Compact the re-run flags into the fallback list (order does not matter:
 // every ray is independent) and count them.
 __global__ void fallback_list_kernel(const uint8_t* __restrict__ need, int64_t n, uint32_t* __restrict__ list,
@@ -811,12 +824,15 @@ __global__ void init_rays_kernel(const Image im, int64_t n, double* state, uint8
     }
 }
 
+#endif  // !KT_TRACE_ONLY
+
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
 
 static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
 
+#if !KT_TRACE_ONLY
 static int small_grid(int64_t n, int block) {
     int64_t g = (n + block - 1) / block;
     if (g > 4096) g = 4096;
@@ -850,6 +866,8 @@ int launch_upload_images(const Image* host, int32_t n, Image* dev, void* stream)
     }
     return 0;
 }
+
+#endif  // !KT_TRACE_ONLY
 
 static Hot make_hot(const Params& p) {
     const Image& im = p.img0;  // batch renders take the per-image values from the table
@@ -933,6 +951,7 @@ int launch_trace(const Params& p, int grid, int block, void* stream) {
     return check_launch();
 }
 
+#if !KT_TRACE_ONLY
 int launch_fallback_list(const Params& p, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(fallback_list_kernel, dim3(small_grid(p.n_rays, 256)), dim3(256), 0, s, p.need_fb,
@@ -941,6 +960,8 @@ int launch_fallback_list(const Params& p, void* stream) {
     hipLaunchKernelGGL(to_fallback_kernel, dim3(1), dim3(64), 0, s, p.ws_params);
     return check_launch();
 }
+
+#endif  // !KT_TRACE_ONLY
 
 int launch_trace_fallback(const Params& p, int grid, int block, void* stream) {
     const Hot hp = make_hot(p);
@@ -976,6 +997,7 @@ int trace_max_blocks_per_cu(const Params& p, int block) {
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
+#if !KT_TRACE_ONLY
 int launch_disk_obs(const Params& p, void* stream) {
     hipLaunchKernelGGL(disk_obs_kernel, dim3(small_grid(p.n_rays, 256)), dim3(256), 0,
                        static_cast<hipStream_t>(stream), p.ws_params);
@@ -1013,4 +1035,6 @@ int launch_init_rays(const Params& p, double* state, uint8_t* invalid, void* str
     return check_launch();
 }
 
-}  // namespace kt
+#endif  // !KT_TRACE_ONLY
+
+}  // namespace KT_TRACE_NS

@@ -126,7 +126,7 @@ _lib.kt_version.restype = C.c_int
 EXPORTED = ("kt_render", "kt_render_ex", "kt_render_noalloc", "kt_render_batch", "kt_autotune_batch", "kt_adjoint",
             "kt_workspace_bytes", "kt_workspace_bytes_batch", "kt_adjoint_workspace_bytes", "kt_init_rays",
             "kt_last_error", "kt_version")
-AUTOTUNE_DEFAULT_COUNT = 20
+AUTOTUNE_DEFAULT_COUNT = 30
 
 
 class KtError(RuntimeError):

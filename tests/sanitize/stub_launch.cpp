@@ -164,3 +164,12 @@ int launch_adjoint(const AdjParams& p, void*) {
 }
 
 }  // namespace kt
+
+// the 3-wave build of the trace kernels touches the same memory
+namespace kt_w3 {
+int launch_trace(const kt::Params& p, int grid, int block, void* s) { return kt::launch_trace(p, grid, block, s); }
+int launch_trace_fallback(const kt::Params& p, int grid, int block, void* s) {
+    return kt::launch_trace_fallback(p, grid, block, s);
+}
+int trace_max_blocks_per_cu(const kt::Params&, int block) { return 768 / block; }
+}  // namespace kt_w3

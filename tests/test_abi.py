@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared_functions():
         assert hasattr(lib, name), name
     assert set(K.EXPORTED) == set(_declared_functions())
-    assert K.kt_version() == 200
+    assert K.kt_version() == 201
 
 
 def test_struct_layouts_match_header():

@@ -106,7 +106,8 @@ def test_batch_launch_shapes_are_bit_identical(K):
     _announce("batch launch shapes")
     _, ref = batch_render(K, images, integ)
     for ln in [K.kt_launch(1, 128, 0, 1), K.kt_launch(1, 64, 1, 8), K.kt_launch(0, 256, 0, 32),
-               K.kt_launch(1, 256, 3, 4096), K.kt_launch(1, 256, 0, 32, K.ORDER_ROWS)]:
+               K.kt_launch(1, 256, 3, 4096), K.kt_launch(1, 256, 0, 32, K.ORDER_ROWS),
+               K.kt_launch(1, 128, 6, 8)]:
         _announce("  launch", ln.persistent, ln.block, ln.blocks_per_cu, ln.batch, ln.order)
         _, g = batch_render(K, images, integ, launch=ln)
         for key in _BITWISE:

@@ -149,15 +149,18 @@ def test_ragged_and_tiny_images(K):
 
 def test_launch_shapes_are_bit_identical(K):
     """Per-ray arithmetic does not depend on which lane or wave runs the ray:
-    persistent / one-ray-per-lane / queue batch 1 / small blocks and both
-    dispatch orders give bit-identical outputs (the default is ring-first
-    order; every pixel must still be traced exactly once)."""
+    persistent / one-ray-per-lane / queue batch 1 / small blocks, both
+    dispatch orders and both builds of the kernels (2 and 3 waves per SIMD)
+    give bit-identical outputs (the default is ring-first order; every pixel
+    must still be traced exactly once)."""
     params = dict(W.kerr_ring(0.9, n=96), disk_on=1, r_in=2.320883, r_out=30.0)
     _announce("launch shapes")
     base = gpu_render(K, params)
+    # the last three ask for 3 waves per SIMD: the 3-wave build of the kernels
     shapes = [K.kt_launch(0, 256, 0, 32), K.kt_launch(1, 64, 1, 1), K.kt_launch(1, 128, 2, 7),
               K.kt_launch(1, 256, 1, 4096), K.kt_launch(1, 256, 0, 32, K.ORDER_ROWS),
-              K.kt_launch(0, 64, 0, 32, K.ORDER_ROWS)]
+              K.kt_launch(0, 64, 0, 32, K.ORDER_ROWS), K.kt_launch(1, 256, 3, 4), K.kt_launch(1, 128, 6, 1),
+              K.kt_launch(1, 256, 3, 16, K.ORDER_ROWS)]
     for ln in shapes:
         _announce("launch", ln.persistent, ln.block, ln.blocks_per_cu, ln.batch, ln.order)
         g = gpu_render(K, params, launch=ln)
@@ -274,6 +277,11 @@ def test_mixed_zero_budget_equals_fp64(K):
     g = gpu_render(K, dict(params, precision=K.MIXED, h_budget=0.0, r_switch=300.0))
     for key in _BITWISE_KEYS:
         np.testing.assert_array_equal(g[key].view(np.uint8), ref[key].view(np.uint8), err_msg=key)
+    # the same through the 3-wave build of the kernels (3 waves per SIMD)
+    g3 = gpu_render(K, dict(params, precision=K.MIXED, h_budget=0.0, r_switch=300.0),
+                    launch=K.kt_launch(1, 256, 3, 4))
+    for key in _BITWISE_KEYS:
+        np.testing.assert_array_equal(g3[key].view(np.uint8), ref[key].view(np.uint8), err_msg="w3 " + key)
     st = g["stats"]
     assert st.evals_fp32 > 0
     assert st.fallback_rays == int(g["used_fp64"].sum()) > 0

@@ -97,7 +97,8 @@ def test_qmetric_launch_shapes_and_q_zero(K):
     params = W.qmetric_lensing(q=0.5, n=24)
     _announce("q-metric launch shapes")
     ref = gpu_render(K, params)
-    for ln in [K.kt_launch(1, 64, 1, 1), K.kt_launch(0, 128, 0, 32)]:
+    # the last shape runs the 3-wave build of the kernels
+    for ln in [K.kt_launch(1, 64, 1, 1), K.kt_launch(0, 128, 0, 32), K.kt_launch(1, 256, 3, 4)]:
         g = gpu_render(K, params, launch=ln)
         for key in ("fate", "sky", "theta_f", "phi_f", "max_rel_h", "n_steps"):
             np.testing.assert_array_equal(g[key].view(np.uint8), ref[key].view(np.uint8), err_msg=key)

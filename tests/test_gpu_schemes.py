@@ -111,7 +111,7 @@ def test_scheme_batch_and_launch_shapes_bit_identical(K, name, method):
                                           s[key].view(np.uint8), err_msg=f"{name} image {k} {key}")
     p0 = W.image_params(images[0], integ)
     ref = gpu_render(K, p0)
-    for ln in [K.kt_launch(1, 64, 1, 1), K.kt_launch(0, 128, 0, 32)]:
+    for ln in [K.kt_launch(1, 64, 1, 1), K.kt_launch(0, 128, 0, 32), K.kt_launch(1, 256, 3, 4)]:
         g = gpu_render(K, p0, launch=ln)
         for key in ("fate", "r_hit", "g", "max_rel_h", "n_steps"):
             np.testing.assert_array_equal(g[key].view(np.uint8), ref[key].view(np.uint8), err_msg=key)
