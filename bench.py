@@ -65,7 +65,7 @@ def flop_per_launch(evals, attempts6, accepted, src_on, qmetric=False):
 PEAK_FP64_VECTOR = 78.6e12  # MI355X FP64 vector, FLOP/s
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "trace_kernel_kerr_ring_1024_a0.9_counters.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_00086_amd", "csrc", f)
-                  for f in ("kt_device.h", "kt_elem.h", "kt_ray.h", "kt_internal.h", "kt_trace.hip")]
+                  for f in ("kt_device.h", "kt_elem.h", "kt_ray.h", "kt_internal.h", "kt_trace.hip", "kt_trace_w3.hip")]
 
 
 def kernel_source_hash():
