@@ -375,10 +375,30 @@ def run_adjoint_form(K, torch, W, steps):
     adjoint()
     t_adj = _time(torch, adjoint, steps)
     st = [int(v) for v in stats.cpu().tolist()]
+    g_default = grad_sum.cpu().tolist()
+    # every accepted step stored (checkpoint_every 1): no recomputation in
+    # the backward sweep, a larger workspace
+    integ1 = K.make_structs(**dict(params, checkpoint_every=1))[4]
+    nbytes1 = K.kt_adjoint_workspace_bytes(r.cam, integ1)
+    ws1 = torch.empty(nbytes1, dtype=torch.uint8, device="cuda:0")
+
+    def adjoint_every_step():
+        rc = K.kt_adjoint(r.cam, r.st, r.disk, integ1, out["fate"].data_ptr(), out["r_hit"].data_ptr(),
+                          cot.data_ptr(), grads[0].data_ptr(), grads[1].data_ptr(), grads[2].data_ptr(),
+                          stats.data_ptr(), ws1.data_ptr(), nbytes1, stream, out["n_steps"].data_ptr(),
+                          grad_sum.data_ptr())
+        if rc != K.KT_OK:
+            raise K.KtError(rc, K.kt_last_error())
+    adjoint_every_step()
+    t_adj1 = _time(torch, adjoint_every_step, steps)
+    same = grad_sum.cpu().tolist() == g_default
+    del ws1
     return {"workload": "Kerr a=0.7 disk, 512x512, i=45 deg, r_obs=1000M, +-35M, r_in=ISCO(0.7), r_out=30M, "
                         "tapered emissivity, DP45 rtol=atol=1e-12; L2 loss vs (a=0.6, i=50 deg, r_in=1.1 ISCO)",
             "forward_ms": 1e3 * t_fwd, "adjoint_ms": 1e3 * t_adj, "adjoint_over_forward": t_adj / t_fwd,
             "adjoint_ms_without_step_counts": 1e3 * t_unsorted,
+            "adjoint_ms_every_step_stored": 1e3 * t_adj1, "every_step_grad_identical": same,
+            "workspace_bytes": {"checkpoint_every_64": nbytes, "every_step": nbytes1},
             "loss": float((((out["intensity"] - T) ** 2) * mask).sum().item()),
             "grad": dict(zip(("a", "incl", "r_in"), grad_sum.cpu().tolist())),
             "rays_differentiated": st[0], "failed": st[1], "overflow": st[2], "mismatch": st[3],

@@ -146,7 +146,9 @@ typedef struct kt_integrator {
     double r_switch;        /* MIXED: FP32 RHS part only where r >= r_switch */
     int64_t max_steps;      /* accepted-step budget per ray, >= 1 */
     int32_t checkpoint_every; /* kt_adjoint: a checkpoint every this many accepted
-                                 steps, a power of two in [8, 1024]; 0 selects 64.
+                                 steps, a power of two in [1, 1024]; 0 selects 64.
+                                 1 stores every step (no recomputation in the
+                                 backward sweep; the largest workspace).
                                  Renders ignore it (but reject other values) */
 } kt_integrator;
 
@@ -326,10 +328,13 @@ int kt_autotune_batch(int32_t n_images, const kt_image *images, const kt_integra
    and neighbouring lanes get rays of similar length; it changes only the
    time).  Each ray is re-integrated with the forward's own arithmetic,
    checkpointed every integ->checkpoint_every accepted steps (64 when 0), and
-   swept backward segment by segment.
+   swept backward segment by segment, each segment recomputed from its
+   checkpoint; with checkpoint_every 1 every accepted step is stored and
+   the sweep reads them instead (same gradients bit for bit).
    stats (device, 4 uint64, may be NULL): rays differentiated, rays that
-   failed, rays beyond the checkpoint capacity (256 checkpoints, i.e.
-   256 * checkpoint_every accepted steps), rays whose re-integration did not
+   failed, rays beyond the checkpoint capacity (max(256, 2048 /
+   checkpoint_every) checkpoints, i.e. at least 2048 accepted steps and
+   256 * checkpoint_every from 8 on), rays whose re-integration did not
    reproduce r_hit; the last three get zero gradient and drop out of
    grad_sum, so a caller that needs the whole gradient checks them.
    workspace: kt_adjoint_workspace_bytes() bytes, 256-byte aligned.

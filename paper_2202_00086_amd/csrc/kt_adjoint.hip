@@ -144,6 +144,11 @@ __device__ int adjoint_ray(const AdjParams& P, const Spacetime& st, int lane, in
             break;
         }
         if (yn[0] < im.r_cap || yn[0] > im.r_esc) return ADJ_MISMATCH;
+        if (P.ck_shift == 0) {
+            // every accepted step: its start state and its accepted size
+            if (n >= P.max_ckpt) return ADJ_OVERFLOW;
+            put6(slot(P.ckpt, n, lane, P.n_lanes), P.n_lanes, y, h);
+        }
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
             y[i] = yn[i];
@@ -154,7 +159,7 @@ __device__ int adjoint_ray(const AdjParams& P, const Spacetime& st, int lane, in
         h = hn;
         rej = false;
         ++n;
-        if ((n & ck_mask) == 0) {
+        if (P.ck_shift > 0 && (n & ck_mask) == 0) {
             if ((n >> P.ck_shift) >= P.max_ckpt) return ADJ_OVERFLOW;
             put6(slot(P.ckpt, n >> P.ck_shift, lane, P.n_lanes), P.n_lanes, y, h);
         }
@@ -172,6 +177,15 @@ __device__ int adjoint_ray(const AdjParams& P, const Spacetime& st, int lane, in
 
     // ---- 3. reverse sweep with frozen steps ------------------------------
     adj::dp_step_vjp(im.M, im.a, E, L, y, hstar, zb, &pb);
+    if (P.ck_shift == 0) {
+        // every step was stored: no recomputation
+        for (int j = n - 1; j >= 0; --j) {
+            double yj[5], hj;
+            get6(slot(P.ckpt, j, lane, P.n_lanes), P.n_lanes, yj, &hj);
+            adj::dp_step_vjp(im.M, im.a, E, L, yj, hj, zb, &pb);
+        }
+        n = 0;  // the segment sweep below has nothing left to do
+    }
     for (int s = (n - 1) >> P.ck_shift; n > 0 && s >= 0; --s) {
         const int first = s << P.ck_shift, last = min(n, first + ck_mask + 1);
         double ys[5], hs;

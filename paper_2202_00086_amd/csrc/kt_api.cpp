@@ -213,7 +213,7 @@ int validate_integ(const kt_integrator* integ) {
     if (integ->max_steps < 1 || integ->max_steps > 100000000)
         return fail(KT_EINVAL, "max_steps must lie in [1, 1e8]");
     if (kt::adj_ck_shift(integ->checkpoint_every) < 0)
-        return fail(KT_EINVAL, "checkpoint_every must be 0 or a power of two in [8, 1024] (got %d)",
+        return fail(KT_EINVAL, "checkpoint_every must be 0 or a power of two in [1, 1024] (got %d)",
                     integ->checkpoint_every);
     return KT_OK;
 }
@@ -569,7 +569,7 @@ int kt_adjoint(const kt_camera* camera, const kt_spacetime* spacetime, const kt_
     if (!fate || !cot_intensity) return fail(KT_EINVAL, "fate and cot_intensity must not be NULL");
     const int ck_shift = kt::adj_ck_shift(integ->checkpoint_every);
     if (ck_shift < 0)
-        return fail(KT_EINVAL, "checkpoint_every must be 0 or a power of two in [8, 1024] (got %d)",
+        return fail(KT_EINVAL, "checkpoint_every must be 0 or a power of two in [1, 1024] (got %d)",
                     integ->checkpoint_every);
     kt::Image im;
     if ((rc = make_image(camera, spacetime, disk, nullptr, integ, false, im))) return rc;

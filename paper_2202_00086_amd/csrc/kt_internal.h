@@ -169,13 +169,16 @@ struct AdjParams {
 #define KT_ADJ_MAX_LANES 65536
 #endif
 constexpr int ADJ_MAX_LANES = KT_ADJ_MAX_LANES;
-constexpr int ADJ_MAX_CKPT = 256;
-constexpr int ADJ_CK_SHIFT_DEFAULT = 6;  // checkpoints every 64 accepted steps
-constexpr int ADJ_CK_SHIFT_MIN = 3, ADJ_CK_SHIFT_MAX = 10;
+constexpr int ADJ_MAX_CKPT = 256;            // checkpoint slots per lane, at least
+constexpr int ADJ_MIN_STEPS_COVERED = 2048;  // and at least this many accepted steps covered
+constexpr int ADJ_CK_SHIFT_DEFAULT = 6;      // checkpoints every 64 accepted steps
+// 0 stores every accepted step (start state and accepted size): the reverse
+// sweep then reads each step instead of recomputing it
+constexpr int ADJ_CK_SHIFT_MIN = 0, ADJ_CK_SHIFT_MAX = 10;
 constexpr int ADJ_RED_BLOCKS = 256;      // fixed grid of the gradient reduction (deterministic)
 
 // log2 of kt_integrator.checkpoint_every (0 selects 64); -1 unless a power
-// of two in [8, 1024].
+// of two in [1, 1024].
 inline int adj_ck_shift(int32_t every) {
     if (every == 0) return ADJ_CK_SHIFT_DEFAULT;
     for (int s = ADJ_CK_SHIFT_MIN; s <= ADJ_CK_SHIFT_MAX; ++s)
@@ -194,7 +197,9 @@ inline AdjLayout adj_layout(size_t n_rays, int64_t max_steps, int ck_shift) {
     if (lanes > static_cast<size_t>(ADJ_MAX_LANES)) lanes = ADJ_MAX_LANES;
     if (lanes < 256) lanes = 256;
     int64_t ck = (max_steps >> ck_shift) + 2;
-    if (ck > ADJ_MAX_CKPT) ck = ADJ_MAX_CKPT;
+    const int64_t cap = ADJ_MAX_CKPT > (ADJ_MIN_STEPS_COVERED >> ck_shift) ? ADJ_MAX_CKPT
+                                                                         : (ADJ_MIN_STEPS_COVERED >> ck_shift);
+    if (ck > cap) ck = cap;
     w.n_lanes = static_cast<int32_t>(lanes);
     w.max_ckpt = static_cast<int32_t>(ck);
     w.stats = 64;

@@ -101,7 +101,8 @@ BAD = [
     dict(metric=1, q=0.5, precision=1),
     dict(sky_on=1, line_deg=float("inf")),
     dict(checkpoint_every=48),                       # not a power of two
-    dict(checkpoint_every=4),                        # below 8
+    dict(checkpoint_every=3),                        # not a power of two
+    dict(checkpoint_every=-1),                       # negative
     dict(checkpoint_every=2048),                     # above 1024
 ]
 
@@ -178,7 +179,7 @@ def test_workspace_bytes_zero_on_bad_camera():
     assert K.kt_adjoint_workspace_bytes(cam, integ) == 0
     K, cam, st, disk, src, integ = _args(checkpoint_every=96)
     assert K.kt_adjoint_workspace_bytes(cam, integ) == 0
-    for every in (8, 64, 1024):
+    for every in (1, 2, 8, 64, 1024):
         K, cam, st, disk, src, integ = _args(checkpoint_every=every)
         assert K.kt_adjoint_workspace_bytes(cam, integ) > 0
 

@@ -251,8 +251,8 @@ def test_adjoint_image_sums_and_checkpoint_interval(torch_mod):
     """grad_sum: the library's own sums of the three gradient maps, equal to
     an exactly rounded sum of the maps to 1e-13 and bit-identical whatever
     lanes ran the rays (with and without step counts).  The checkpoint
-    interval (8, 64 = default, 256 accepted steps) changes only what is
-    recomputed: the maps are bit-identical."""
+    interval (1 = every step stored, 2, 8, 64 = default, 256 accepted
+    steps) changes only what is recomputed: the maps are bit-identical."""
     import ctypes as C
     import math as _m
     torch = torch_mod
@@ -264,7 +264,7 @@ def test_adjoint_image_sums_and_checkpoint_interval(torch_mod):
     out = r.render()
     cot = torch.linspace(-1.0, 2.0, r.n, dtype=torch.float64, device="cuda:0")
     res = {}
-    for every in (8, 0, 256):
+    for every in (1, 2, 8, 0, 256):
         integ = K.make_structs(**dict(params, checkpoint_every=every))[4]
         nbytes = K.kt_adjoint_workspace_bytes(r.cam, integ)
         assert nbytes > 0
