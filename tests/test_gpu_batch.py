@@ -198,7 +198,8 @@ def test_autotune_picks_the_fastest_candidate(K):
     br, ref = batch_render(K, images, integ)
     best, times = br.autotune(repeats=1)
     assert len(times) == K.AUTOTUNE_DEFAULT_COUNT and min(times) > 0.0
-    shapes = [(b, w * 256 // b, q) for b in (128, 256) for w in (1, 2) for q in (4, 8, 16, 32, 64)]
+    shapes = [(b, w * 256 // b, q) for b in (128, 256) for w in (1, 2, 3) for q in (4, 8, 16, 32, 64)]
+    assert len(shapes) == K.AUTOTUNE_DEFAULT_COUNT
     assert (best.block, best.blocks_per_cu, best.batch) == shapes[int(np.argmin(times))]
     after = _host(K, br.out)
     for key in _BITWISE:
