@@ -347,6 +347,7 @@ def run_adjoint_form(K, torch, W, steps):
     ISCO, tapered emissivity): forward render and the discrete adjoint of the
     L2 loss against the image at (0.6, 50 deg, 1.1 ISCO(0.6)), both timed."""
     import ctypes as C
+    import numpy as np
     params = W.differentiable_disk(n=512)
     want = ("fate", "r_hit", "g", "intensity", "n_cross", "n_steps")
     T = K.Renderer(device="cuda:0", want=want, stats=False, **W.disk_fit_target(n=512)).render()["intensity"]
@@ -359,49 +360,61 @@ def run_adjoint_form(K, torch, W, steps):
     grads = [torch.empty(r.n, dtype=torch.float64, device="cuda:0") for _ in range(3)]
     grad_sum = torch.empty(3, dtype=torch.float64, device="cuda:0")
     stats = torch.zeros(4, dtype=torch.int64, device="cuda:0")
-    nbytes = K.kt_adjoint_workspace_bytes(r.cam, r.integ)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
     stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
-    def adjoint(sorted_list=True):
-        rc = K.kt_adjoint(r.cam, r.st, r.disk, r.integ, out["fate"].data_ptr(), out["r_hit"].data_ptr(),
-                          cot.data_ptr(), grads[0].data_ptr(), grads[1].data_ptr(), grads[2].data_ptr(),
-                          stats.data_ptr(), ws.data_ptr(), nbytes, stream,
-                          out["n_steps"].data_ptr() if sorted_list else None, grad_sum.data_ptr())
-        if rc != K.KT_OK:
-            raise K.KtError(rc, K.kt_last_error())
-    adjoint(False)
-    t_unsorted = _time(torch, lambda: adjoint(False), steps)
-    adjoint()
-    t_adj = _time(torch, adjoint, steps)
-    st = [int(v) for v in stats.cpu().tolist()]
-    g_default = grad_sum.cpu().tolist()
+    def variant(**kw):
+        """A kt_adjoint call with these integrator fields, on a workspace of its own."""
+        integ = K.make_structs(**dict(params, **kw))[4]
+        nb = K.kt_adjoint_workspace_bytes(r.cam, integ)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+
+        def call(sorted_list=True):
+            rc = K.kt_adjoint(r.cam, r.st, r.disk, integ, out["fate"].data_ptr(), out["r_hit"].data_ptr(),
+                              cot.data_ptr(), grads[0].data_ptr(), grads[1].data_ptr(), grads[2].data_ptr(),
+                              stats.data_ptr(), ws.data_ptr(), nb, stream,
+                              out["n_steps"].data_ptr() if sorted_list else None, grad_sum.data_ptr())
+            if rc != K.KT_OK:
+                raise K.KtError(rc, K.kt_last_error())
+        return call, ws, nb
+
+    def timed(call, **kw):
+        call(**kw)
+        t = _time(torch, lambda: call(**kw), steps)
+        return t, grad_sum.cpu().tolist(), [int(v) for v in stats.cpu().tolist()]
+
+    # the default: checkpoints every 64 steps, long rays' sweeps split
+    adjoint, ws, nbytes = variant()
+    t_unsorted, g_unsorted, _ = timed(adjoint, sorted_list=False)
+    t_adj, g_default, st = timed(adjoint)
+    n_split = int(ws[16:20].cpu().numpy().view(np.uint32)[0])  # the library's count of split rays
+    seq, ws_seq, _ = variant(split_above=-1)
+    t_seq, g_seq, st_seq = timed(seq)
+    del ws_seq
     # every accepted step stored (checkpoint_every 1): no recomputation in
     # the backward sweep, a larger workspace
-    integ1 = K.make_structs(**dict(params, checkpoint_every=1))[4]
-    nbytes1 = K.kt_adjoint_workspace_bytes(r.cam, integ1)
-    ws1 = torch.empty(nbytes1, dtype=torch.uint8, device="cuda:0")
-
-    def adjoint_every_step():
-        rc = K.kt_adjoint(r.cam, r.st, r.disk, integ1, out["fate"].data_ptr(), out["r_hit"].data_ptr(),
-                          cot.data_ptr(), grads[0].data_ptr(), grads[1].data_ptr(), grads[2].data_ptr(),
-                          stats.data_ptr(), ws1.data_ptr(), nbytes1, stream, out["n_steps"].data_ptr(),
-                          grad_sum.data_ptr())
-        if rc != K.KT_OK:
-            raise K.KtError(rc, K.kt_last_error())
-    adjoint_every_step()
-    t_adj1 = _time(torch, adjoint_every_step, steps)
-    same = grad_sum.cpu().tolist() == g_default
+    every, ws1, nbytes1 = variant(checkpoint_every=1)
+    t_adj1, g_every, _ = timed(every)
     del ws1
+    every_seq, ws1s, _ = variant(checkpoint_every=1, split_above=-1)
+    t_adj1_seq, _, _ = timed(every_seq)
+    del ws1s
+    rel = max(abs(a - b) / abs(b) for a, b in zip(g_default, g_seq))
     return {"workload": "Kerr a=0.7 disk, 512x512, i=45 deg, r_obs=1000M, +-35M, r_in=ISCO(0.7), r_out=30M, "
                         "tapered emissivity, DP45 rtol=atol=1e-12; L2 loss vs (a=0.6, i=50 deg, r_in=1.1 ISCO)",
             "forward_ms": 1e3 * t_fwd, "adjoint_ms": 1e3 * t_adj, "adjoint_over_forward": t_adj / t_fwd,
+            "split_rays": n_split,
+            "adjoint_ms_sequential_sweeps": 1e3 * t_seq,
             "adjoint_ms_without_step_counts": 1e3 * t_unsorted,
-            "adjoint_ms_every_step_stored": 1e3 * t_adj1, "every_step_grad_identical": same,
+            "adjoint_ms_every_step_stored": 1e3 * t_adj1,
+            "adjoint_ms_every_step_stored_sequential_sweeps": 1e3 * t_adj1_seq,
+            "every_step_grad_identical": g_every == g_default,
+            "split_vs_sequential_grad_rel_diff": rel,
+            "sequential_grad_identical_without_step_counts": g_unsorted == g_seq,
             "workspace_bytes": {"checkpoint_every_64": nbytes, "every_step": nbytes1},
             "loss": float((((out["intensity"] - T) ** 2) * mask).sum().item()),
-            "grad": dict(zip(("a", "incl", "r_in"), grad_sum.cpu().tolist())),
+            "grad": dict(zip(("a", "incl", "r_in"), g_default)),
             "rays_differentiated": st[0], "failed": st[1], "overflow": st[2], "mismatch": st[3],
+            "sequential_stats_equal": st_seq == st,
             "differentiated_rays_per_s": st[0] / t_adj}
 
 

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define KT_VERSION_NUMBER 201
+#define KT_VERSION_NUMBER 202
 
 /* return codes */
 #define KT_OK 0
@@ -150,6 +150,14 @@ typedef struct kt_integrator {
                                  1 stores every step (no recomputation in the
                                  backward sweep; the largest workspace).
                                  Renders ignore it (but reject other values) */
+    int32_t split_above;    /* kt_adjoint with the forward step counts: a ray whose
+                               forward render took more than this many accepted
+                               steps has its backward sweep split into 64-step
+                               segments swept on separate lanes; 0 picks the
+                               threshold from the work list, -1 never splits
+                               (and leaves the split buffers out of the
+                               workspace).  Renders ignore it (but reject values
+                               below -1) */
 } kt_integrator;
 
 /* Launch shape.  Pass NULL for the defaults: persistent, block 256,
@@ -325,12 +333,26 @@ int kt_autotune_batch(int32_t n_images, const kt_image *images, const kt_integra
    kt_render (method KT_DP45, KT_FP64, disk enabled), and that render's fate
    array, its r_hit array (optional, for a bit-identity check) and its
    n_steps array (optional: the differentiated rays are run longest first
-   and neighbouring lanes get rays of similar length; it changes only the
-   time).  Each ray is re-integrated with the forward's own arithmetic,
-   checkpointed every integ->checkpoint_every accepted steps (64 when 0), and
-   swept backward segment by segment, each segment recomputed from its
-   checkpoint; with checkpoint_every 1 every accepted step is stored and
-   the sweep reads them instead (same gradients bit for bit).
+   and neighbouring lanes get rays of similar length, and long rays can be
+   split, below).  Each ray is re-integrated with the forward's own
+   arithmetic, checkpointed every integ->checkpoint_every accepted steps (64
+   when 0), and swept backward segment by segment, each segment recomputed
+   from its checkpoint; with checkpoint_every 1 every accepted step is
+   stored and the sweep reads them instead (same gradients bit for bit).
+   Split sweeps (n_steps given, integ->split_above >= 0): a ray whose
+   forward took more than split_above accepted steps (0: 0.85 times the mean
+   number of steps per lane of the work list, at least 128; the longest rays
+   first, whole step-count bins of 4 steps at a time, as many as fit 8192
+   records and a store of 32 steps per lane of the grid; rays of more than
+   2046 steps are not split) stores every step, and the transposed Jacobian
+   of each 64-step segment is
+   swept on four lanes at once, one per basis cotangent of (r, theta, p_r,
+   p_theta) (that of phi stays zero: the field does not depend on phi); the
+   segments' maps are then applied in order to the ray's cotangent.  This
+   cuts the sequential length of the longest rays, which otherwise set the
+   adjoint's run time.  Split rays' gradients equal the sequential sweep's
+   up to rounding (the same products, associated differently); they do not
+   depend on checkpoint_every.
    stats (device, 4 uint64, may be NULL): rays differentiated, rays that
    failed, rays beyond the checkpoint capacity (max(256, 2048 /
    checkpoint_every) checkpoints, i.e. at least 2048 accepted steps and

@@ -215,6 +215,8 @@ int validate_integ(const kt_integrator* integ) {
     if (kt::adj_ck_shift(integ->checkpoint_every) < 0)
         return fail(KT_EINVAL, "checkpoint_every must be 0 or a power of two in [1, 1024] (got %d)",
                     integ->checkpoint_every);
+    if (integ->split_above < -1) return fail(KT_EINVAL, "split_above must be -1, 0 or a step count (got %d)",
+                                             integ->split_above);
     return KT_OK;
 }
 
@@ -548,7 +550,8 @@ size_t kt_adjoint_workspace_bytes(const kt_camera* camera, const kt_integrator* 
     if (n >= (size_t{1} << 31)) return 0;  // ray ids are int32
     const int ck_shift = kt::adj_ck_shift(integ->checkpoint_every);
     if (ck_shift < 0) return 0;
-    return kt::adj_layout(n, integ->max_steps, ck_shift).total;
+    if (integ->split_above < -1) return 0;
+    return kt::adj_layout(n, integ->max_steps, ck_shift, integ->split_above >= 0).total;
 }
 
 int kt_adjoint(const kt_camera* camera, const kt_spacetime* spacetime, const kt_disk* disk,
@@ -575,7 +578,7 @@ int kt_adjoint(const kt_camera* camera, const kt_spacetime* spacetime, const kt_
     if ((rc = make_image(camera, spacetime, disk, nullptr, integ, false, im))) return rc;
     im.first = 0;
     const size_t n = static_cast<size_t>(camera->nx) * static_cast<size_t>(camera->ny);
-    const kt::AdjLayout w = kt::adj_layout(n, integ->max_steps, ck_shift);
+    const kt::AdjLayout w = kt::adj_layout(n, integ->max_steps, ck_shift, integ->split_above >= 0);
     if (!workspace) return fail(KT_EINVAL, "workspace must not be NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
         return fail(KT_EINVAL, "workspace must be 256-byte aligned");
@@ -606,7 +609,7 @@ int kt_adjoint(const kt_camera* camera, const kt_spacetime* spacetime, const kt_
     p.grad_sum = grad_sum;
     p.partials = reinterpret_cast<double*>(ws + w.partials);
     p.ck_shift = ck_shift;
-    p.ticket = reinterpret_cast<uint32_t*>(ws);
+    p.ticket = reinterpret_cast<uint32_t*>(ws + kt::ADJ_WS_TICKET);
     p.stats = stats ? reinterpret_cast<unsigned long long*>(stats)
                     : reinterpret_cast<unsigned long long*>(ws + w.stats);
     p.ckpt = reinterpret_cast<double*>(ws + w.ckpt);
@@ -617,6 +620,16 @@ int kt_adjoint(const kt_camera* camera, const kt_spacetime* spacetime, const kt_
     p.list = reinterpret_cast<uint32_t*>(ws + w.list);
     p.n_lanes = w.n_lanes;
     p.max_ckpt = w.max_ckpt;
+    // split sweeps need the forward step counts (the work list's order)
+    p.split_above = integ->split_above;
+    p.max_long = n_steps && integ->split_above >= 0 ? w.max_long : 0;
+    p.long_cap = w.long_cap;
+    p.item_cap = w.item_cap;
+    p.counters = reinterpret_cast<uint32_t*>(ws + kt::ADJ_WS_COUNTERS);
+    p.long_store = reinterpret_cast<double*>(ws + w.long_store);
+    p.longs = reinterpret_cast<kt::AdjLong*>(ws + w.longs);
+    p.owner = reinterpret_cast<uint32_t*>(ws + w.owner);
+    p.items = reinterpret_cast<double*>(ws + w.items);
     if (kt::launch_adjoint(p, hip_stream))
         return fail(KT_EDEVICE, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError()));
     return KT_OK;

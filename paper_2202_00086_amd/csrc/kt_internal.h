@@ -138,6 +138,21 @@ struct Hot {
     const Params* cold;         // the workspace copy of Params
 };
 
+// A ray whose backward sweep is split into segments (the first n_long
+// entries of the work list).  The forward pass stores every accepted step
+// in the split-ray store from `base`, then the cotangents of the state at
+// the start of the located partial step.  Segment s covers the steps
+// [ADJ_SEG s, ADJ_SEG (s + 1)); its four basis runs are segment items
+// item_base + 4 s + b.
+enum : int32_t { ADJ_LONG_DONE = 0, ADJ_LONG_SPLIT = 1 };
+struct AdjLong {
+    int32_t ray, status, n, n_seg;  // n accepted steps before the crossing
+    uint32_t base, item_base, pad0, pad1;
+    double zb[4];                   // cotangents of (r, theta, p_r, p_theta); that of phi is 0
+    double pb[3];                   // of (E, L, a)
+    double gr, E, L;                // the r_in gradient (from the seed alone) and the ray constants
+};
+
 // Everything the adjoint kernel needs (passed by value).
 struct AdjParams {
     Image im;
@@ -163,6 +178,15 @@ struct AdjParams {
     uint32_t* hist;             // [SORT_BINS + 1] bin counts, then offsets; [SORT_BINS] = list length
     uint16_t* keys;             // [n_rays] bin of each ray, SORT_SKIP if not differentiated
     uint32_t* list;             // [n_rays] ray ids
+    // split backward sweeps (only with n_steps; max_long 0 switches them off)
+    int32_t split_above;        // 0: threshold from the work list; > 0: this many steps
+    int32_t max_long;           // records in `longs`
+    uint32_t long_cap, item_cap;
+    uint32_t* counters;         // [0] n_long, [1] store allocation, [2] item allocation
+    double* long_store;         // [long_cap][6] every accepted step (state, size) of the split rays
+    AdjLong* longs;             // [max_long]
+    uint32_t* owner;            // [item_cap] record of each segment item (0xffffffff: none)
+    double* items;              // [item_cap][8] one segment's sweep of one basis cotangent
 };
 
 #ifndef KT_ADJ_MAX_LANES
@@ -176,6 +200,13 @@ constexpr int ADJ_CK_SHIFT_DEFAULT = 6;      // checkpoints every 64 accepted st
 // sweep then reads each step instead of recomputing it
 constexpr int ADJ_CK_SHIFT_MIN = 0, ADJ_CK_SHIFT_MAX = 10;
 constexpr int ADJ_RED_BLOCKS = 256;      // fixed grid of the gradient reduction (deterministic)
+// Split backward sweeps: segments of ADJ_SEG steps, at most ADJ_SEG_MAX of
+// them per ray, at most ADJ_MAX_LONG split rays, and a store of
+// ADJ_LONG_STEPS_PER_LANE accepted steps per lane of the grid.
+constexpr int ADJ_SEG = 64, ADJ_SEG_MAX = 32;
+constexpr int ADJ_MAX_LONG = 8192;
+constexpr int ADJ_LONG_STEPS_PER_LANE = 32;
+constexpr int ADJ_SPLIT_MIN = 128;        // the automatic threshold is at least this many steps
 
 // log2 of kt_integrator.checkpoint_every (0 selects 64); -1 unless a power
 // of two in [1, 1024].
@@ -187,11 +218,16 @@ inline int adj_ck_shift(int32_t every) {
 }
 
 struct AdjLayout {
-    size_t stats, hist, partials, ckpt, seg, keys, list, grad, total;
-    int32_t n_lanes, max_ckpt;
+    size_t stats, hist, partials, ckpt, seg, keys, list, grad, longs, owner, items, long_store, total;
+    int32_t n_lanes, max_ckpt, max_long;
+    uint32_t long_cap, item_cap;
 };
 
-inline AdjLayout adj_layout(size_t n_rays, int64_t max_steps, int ck_shift) {
+// Byte offsets in the first 256 bytes of the adjoint's workspace.
+constexpr size_t ADJ_WS_TICKET = 0, ADJ_WS_COUNTERS = 16;
+
+// split: room for split backward sweeps (kt_integrator.split_above >= 0).
+inline AdjLayout adj_layout(size_t n_rays, int64_t max_steps, int ck_shift, bool split) {
     AdjLayout w;
     size_t lanes = (n_rays + 255) / 256 * 256;
     if (lanes > static_cast<size_t>(ADJ_MAX_LANES)) lanes = ADJ_MAX_LANES;
@@ -210,7 +246,16 @@ inline AdjLayout adj_layout(size_t n_rays, int64_t max_steps, int ck_shift) {
     w.keys = align256(w.seg + (size_t{1} << ck_shift) * 6u * lanes * sizeof(double));
     w.list = align256(w.keys + 2u * n_rays);
     w.grad = align256(w.list + 4u * n_rays);
-    w.total = align256(w.grad + 3u * sizeof(double) * n_rays);
+    w.max_long = split ? static_cast<int32_t>(n_rays < size_t{ADJ_MAX_LONG} ? n_rays : size_t{ADJ_MAX_LONG}) : 0;
+    w.long_cap = split ? static_cast<uint32_t>(lanes * ADJ_LONG_STEPS_PER_LANE) : 0u;
+    // every split ray's segments fit: sum over rays of 4 ceil(n / ADJ_SEG)
+    // <= 4 (long_cap / ADJ_SEG + max_long), since the rays' stores do not overlap
+    w.item_cap = split ? 4u * (w.long_cap / ADJ_SEG + static_cast<uint32_t>(w.max_long)) : 0u;
+    w.longs = align256(w.grad + 3u * sizeof(double) * n_rays);
+    w.owner = align256(w.longs + static_cast<size_t>(w.max_long) * sizeof(AdjLong));
+    w.items = align256(w.owner + 4u * static_cast<size_t>(w.item_cap));
+    w.long_store = align256(w.items + 8u * sizeof(double) * w.item_cap);
+    w.total = align256(w.long_store + 6u * sizeof(double) * w.long_cap);
     return w;
 }
 

@@ -64,7 +64,7 @@ class kt_integrator(C.Structure):
                 ("rtol", C.c_double), ("atol", C.c_double), ("h_init", C.c_double),
                 ("capture_buffer", C.c_double), ("r_escape", C.c_double),
                 ("h_budget", C.c_double), ("r_switch", C.c_double), ("max_steps", C.c_int64),
-                ("checkpoint_every", C.c_int32)]
+                ("checkpoint_every", C.c_int32), ("split_above", C.c_int32)]
 
 
 class kt_launch(C.Structure):
@@ -220,12 +220,12 @@ def make_structs(M=1.0, a=0.0, metric=0, q=0.0, r_obs=1000.0, incl=math.pi / 2, 
                  h_init=1.0, cap_buffer=0.01, r_escape=0.0, h_budget=1e-10, r_switch=300.0,
                  max_steps=1_000_000, disk_on=0, r_in=6.0, r_out=30.0, emis_q=2.0, rotation=0, l0=0.0,
                  emis_model=0, src_on=0, r_src=1000.0, sky_on=0, grid_deg=6.0, line_deg=0.25,
-                 checkpoint_every=0):
+                 checkpoint_every=0, split_above=0):
     """C structs from keyword parameters (the same names the workloads use)."""
     cam = kt_camera(r_obs, incl, fov_x, fov_y, nx, ny)
     st = kt_spacetime(M, a, int(metric), q)
     integ = kt_integrator(method, precision, h_fixed, rtol, atol, h_init, cap_buffer, r_escape,
-                          h_budget, r_switch, int(max_steps), int(checkpoint_every))
+                          h_budget, r_switch, int(max_steps), int(checkpoint_every), int(split_above))
     disk = kt_disk(int(disk_on), r_in, r_out, emis_q, int(rotation), l0, int(emis_model))
     src = kt_source(int(src_on), r_src, int(sky_on), grid_deg, line_deg)
     return cam, st, disk, src, integ

@@ -120,12 +120,13 @@ void batch_case(bool mixed, bool src_on) {
     std::free(ws);
 }
 
-void adjoint_case(int nx, int ny, int every, bool maps, bool sums, bool stats) {
+void adjoint_case(int nx, int ny, int every, bool maps, bool sums, bool stats, int split = 0) {
     kt_camera cam = {1000.0, 0.8, 35.0, 35.0, nx, ny};
     kt_spacetime st = {1.0, 0.7, KT_METRIC_KERR, 0.0};
     kt_disk disk = {1, 3.4, 30.0, 2.0, KT_ROT_KEPLER, 0.0, KT_EMIS_TAPERED};
     kt_integrator it = integ_of(KT_DP45, KT_FP64);
     it.checkpoint_every = every;
+    it.split_above = split;
     const size_t n = static_cast<size_t>(nx) * ny;
     std::vector<void*> b;
     auto take = [&](size_t bytes) { b.push_back(alloc_exact(bytes)); return b.back(); };
@@ -169,6 +170,9 @@ int main() {
         adjoint_case(1, 1, every, false, true, false);
         adjoint_case(300, 301, every, false, false, true);
     }
+    // split backward sweeps off, and at a fixed threshold
+    adjoint_case(40, 24, 1, true, true, true, -1);
+    adjoint_case(300, 301, 0, true, false, true, 500);
 
     // init_rays
     {

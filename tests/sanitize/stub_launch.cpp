@@ -156,6 +156,13 @@ int launch_adjoint(const AdjParams& p, void*) {
     write_bytes(p.grad_a, 8 * n);
     write_bytes(p.grad_incl, 8 * n);
     write_bytes(p.grad_rin, 8 * n);
+    if (p.max_long > 0) {  // split backward sweeps
+        write_bytes(p.counters, 3 * 4);
+        write_bytes(p.longs, static_cast<size_t>(p.max_long) * sizeof(AdjLong));
+        write_bytes(p.owner, 4 * static_cast<size_t>(p.item_cap));
+        write_bytes(p.items, 8 * 8 * static_cast<size_t>(p.item_cap));
+        write_bytes(p.long_store, 6 * 8 * static_cast<size_t>(p.long_cap));
+    }
     if (p.grad_sum) {
         write_bytes(p.partials, 3 * ADJ_RED_BLOCKS * 8);
         write_bytes(p.grad_sum, 3 * 8);

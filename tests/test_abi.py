@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared_functions():
         assert hasattr(lib, name), name
     assert set(K.EXPORTED) == set(_declared_functions())
-    assert K.kt_version() == 201
+    assert K.kt_version() == 202
 
 
 def test_struct_layouts_match_header():
@@ -52,7 +52,8 @@ def test_struct_layouts_match_header():
     assert C.sizeof(K.kt_spacetime) == 32
     assert C.sizeof(K.kt_disk) == 56
     assert C.sizeof(K.kt_source) == 40
-    assert C.sizeof(K.kt_integrator) == 8 + 8 * 8 + 8 + 8  # checkpoint_every padded to 8
+    assert C.sizeof(K.kt_integrator) == 8 + 8 * 8 + 8 + 8  # checkpoint_every and split_above
+    assert K.kt_integrator.split_above.offset == 84
     assert C.sizeof(K.kt_launch) == 20
     assert C.sizeof(K.kt_stats) == 12 * 8
     assert C.sizeof(K.kt_outputs) == 17 * 8
@@ -104,6 +105,7 @@ BAD = [
     dict(checkpoint_every=3),                        # not a power of two
     dict(checkpoint_every=-1),                       # negative
     dict(checkpoint_every=2048),                     # above 1024
+    dict(split_above=-2),                            # below -1
 ]
 
 
@@ -182,6 +184,20 @@ def test_workspace_bytes_zero_on_bad_camera():
     for every in (1, 2, 8, 64, 1024):
         K, cam, st, disk, src, integ = _args(checkpoint_every=every)
         assert K.kt_adjoint_workspace_bytes(cam, integ) > 0
+    K, cam, st, disk, src, integ = _args(split_above=-2)
+    assert K.kt_adjoint_workspace_bytes(cam, integ) == 0
+    # the split buffers: a store of 32 steps (6 doubles each) per lane of the grid,
+    # 4 (store / 64 + records) segment items (8 doubles and a 4-byte owner each)
+    # and 8192 records of 112 bytes
+    sizes = {}
+    for split in (-1, 0, 700):
+        K, cam, st, disk, src, integ = _args(nx=512, ny=512, split_above=split)
+        sizes[split] = K.kt_adjoint_workspace_bytes(cam, integ)
+    assert sizes[0] == sizes[700] > sizes[-1]
+    lanes = 65536
+    items = 4 * (32 * lanes // 64 + 8192)
+    extra = 32 * lanes * 48 + items * (64 + 4) + 8192 * 112
+    assert 0 <= sizes[0] - sizes[-1] - extra < 4 * 256
 
 
 def _batch(images, **integ_kw):

@@ -111,9 +111,10 @@ def test_autograd_loss_gradient_matches_finite_differences(torch_mod):
 
 def test_adjoint_work_list_order_and_cotangent_mask(torch_mod):
     """The work list (differentiated rays, sorted by forward step count when
-    n_steps is given) changes only which lane runs a ray: gradients are
-    bit-identical with and without step counts.  Disk pixels with a zero
-    cotangent are skipped (zero gradient, not counted)."""
+    n_steps is given) changes only which lane runs a ray: with split sweeps
+    off, gradients are bit-identical with and without step counts.  Disk
+    pixels with a zero cotangent are skipped (zero gradient, not counted),
+    with split sweeps too."""
     import ctypes as C
     torch = torch_mod
     from paper_2202_00086_amd import kerrtrace as K
@@ -128,16 +129,19 @@ def test_adjoint_work_list_order_and_cotangent_mask(torch_mod):
     nbytes = K.kt_adjoint_workspace_bytes(r.cam, r.integ)
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
     stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    sequential = K.make_structs(**dict(params, split_above=-1))[4]
     res = []
-    for steps in (out["n_steps"].data_ptr(), None):
+    for steps, integ in ((out["n_steps"].data_ptr(), sequential), (None, sequential),
+                         (out["n_steps"].data_ptr(), r.integ)):
         grads = [torch.full((n,), float("nan"), dtype=torch.float64, device="cuda:0") for _ in range(3)]
         stats = torch.zeros(4, dtype=torch.int64, device="cuda:0")
-        rc = K.kt_adjoint(r.cam, r.st, r.disk, r.integ, out["fate"].data_ptr(), out["r_hit"].data_ptr(),
+        rc = K.kt_adjoint(r.cam, r.st, r.disk, integ, out["fate"].data_ptr(), out["r_hit"].data_ptr(),
                           cot.data_ptr(), grads[0].data_ptr(), grads[1].data_ptr(), grads[2].data_ptr(),
                           stats.data_ptr(), ws.data_ptr(), nbytes, stream, steps)
         assert rc == K.KT_OK, K.kt_last_error()
         torch.cuda.synchronize()
         res.append(([g.cpu().numpy() for g in grads], stats.cpu().numpy()))
+    assert _split_rays(ws) > 0  # the last call split some sweeps
     fate = out["fate"].cpu().numpy()
     c = cot.cpu().numpy()
     want = int(((fate == K.DISK) & (c != 0.0)).sum())
@@ -149,6 +153,28 @@ def test_adjoint_work_list_order_and_cotangent_mask(torch_mod):
             assert (g[(fate == K.DISK) & (c != 0.0)] != 0.0).mean() > 0.9
     for g1, g2 in zip(res[0][0], res[1][0]):
         np.testing.assert_array_equal(g1.view(np.uint8), g2.view(np.uint8))
+    for g1, g3 in zip(res[0][0], res[2][0]):
+        _assert_split_close(g3, g1)
+
+
+def _split_rays(ws):
+    """How many work-list entries the last kt_adjoint call on this workspace
+    took for split sweeps: the library keeps that count in the workspace's
+    first bytes (a uint32 at byte 16, after the work-list ticket)."""
+    return int(ws[16:20].cpu().numpy().view(np.uint32)[0])
+
+
+# Split sweeps apply the same step maps as the sequential sweep, associated
+# differently; the per-pixel gradients agree to rounding amplified by the
+# length of the sweep.
+SPLIT_RTOL = 1e-9
+
+
+def _assert_split_close(split, seq):
+    scale = np.abs(seq).max()
+    err = np.abs(split - seq) / (np.abs(seq) + 1e-6 * scale)
+    assert err.max() <= SPLIT_RTOL, (err.max(), int(np.argmax(err)))
+    return float(err.max())
 
 
 def test_full_size_adjoint_sampled(torch_mod):
@@ -250,9 +276,11 @@ def _adjoint_call(K, torch, r, out, cot, ws, nbytes, integ=None, steps=True, r_h
 def test_adjoint_image_sums_and_checkpoint_interval(torch_mod):
     """grad_sum: the library's own sums of the three gradient maps, equal to
     an exactly rounded sum of the maps to 1e-13 and bit-identical whatever
-    lanes ran the rays (with and without step counts).  The checkpoint
-    interval (1 = every step stored, 2, 8, 64 = default, 256 accepted
-    steps) changes only what is recomputed: the maps are bit-identical."""
+    lanes ran the rays (with and without step counts when sweeps are not
+    split).  The checkpoint interval (1 = every step stored, 2, 8, 64 =
+    default, 256 accepted steps) changes only what is recomputed: the maps
+    are bit-identical, with split sweeps too (split rays store every step
+    whatever the interval)."""
     import ctypes as C
     import math as _m
     torch = torch_mod
@@ -265,22 +293,35 @@ def test_adjoint_image_sums_and_checkpoint_interval(torch_mod):
     cot = torch.linspace(-1.0, 2.0, r.n, dtype=torch.float64, device="cuda:0")
     res = {}
     for every in (1, 2, 8, 0, 256):
-        integ = K.make_structs(**dict(params, checkpoint_every=every))[4]
-        nbytes = K.kt_adjoint_workspace_bytes(r.cam, integ)
-        assert nbytes > 0
-        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
-        for steps in (True, False):
-            res[(every, steps)] = _adjoint_call(K, torch, r, out, cot, ws, nbytes, integ, steps)
-    base_maps, base_sum, base_st = res[(0, True)]
-    assert base_st[1:].tolist() == [0, 0, 0] and base_st[0] > 300
-    for k in range(3):
-        want = _m.fsum(base_maps[k].tolist())
-        assert abs(base_sum[k] - want) <= 1e-13 * _m.fsum(abs(v) for v in base_maps[k].tolist()), (k, base_sum[k], want)
+        for split in (-1, 0):
+            integ = K.make_structs(**dict(params, checkpoint_every=every, split_above=split))[4]
+            nbytes = K.kt_adjoint_workspace_bytes(r.cam, integ)
+            assert nbytes > 0
+            ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+            for steps in (True, False):
+                res[(every, split, steps)] = _adjoint_call(K, torch, r, out, cot, ws, nbytes, integ, steps)
+                if split == 0 and steps:
+                    assert _split_rays(ws) > 0
+    for group in ((-1, True), (-1, False), (0, False), (0, True)):
+        base_maps, base_sum, base_st = res[(0,) + group]
+        assert base_st[1:].tolist() == [0, 0, 0] and base_st[0] > 300
+        for k in range(3):
+            want = _m.fsum(base_maps[k].tolist())
+            tot = _m.fsum(abs(v) for v in base_maps[k].tolist())
+            assert abs(base_sum[k] - want) <= 1e-13 * tot, (group, k, base_sum[k], want)
+    # bit-identical: every interval, and sequential sweeps with or without step counts
+    seq_maps, seq_sum, seq_st = res[(0, -1, True)]
+    split_maps, split_sum, _ = res[(0, 0, True)]
     for key, (maps, sums, st) in res.items():
-        assert st.tolist() == base_st.tolist(), key
-        np.testing.assert_array_equal(sums.view(np.uint8), base_sum.view(np.uint8), err_msg=str(key))
-        for a, b in zip(maps, base_maps):
+        assert st.tolist() == seq_st.tolist(), key
+        want_maps, want_sum = (split_maps, split_sum) if key[1:] == (0, True) else (seq_maps, seq_sum)
+        np.testing.assert_array_equal(sums.view(np.uint8), want_sum.view(np.uint8), err_msg=str(key))
+        for a, b in zip(maps, want_maps):
             np.testing.assert_array_equal(a.view(np.uint8), b.view(np.uint8), err_msg=str(key))
+    # split against sequential: close, per pixel and in the sums
+    errs = [_assert_split_close(a, b) for a, b in zip(split_maps, seq_maps)]
+    np.testing.assert_allclose(split_sum, seq_sum, rtol=1e-11)
+    print(f"[adjoint] split vs sequential sweeps: worst per-pixel relative difference {max(errs):.2e}", flush=True)
     bad = K.make_structs(**dict(params, checkpoint_every=48))[4]
     assert K.kt_adjoint_workspace_bytes(r.cam, bad) == 0
 
