@@ -342,10 +342,12 @@ def ring_report(torch, out, p):
             "max_flag_distance_px": float(dist.max()) if dist.size else None}
 
 
-def run_adjoint_form(K, torch, W, steps):
+def run_adjoint_form(K, torch, W, steps, default_only=False):
     """The differentiable disk image (512^2, a = 0.7, i = 45 deg, r_in =
     ISCO, tapered emissivity): forward render and the discrete adjoint of the
-    L2 loss against the image at (0.6, 50 deg, 1.1 ISCO(0.6)), both timed."""
+    L2 loss against the image at (0.6, 50 deg, 1.1 ISCO(0.6)), both timed.
+    default_only: the default adjoint alone (with step counts, split sweeps),
+    so that a profile of the run covers that configuration only."""
     import ctypes as C
     import numpy as np
     params = W.differentiable_disk(n=512)
@@ -384,6 +386,12 @@ def run_adjoint_form(K, torch, W, steps):
 
     # the default: checkpoints every 64 steps, long rays' sweeps split
     adjoint, ws, nbytes = variant()
+    if default_only:
+        t_adj, g_default, st = timed(adjoint)
+        return {"forward_ms": 1e3 * t_fwd, "adjoint_ms": 1e3 * t_adj, "adjoint_over_forward": t_adj / t_fwd,
+                "split_rays": int(ws[16:20].cpu().numpy().view(np.uint32)[0]),
+                "grad": dict(zip(("a", "incl", "r_in"), g_default)),
+                "rays_differentiated": st[0], "failed": st[1], "overflow": st[2], "mismatch": st[3]}
     t_unsorted, g_unsorted, _ = timed(adjoint, sorted_list=False)
     t_adj, g_default, st = timed(adjoint)
     n_split = int(ws[16:20].cpu().numpy().view(np.uint32)[0])  # the library's count of split rays
@@ -587,6 +595,8 @@ def main():
                     default=None, help="run one extra form alone and print its JSON (for profiling); no headline line")
     ap.add_argument("--workload", choices=("ring", "disk", "qmetric", "batch"), default="ring",
                     help="with --only render: the workload rendered --steps times")
+    ap.add_argument("--adjoint-default-only", action="store_true",
+                    help="with --only adjoint: the default adjoint configuration alone (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this build measures one GPU (rays are "
@@ -600,7 +610,11 @@ def main():
         if args.only == "render":
             print(json.dumps({"render": run_render(K, torch, W, max(1, args.steps), args.workload)}), flush=True)
             return
-        run = {"batch": run_batch_forms, "adjoint": run_adjoint_form, "images": run_f4_forms,
+        if args.only == "adjoint":
+            res = run_adjoint_form(K, torch, W, max(1, args.steps), args.adjoint_default_only)
+            print(json.dumps({"adjoint": res}), flush=True)
+            return
+        run = {"batch": run_batch_forms, "images": run_f4_forms,
                "integrators": run_scheme_forms, "mixed": run_mixed_sweep, "cpu": run_cpu_legs}[args.only]
         print(json.dumps({args.only: run(K, torch, W, max(1, args.steps))}), flush=True)
         return
