@@ -68,6 +68,15 @@ int device_cus() {
 // can run a launch shape of 3 or more waves per SIMD.
 constexpr int64_t W3_MIN_RAYS_PER_LANE = 10;
 
+// The default shape's ticket batch.  With a few rays per lane the whole
+// launch is the start and the end of the schedule, and taking 16 ids per
+// ticket fetch instead of 4 measured 25% faster on 512x512 images (2 rays
+// per lane of the 2-wave grid), even at 724x724 (4 rays per lane), and
+// worse from ~8 rays per lane on, where a wave holding ids that no one
+// else can take delays the end (the 1024x1024 headline image).
+constexpr int64_t SMALL_MIN_RAYS_PER_LANE = 1, SMALL_MAX_RAYS_PER_LANE = 4;
+constexpr int32_t DEFAULT_BATCH = 4, SMALL_BATCH = 16;
+
 bool three_wave_form(const kt_launch& ln, int64_t n_rays) {
     if (!ln.persistent) return false;
     if (ln.blocks_per_cu > 0) return static_cast<int64_t>(ln.blocks_per_cu) * ln.block >= 3 * 256;
@@ -307,7 +316,7 @@ bool is_mixed(const kt_integrator* integ) { return integ->precision == KT_MIXED;
 int render_images(const kt::Image* table, int32_t n_images, int64_t n_rays, const kt_integrator* integ,
                   const kt_outputs* out, void* workspace, size_t workspace_bytes, void* hip_stream,
                   const kt_launch* launch) {
-    kt_launch ln{1, 256, 0, 4, KT_ORDER_RING};
+    kt_launch ln{1, 256, 0, DEFAULT_BATCH, KT_ORDER_RING};
     if (launch) ln = *launch;
     if (ln.block != 64 && ln.block != 128 && ln.block != 256)
         return fail(KT_EINVAL, "launch block must be 64, 128 or 256");
@@ -373,16 +382,7 @@ int render_images(const kt::Image* table, int32_t n_images, int64_t n_rays, cons
         p.order_bins = reinterpret_cast<uint16_t*>(ws + w.bins);
     }
     p.persistent = ln.persistent ? 1 : 0;
-    p.batch = ln.batch;
     p.from_list = 0;
-
-    if (batch && kt::launch_upload_images(table, n_images, reinterpret_cast<kt::Image*>(ws + w.images),
-                                          hip_stream))
-        return fail(KT_EDEVICE, "image table upload failed: %s", hipGetErrorString(hipGetLastError()));
-    if (kt::launch_ws_init(p, hip_stream))
-        return fail(KT_EDEVICE, "workspace init launch failed: %s", hipGetErrorString(hipGetLastError()));
-    if (p.perm && kt::launch_order(p, hip_stream))
-        return fail(KT_EDEVICE, "dispatch order launch failed: %s", hipGetErrorString(hipGetLastError()));
     const int64_t lane_grid = (n_rays + ln.block - 1) / ln.block;
     const bool w3 = three_wave_form(ln, n_rays);
     int grid;
@@ -396,6 +396,20 @@ int render_images(const kt::Image* table, int32_t n_images, int64_t n_rays, cons
         grid = static_cast<int>(lane_grid);
     }
     if (grid < 1) grid = 1;
+    p.batch = ln.batch;
+    if (!launch && p.persistent) {
+        const int64_t lanes = static_cast<int64_t>(grid) * ln.block;
+        if (n_rays >= SMALL_MIN_RAYS_PER_LANE * lanes && n_rays <= SMALL_MAX_RAYS_PER_LANE * lanes)
+            p.batch = SMALL_BATCH;
+    }
+
+    if (batch && kt::launch_upload_images(table, n_images, reinterpret_cast<kt::Image*>(ws + w.images),
+                                          hip_stream))
+        return fail(KT_EDEVICE, "image table upload failed: %s", hipGetErrorString(hipGetLastError()));
+    if (kt::launch_ws_init(p, hip_stream))
+        return fail(KT_EDEVICE, "workspace init launch failed: %s", hipGetErrorString(hipGetLastError()));
+    if (p.perm && kt::launch_order(p, hip_stream))
+        return fail(KT_EDEVICE, "dispatch order launch failed: %s", hipGetErrorString(hipGetLastError()));
     if ((w3 ? kt_w3::launch_trace : kt::launch_trace)(p, grid, ln.block, hip_stream))
         return fail(KT_EDEVICE, "trace kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
     if (p.precision == KT_MIXED) {
