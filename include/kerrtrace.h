@@ -161,7 +161,8 @@ typedef struct kt_integrator {
 } kt_integrator;
 
 /* Launch shape.  Pass NULL for the defaults: persistent, block 256,
-   blocks_per_cu 0, batch 4, KT_ORDER_RING.
+   blocks_per_cu 0, batch 4 (16 when the render has 1 to 4 rays per lane of
+   the grid), KT_ORDER_RING.
    The trace kernels exist in two builds with bit-identical outputs: one for
    2 waves per SIMD and one for 3 (fewer registers, a few more instructions
    per step).  A persistent launch runs the 3-wave build when its shape asks
