@@ -215,6 +215,33 @@ def test_full_size_adjoint_sampled(torch_mod):
         assert err.max() < 1e-4, (k, err.max())
 
 
+def test_full_size_split_sweeps_match_sequential(torch_mod):
+    """512x512 with the L2 loss's kind of cotangent (every disk ray of order
+    <= 1): the default adjoint splits the longest rays' sweeps (a few
+    thousand of them), and every pixel's gradient equals that of the
+    sequential sweeps to SPLIT_RTOL; both count the same rays."""
+    torch = torch_mod
+    from paper_2202_00086_amd import kerrtrace as K
+    params = W.differentiable_disk(n=512)
+    _announce("adjoint 512 split against sequential")
+    r = K.Renderer(device="cuda:0", want=("fate", "r_hit", "g", "intensity", "n_cross", "n_steps"),
+                   stats=False, **params)
+    out = r.render()
+    cot = ((out["fate"] == K.DISK) & (out["n_cross"] <= 1)).to(torch.float64).contiguous()
+    nbytes = K.kt_adjoint_workspace_bytes(r.cam, r.integ)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    split_maps, split_sum, split_st = _adjoint_call(K, torch, r, out, cot, ws, nbytes)
+    n_split = _split_rays(ws)
+    seq = K.make_structs(**dict(params, split_above=-1))[4]
+    seq_maps, seq_sum, seq_st = _adjoint_call(K, torch, r, out, cot, ws, nbytes, integ=seq)
+    print(f"[adjoint 512] {n_split} rays split; stats {split_st.tolist()}", flush=True)
+    assert n_split > 1000
+    assert split_st.tolist() == seq_st.tolist() and split_st[1:].tolist() == [0, 0, 0]
+    errs = [_assert_split_close(a, b) for a, b in zip(split_maps, seq_maps)]
+    np.testing.assert_allclose(split_sum, seq_sum, rtol=1e-11)
+    print(f"[adjoint 512] split vs sequential: worst per-pixel relative difference {max(errs):.2e}", flush=True)
+
+
 def _random_disk(seed):
     """Seeds 31-34: prograde spin, Keplerian or constant-l0 rotation; 35 and 36:
     retrograde spin (the disk counter-rotates with the hole), Keplerian."""

@@ -171,6 +171,23 @@ def test_launch_shapes_are_bit_identical(K):
             np.testing.assert_array_equal(g[key].view(np.uint8), v.view(np.uint8), err_msg=key)
 
 
+def test_small_render_default_ticket_batch(K):
+    """A 512x512 disk image has 2 rays per lane of the default grid, where
+    the default launch takes 16 ids per ticket fetch instead of 4: its
+    outputs equal those of an explicit batch-4 launch bit for bit, and every
+    pixel is traced once."""
+    params = W.differentiable_disk(n=512)
+    want = ("fate", "r_hit", "g", "intensity", "n_cross", "n_steps", "n_evals", "max_rel_h")
+    _announce("default ticket batch at 512x512")
+    base = gpu_render(K, params, want=want)
+    g = gpu_render(K, params, launch=K.kt_launch(1, 256, 0, 4), want=want)
+    assert base["stats"].rays == 512 * 512 and sum(base["stats"].fate_count) == 512 * 512
+    assert base["stats"].evals == g["stats"].evals == int(base["n_evals"].astype(np.int64).sum())
+    for key, v in base.items():
+        if key != "stats":
+            np.testing.assert_array_equal(g[key].view(np.uint8), v.view(np.uint8), err_msg=key)
+
+
 def test_max_steps_forces_fate(K):
     params = dict(W.kerr_ring(0.9, n=32), max_steps=10)
     _announce("max_steps=10")
