@@ -73,7 +73,7 @@ constexpr int64_t W3_MIN_RAYS_PER_LANE = 10;
 // ticket fetch instead of 4 measured 25% faster on 512x512 images (2 rays
 // per lane of the 2-wave grid), even at 724x724 (4 rays per lane), and
 // worse from ~8 rays per lane on, where a wave holding ids that no one
-// else can take delays the end (the 1024x1024 headline image).
+// else can take delays the end (the 1024x1024 Kerr a = 0.9 image).
 constexpr int64_t SMALL_MIN_RAYS_PER_LANE = 1, SMALL_MAX_RAYS_PER_LANE = 4;
 constexpr int32_t DEFAULT_BATCH = 4, SMALL_BATCH = 16;
 

@@ -80,7 +80,7 @@ def test_unit_counts_are_the_benchmark_basis(counter):
 
 
 def test_oracle_matrix_form_overcounts(counter):
-    """The oracle's own arithmetic per evaluation on a few headline pixels:
+    """The oracle's own arithmetic per evaluation on a few pixels of the 1024^2 Kerr a = 0.9 image:
     several times the Carter-form figure (it builds the full inverse metric
     and its derivatives, multiplies zero tableau entries and recomputes the
     metric for H), so it is reported, not used."""

@@ -68,7 +68,7 @@ def _ring_radii(r0=1000.0):
 
 def test_einstein_ring_radii_by_quadrature():
     """The primary ring at image radius 46.188M lies outside the +-12M field
-    of the headline image (it needs the +-60M one); the 3 pi and 5 pi rings
+    of the 1024^2 Kerr ring image (it needs the +-60M one); the 3 pi and 5 pi rings
     hug the shadow edge sqrt(27) sqrt(1 - 2/r0)."""
     r1, r3, r5 = _ring_radii()
     edge = math.sqrt(27.0) * math.sqrt(1.0 - 2.0 / 1000.0)
