@@ -299,11 +299,6 @@ __device__ __forceinline__ void put_grads(const AdjParams& P, int32_t ray, int s
     if (P.grad_rin) P.grad_rin[ray] = gr;
 }
 
-// One wave per SIMD: the unrolled step VJP wants about 500 VGPRs, and a
-// two-wave budget (256) spills enough to run 1.6x slower.
-#ifndef KT_ADJ_WAVES_PER_EU
-#define KT_ADJ_WAVES_PER_EU 1
-#endif
 // One entry t of the work list on this lane.  An entry among the first
 // n_long (the split rays) that fits the split-ray store runs the forward
 // pass into the store, seeds its cotangent, reserves its segment items and
@@ -366,6 +361,11 @@ __device__ __forceinline__ void adjoint_entry(const AdjParams& P, const Spacetim
     put_grads(P, ray, status, ga, gi, gr);
 }
 
+// One wave per SIMD: the unrolled step VJP wants about 500 VGPRs, and a
+// two-wave budget (256) spills enough to run 1.6x slower.
+#ifndef KT_ADJ_WAVES_PER_EU
+#define KT_ADJ_WAVES_PER_EU 1
+#endif
 // Lanes take entries of the work list from an atomic ticket.
 __global__ void __launch_bounds__(ADJ_BLOCK) __attribute__((amdgpu_waves_per_eu(KT_ADJ_WAVES_PER_EU)))
 adjoint_kernel(const AdjParams P) {
