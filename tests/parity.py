@@ -103,7 +103,7 @@ def neighbours(pix, nx, ny):
     return np.stack(out, 1)
 
 
-def sampled_parity(gpu, nx, ny, sample, trace, keys=(), rtol=1e-8, frac=1e-3, extra_rtol=None):
+def sampled_parity(gpu, nx, ny, sample, trace, keys=(), rtol=1e-8, frac=1e-3, extra_rtol=None, max_order=1):
     """The parity rules on a sample of a full-size image.
 
     gpu: dict of full-image numpy arrays (fate, n_cross and the keys);
@@ -119,7 +119,8 @@ def sampled_parity(gpu, nx, ny, sample, trace, keys=(), rtol=1e-8, frac=1e-3, ex
     values were compared).  Asserts: fate mismatches only next
     to an oracle boundary and at most frac of the sample; the keys within
     rtol (extra_rtol: {key: (rtol, min |value|)} overrides) where fate and
-    image order agree, image order <= 1 and no oracle boundary is near."""
+    image order agree, image order <= max_order and no oracle boundary is
+    near."""
     sample = np.asarray(sample, np.int64)
     g_f = np.asarray(gpu["fate"]).ravel()
     has_nc = "n_cross" in gpu
@@ -155,7 +156,7 @@ def sampled_parity(gpu, nx, ny, sample, trace, keys=(), rtol=1e-8, frac=1e-3, ex
     assert mism.sum() <= allowed, f"{mism.sum()} fate mismatches > {allowed} ({frac:.1e} of {sample.size})"
     ok = ~mism & ~o_near
     if has_nc:
-        ok &= (g_c[sample] == o_c_s) & (o_c_s <= 1)
+        ok &= (g_c[sample] == o_c_s) & (o_c_s <= max_order)
     stats = {"sample": int(sample.size), "oracle_rays": int(sample.size + extra.size),
              "fate_mismatches": int(mism.sum()), "compared": int(ok.sum())}
     for key in keys:

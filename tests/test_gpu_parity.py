@@ -188,6 +188,39 @@ def test_small_render_default_ticket_batch(K):
             np.testing.assert_array_equal(g[key].view(np.uint8), v.view(np.uint8), err_msg=key)
 
 
+def test_higher_order_disk_images(K):
+    """Disk images of order 2 and more (rays that cross the equatorial plane
+    twice outside the disk before they hit it, winding round the photon
+    sphere), which the value checks elsewhere leave out: the 80-degree
+    Schwarzschild disk over +-7M at 4096x4096 (0.0034M pixels: the order-2
+    ring is a few pixels wide).  600 sampled order >= 2 pixels with their
+    neighbourhoods against the oracle: fates under the boundary rule, and
+    r_hit, g and I, where fate and order agree and no boundary is near,
+    under the rounding rule (each pixel within max(1e-8, 10 S, 2 s_p), s_p
+    the oracle's own one-ulp sensitivity there and S its 99.9th
+    percentile)."""
+    n = 4096
+    params = dict(W.schwarzschild_disk(n=n), fov_x=7.0, fov_y=7.0)
+    _announce("higher-order disk images", n, "+-7M")
+    img = gpu_render(K, params, want=("fate", "n_cross", "r_hit", "g", "intensity"))
+    cand = np.flatnonzero((img["fate"] == O.DISK) & (img["n_cross"] >= 2))
+    assert cand.size > 1000
+    rng = np.random.default_rng(4096)
+    sample = np.sort(rng.choice(cand, 600, replace=False)).astype(np.int64)
+    s = O.Setup(**params)
+    o, stats, ok = P.sampled_parity(img, n, n, sample, lambda pix: O.trace_pixels(s, pix), max_order=255)
+    assert ok.sum() > 100, stats
+    pix = sample[ok]
+    xy = np.array([O.pixel_xy(s, int(p % n), int(p // n)) for p in pix])
+    res = {}
+    for key in ("r_hit", "g", "intensity"):
+        sens = P.ulp_sensitivity(lambda x, y: O.trace_xy(s, x, y), xy[:, 0].copy(), xy[:, 1].copy(), key)
+        res[key] = P.check_values_rounding({key: img[key][pix]}, {key: o[key][ok]}, key,
+                                           np.ones(pix.size, bool), sens)
+    print(f"[higher-order images] {stats}; max rel err and the oracle's p99.9 one-ulp sensitivity {res}",
+          flush=True)
+
+
 def test_max_steps_forces_fate(K):
     params = dict(W.kerr_ring(0.9, n=32), max_steps=10)
     _announce("max_steps=10")
