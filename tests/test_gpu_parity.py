@@ -188,20 +188,22 @@ def test_small_render_default_ticket_batch(K):
             np.testing.assert_array_equal(g[key].view(np.uint8), v.view(np.uint8), err_msg=key)
 
 
-def test_higher_order_disk_images(K):
+@pytest.mark.parametrize("a", [0.0, 0.9])
+def test_higher_order_disk_images(K, a):
     """Disk images of order 2 and more (rays that cross the equatorial plane
     twice outside the disk before they hit it, winding round the photon
-    sphere), which the value checks elsewhere leave out: the 80-degree
-    Schwarzschild disk over +-7M at 4096x4096 (0.0034M pixels: the order-2
-    ring is a few pixels wide).  600 sampled order >= 2 pixels with their
+    sphere), which the value checks elsewhere leave out: the 80-degree disk
+    from 6M to 30M around a Schwarzschild and an a = 0.9 Kerr hole, over
+    +-7M at 4096x4096 (0.0034M pixels: the order-2 ring is a few pixels
+    wide).  600 sampled order >= 2 pixels with their
     neighbourhoods against the oracle: fates under the boundary rule, and
     r_hit, g and I, where fate and order agree and no boundary is near,
     under the rounding rule (each pixel within max(1e-8, 10 S, 2 s_p), s_p
     the oracle's own one-ulp sensitivity there and S its 99.9th
     percentile)."""
     n = 4096
-    params = dict(W.schwarzschild_disk(n=n), fov_x=7.0, fov_y=7.0)
-    _announce("higher-order disk images", n, "+-7M")
+    params = dict(W.schwarzschild_disk(n=n), a=a, fov_x=7.0, fov_y=7.0)
+    _announce("higher-order disk images", n, "+-7M, a =", a)
     img = gpu_render(K, params, want=("fate", "n_cross", "r_hit", "g", "intensity"))
     cand = np.flatnonzero((img["fate"] == O.DISK) & (img["n_cross"] >= 2))
     assert cand.size > 1000
