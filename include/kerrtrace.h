@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define KT_VERSION_NUMBER 202
+#define KT_VERSION_NUMBER 203
 
 /* return codes */
 #define KT_OK 0
@@ -194,6 +194,14 @@ typedef struct kt_stats {
     uint64_t evals_fp32;     /* evaluations whose mass term ran in FP32 */
     uint64_t fallback_rays;  /* MIXED: rays re-run in FP64 */
     uint64_t fate_count[8];  /* histogram of final fates */
+    double trace_ms;         /* milliseconds the trace launches took: between two readings
+                                of the GPU's constant-rate wall clock, enqueued on the
+                                render's stream just before the first trace kernel and
+                                just after the last (both passes of a MIXED render and
+                                the list compaction between them); 0 if the device
+                                reports no rate.  Taken on the device, so no host
+                                synchronisation; the readings are only enqueued when
+                                stats is set */
 } kt_stats;
 
 /* Per-pixel outputs: device arrays of nx*ny entries, row-major j*nx + i.

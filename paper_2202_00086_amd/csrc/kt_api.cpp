@@ -60,6 +60,22 @@ int device_cus() {
     return cache[dev];
 }
 
+// The wall clock rate of the current device in kHz (cached per device id;
+// 0 when the device reports none).
+double device_wall_khz() {
+    static std::mutex mu;
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0.0;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cache[dev] == 0) {
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = -1;
+        cache[dev] = khz;
+    }
+    return cache[dev] > 0 ? static_cast<double>(cache[dev]) : 0.0;
+}
+
 // Which build of the trace kernels a launch runs (both give the same
 // outputs bit for bit).  The 3-wave form (kt_trace_w3.hip) steps ~7% faster,
 // but each ray takes longer in wall time, so the end of a persistent launch,
@@ -383,6 +399,7 @@ int render_images(const kt::Image* table, int32_t n_images, int64_t n_rays, cons
     }
     p.persistent = ln.persistent ? 1 : 0;
     p.from_list = 0;
+    p.wall_khz = out->stats ? device_wall_khz() : 0.0;
     const int64_t lane_grid = (n_rays + ln.block - 1) / ln.block;
     const bool w3 = three_wave_form(ln, n_rays);
     int grid;
@@ -410,6 +427,8 @@ int render_images(const kt::Image* table, int32_t n_images, int64_t n_rays, cons
         return fail(KT_EDEVICE, "workspace init launch failed: %s", hipGetErrorString(hipGetLastError()));
     if (p.perm && kt::launch_order(p, hip_stream))
         return fail(KT_EDEVICE, "dispatch order launch failed: %s", hipGetErrorString(hipGetLastError()));
+    if (out->stats && kt::launch_stamp(p, kt::ACC_T0, hip_stream))
+        return fail(KT_EDEVICE, "clock stamp launch failed: %s", hipGetErrorString(hipGetLastError()));
     if ((w3 ? kt_w3::launch_trace : kt::launch_trace)(p, grid, ln.block, hip_stream))
         return fail(KT_EDEVICE, "trace kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
     if (p.precision == KT_MIXED) {
@@ -422,6 +441,8 @@ int render_images(const kt::Image* table, int32_t n_images, int64_t n_rays, cons
         if ((w3 ? kt_w3::launch_trace_fallback : kt::launch_trace_fallback)(p, grid2, ln.block, hip_stream))
             return fail(KT_EDEVICE, "fallback trace launch failed: %s", hipGetErrorString(hipGetLastError()));
     }
+    if (out->stats && kt::launch_stamp(p, kt::ACC_T1, hip_stream))
+        return fail(KT_EDEVICE, "clock stamp launch failed: %s", hipGetErrorString(hipGetLastError()));
     if ((out->r_hit || out->g || out->intensity) && kt::launch_disk_obs(p, hip_stream))
         return fail(KT_EDEVICE, "disk observables launch failed: %s", hipGetErrorString(hipGetLastError()));
     if (out->ring && kt::launch_ring(p, hip_stream))

@@ -10,6 +10,7 @@
 namespace kt {
 
 constexpr int ACC_EVALS = 0, ACC_EVALS_FP32 = 1;  // acc[8..15]: fate histogram
+constexpr int ACC_T0 = 2, ACC_T1 = 3;  // wall clock ticks just before and just after the trace launches
 
 struct Outputs {
     uint8_t* fate;
@@ -79,6 +80,7 @@ struct Params {
     // launch
     int32_t persistent, batch;
     int32_t from_list;  // take ray ids from fb_list[0 .. *fb_count)
+    double wall_khz;    // the device's wall clock rate, kHz (0: unknown)
 };
 
 // Bins of the device counting sorts (dispatch order, adjoint work list), and
@@ -280,6 +282,7 @@ int launch_ring(const Params& p, void* stream);
 int launch_sky(const Params& p, void* stream);  // needs theta_f and phi_f outputs
 int launch_disk_obs(const Params& p, void* stream);
 int launch_stats(const Params& p, void* stream);
+int launch_stamp(const Params& p, int slot, void* stream);  // acc[slot] = the wall clock now
 int launch_init_rays(const Params& p, double* state, uint8_t* invalid, void* stream);
 int trace_max_blocks_per_cu(const Params& p, int block);
 

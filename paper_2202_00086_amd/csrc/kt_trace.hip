@@ -801,14 +801,24 @@ __global__ void fate_hist_kernel(const uint8_t* __restrict__ fate, int64_t n, un
     if (threadIdx.x < 8 && hist[threadIdx.x]) atomicAdd(acc + 8 + threadIdx.x, static_cast<unsigned long long>(hist[threadIdx.x]));
 }
 
+// One reading of the GPU's constant-rate wall clock into acc[slot].  Enqueued
+// just before the first trace launch and just after the last one when a
+// render asks for statistics, so the trace kernels themselves carry no timing
+// code.
+__global__ void stamp_kernel(unsigned long long* acc, int slot) {
+    if (threadIdx.x == 0) acc[slot] = static_cast<unsigned long long>(wall_clock64());
+}
+
 __global__ void stats_kernel(const unsigned long long* acc, const uint32_t* fb_count, int64_t n_rays,
-                             kt_stats* out) {
+                             double wall_khz, kt_stats* out) {
     if (threadIdx.x == 0) {
         out->rays = static_cast<uint64_t>(n_rays);
         out->evals = acc[ACC_EVALS];
         out->evals_fp32 = acc[ACC_EVALS_FP32];
         out->fallback_rays = *fb_count;
         for (int k = 0; k < 8; ++k) out->fate_count[k] = acc[8 + k];
+        const unsigned long long t0 = acc[ACC_T0], t1 = acc[ACC_T1];
+        out->trace_ms = (wall_khz > 0.0 && t1 > t0) ? static_cast<double>(t1 - t0) / wall_khz : 0.0;
     }
 }
 
@@ -1025,7 +1035,12 @@ int launch_stats(const Params& p, void* stream) {
                        static_cast<hipStream_t>(stream), p.out.fate, n, p.acc);
     if (check_launch()) return -1;
     hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), p.acc,
-                       p.fb_count, n, p.out.stats);
+                       p.fb_count, n, p.wall_khz, p.out.stats);
+    return check_launch();
+}
+
+int launch_stamp(const Params& p, int slot, void* stream) {
+    hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), p.acc, slot);
     return check_launch();
 }
 

@@ -74,7 +74,7 @@ class kt_launch(C.Structure):
 
 class kt_stats(C.Structure):
     _fields_ = [("rays", C.c_uint64), ("evals", C.c_uint64), ("evals_fp32", C.c_uint64),
-                ("fallback_rays", C.c_uint64), ("fate_count", C.c_uint64 * 8)]
+                ("fallback_rays", C.c_uint64), ("fate_count", C.c_uint64 * 8), ("trace_ms", C.c_double)]
 
 
 OUTPUT_FIELDS = ("fate", "r_hit", "g", "intensity", "max_abs_h", "max_rel_h", "psi", "deflection",

@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared_functions():
         assert hasattr(lib, name), name
     assert set(K.EXPORTED) == set(_declared_functions())
-    assert K.kt_version() == 202
+    assert K.kt_version() == 203
 
 
 def test_struct_layouts_match_header():
@@ -55,7 +55,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(K.kt_integrator) == 8 + 8 * 8 + 8 + 8  # checkpoint_every and split_above
     assert K.kt_integrator.split_above.offset == 84
     assert C.sizeof(K.kt_launch) == 20
-    assert C.sizeof(K.kt_stats) == 12 * 8
+    assert C.sizeof(K.kt_stats) == 13 * 8
     assert C.sizeof(K.kt_outputs) == 17 * 8
     assert C.sizeof(K.kt_image) == 40 + 32 + 56 + 40
 

@@ -223,6 +223,30 @@ def test_higher_order_disk_images(K, a):
           flush=True)
 
 
+def test_launch_statistics_trace_time(K):
+    """kt_stats.trace_ms, two readings of the device's wall clock enqueued
+    just before the first trace launch and just after the last, lies within
+    the render's HIP-event time (which also holds the dispatch sort and the
+    post-passes) and covers most of it; a mixed render's covers both passes."""
+    import torch
+    for prec in (K.FP64, K.MIXED):
+        params = dict(W.kerr_ring(0.9, n=512), precision=prec)
+        _announce("trace time statistic", prec)
+        r = K.Renderer(device="cuda:0", **params)
+        r.render()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        r.render()
+        b.record()
+        torch.cuda.synchronize()
+        ev = a.elapsed_time(b)
+        st = K.read_stats(r.out)
+        print(f"[stats] precision {prec}: trace_ms {st.trace_ms:.3f}, HIP events {ev:.3f} ms", flush=True)
+        assert 0.0 < st.trace_ms <= 1.02 * ev + 0.02
+        assert st.trace_ms >= 0.8 * ev - 0.2
+
+
 def test_max_steps_forces_fate(K):
     params = dict(W.kerr_ring(0.9, n=32), max_steps=10)
     _announce("max_steps=10")
