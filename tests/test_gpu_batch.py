@@ -72,6 +72,7 @@ def _compare_with_singles(K, br, g, images, integ):
     st = g["stats"]
     assert st.rays == br.n
     assert st.evals == evals
+    assert st.trace_ms > 0.0
     assert list(st.fate_count[:8]) == fates.tolist()
 
 

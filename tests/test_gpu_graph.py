@@ -72,3 +72,4 @@ def test_captured_render_replays_equal_eager(K, case):
             np.testing.assert_array_equal(got[key].view(np.uint8), v.view(np.uint8), err_msg=f"replay {rep} {key}")
         st = K.read_stats(r.out)
         assert st.evals == stats_eager.evals and list(st.fate_count) == list(stats_eager.fate_count)
+        assert st.trace_ms > 0.0  # the clock stamps replay with the graph
