@@ -211,7 +211,7 @@ def run_form(K, torch, params, steps, warmup, launch=None):
            "launch_ms": sum(launch_ms) / len(launch_ms), "launch_ms_min": min(launch_ms),
            "rays": n, "evals": int(st.evals), "evals_fp32": int(st.evals_fp32),
            "fallback_rays": int(st.fallback_rays), "fates": [int(c) for c in st.fate_count[:6]],
-           "out": r.out}
+           "trace_ms_last": float(st.trace_ms), "out": r.out}
     res.update(h_stats(torch, r.out["max_rel_h"]))
     if "n_steps" in r.out:
         res["steps_accepted"] = int(r.out["n_steps"].to(torch.int64).sum().item())
@@ -655,7 +655,11 @@ def main():
                     "hand_count_117.3_per_eval": main_form["evals"] * FLOP_PER_EVAL_HAND_COUNT / launch_s / PEAK_FP64_VECTOR,
                     "survey_estimate_150_per_eval": main_form["evals"] * FLOP_PER_EVAL_SURVEY_ESTIMATE / launch_s / PEAK_FP64_VECTOR},
                 "evals_per_launch": main_form["evals"], "steps_accepted_per_launch": main_form["steps_accepted"],
-                "launch_ms": main_form["launch_ms"]}
+                "launch_ms": main_form["launch_ms"],
+                # the last timed render's trace launch alone, on the GPU's wall
+                # clock (kt_stats.trace_ms): a cross-check of launch_ms, which
+                # also holds the dispatch sort and the post-passes
+                "trace_ms_device_clock": main_form["trace_ms_last"]}
 
     cb = o_full = None
     if not args.no_cpu:
