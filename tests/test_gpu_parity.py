@@ -421,6 +421,55 @@ def test_polar_rays_wind_through_the_axis(K):
         assert tr[:, 2].min() < 0.0 or tr[:, 2].max() > math.pi
 
 
+@pytest.mark.parametrize("a", [1.0, -1.0])
+def test_extremal_spin(K, a):
+    """|a| = M, where the horizon and the co-rotating photon orbit meet at
+    r = M.  One equatorial row (i = 90 deg, y = 0, 4096 pixels over +-8M):
+    every pixel has the fate of the closed-form edges in b = L/E (the
+    capture buffer sets the co-rotating one at b = 2M + 0.01M, the
+    counter-rotating photon orbit the other at -7M) and the oracle's, and
+    the pixels between b = 2M and 2M + 0.01M are captured.  Then a 96x96
+    ring image at i = 60 deg against the oracle under the parity rules."""
+    from tests.test_oracle_shadow import extremal_edges
+    row = dict(W.kerr_ring(a, n=8), incl=math.pi / 2, fov_x=8.0, fov_y=8.0, nx=4096, ny=1)
+    _announce("extremal spin row", a)
+    g = gpu_render(K, row)
+    o = ora_render(row)
+    s = O.Setup(**row)
+    b = np.empty(4096)
+    for i in range(4096):
+        x, y = O.pixel_xy(s, i, 0)
+        assert y == 0.0
+        st, _ = O.camera_ray(1.0, a, row["r_obs"], row["incl"], x, y)
+        b[i] = st[6] / st[5]
+    lo, hi = extremal_edges(a)
+    want = np.where((b > lo) & (b < hi), O.CAPTURED, O.ESCAPED)
+    np.testing.assert_array_equal(o["fate"], want)
+    np.testing.assert_array_equal(g["fate"], want)
+    band = (np.abs(b) > 2.0) & (np.abs(b) < 2.01)
+    assert band.sum() >= 2 and (g["fate"][band] == O.CAPTURED).all()
+    esc = want == O.ESCAPED
+    P.check_values(g, o, "deflection", esc, rtol=1e-8)
+
+    params = W.kerr_ring(a, n=96)
+    _announce("extremal spin image", a)
+    g = gpu_render(K, params)
+    o = ora_render(params)
+    P.check_fates(g["fate"], o["fate"], 96, 96)
+    m = P.value_mask(g, o, 96, 96)
+    assert m.sum() > 0.9 * 96 * 96
+    P.check_values(g, o, "deflection", m, rtol=1e-8)
+    P.check_values(g, o, "psi", m & (o["psi"] > 1e-6), rtol=1e-7)
+    # every ray within the 1e-10 budget on both sides; the distributions are
+    # compared on escaped rays only: at the capture radius of an extremal
+    # hole (Delta = (r - M)^2 ~ 1e-4) the oracle's numerically inverted
+    # t-phi block puts relative rounding of ~eps (r^2 + a^2)^2 / Delta into
+    # its |H|_rel, above the truncation residues that the percentiles compare
+    assert (g["max_rel_h"][m] <= 1e-10).all() and (o["max_rel_h"][m] <= 1e-10).all()
+    P.check_max_h(g, o, "max_rel_h", m & (o["fate"] == O.ESCAPED), budget=1e-10)
+    np.testing.assert_array_equal(g["ring"], O.ring_flags(96, 96, g["deflection"]))
+
+
 def test_resolved_einstein_ring(K):
     """a = 0, i = 60 deg, +-60M at 256x256, so that the primary Einstein ring
     of the source behind the hole (image radius 46.188M by the orbit

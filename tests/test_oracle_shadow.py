@@ -7,6 +7,10 @@
   potential R(r) (no ODE), and the finite-distance form of the analytic
   critical curve eq:anal / eq:xie (Sect. 3.2), which reduces to eq:anal as
   r0 -> infinity;
+- extremal Kerr (|a| = M), equatorial rays: the radial potential factors,
+  so the fate edges along the equator are closed forms that include the
+  capture buffer (b = 2M + delta_r on the co-rotating side, -7M on the
+  counter-rotating one);
 - image symmetries.
 """
 import math
@@ -164,3 +168,60 @@ def test_kerr_equatorial_symmetry():
     # and not under x -> -x (frame dragging): the shadow is shifted
     fs = (f == O.CAPTURED)
     assert (fs != fs[:, ::-1]).any()
+
+
+def extremal_edges(a, M=1.0, cap_buffer=0.01):
+    """Fate edges in b = L/E for equatorial rays of extremal Kerr (a = +-M).
+
+    With Q = 0 and a = M the radial potential is
+    R(r) = (r^2 + M^2 - M b)^2 - (r - M)^2 (b - M)^2 (E = 1), whose factor
+    r^2 + M^2 - M b - (r - M)(b - M) = r (r - b + M) gives the outermost
+    turning point r_t = b - M of a co-rotating ray with b > 2M.  The photon
+    orbit of that side sits on the horizon (r = M, b = 2M), so what decides
+    capture there is the buffer: the ray is stopped once r < r_+ + delta_r =
+    M + delta_r, i.e. for b < 2M + delta_r.  The counter-rotating photon
+    orbit is at r = 4M with b = -7M, outside the buffer.  For a = -M the
+    picture is mirrored in b.  Returns (b_lo, b_hi): captured iff
+    b_lo < b < b_hi."""
+    lo, hi = -7.0 * M, 2.0 * M + cap_buffer
+    return (lo, hi) if a > 0 else (-hi, -lo)
+
+
+def _x_for_b(a, r0, incl, b):
+    """The image-plane x (at y = 0) whose ray has L/E = b: bisection on the
+    oracle's camera relations, which are monotonic in x."""
+    def b_of(x):
+        st, _ = O.camera_ray(1.0, a, r0, incl, x, 0.0)
+        return st[6] / st[5]
+    lo, hi = -20.0, 20.0
+    rising = b_of(hi) > b_of(lo)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if (b_of(mid) > b) == rising:
+            hi = mid
+        else:
+            lo = mid
+    return 0.5 * (lo + hi)
+
+
+@pytest.mark.parametrize("a", [1.0, -1.0])
+def test_extremal_kerr_equatorial_edges(a):
+    """|a| = M, i = 90 deg, y = 0, r0 = 1000M, DP45: rays aimed 0.002M to
+    0.02M on either side of each closed-form edge get the predicted fate.
+    Without the buffer the co-rotating edge would sit at b = 2M, so the rays
+    at 2M + 0.005M and 2M + 0.008M would escape; a wrong horizon, spin sign
+    or Delta moves the edges by more than these offsets."""
+    r0, incl = 1000.0, math.pi / 2
+    lo, hi = extremal_edges(a)
+    bs, want = [], []
+    for e in (lo, hi):
+        for d in (-0.02, -0.005, -0.002, 0.002, 0.005, 0.02):
+            bs.append(e + d)
+            want.append(O.CAPTURED if lo < e + d < hi else O.ESCAPED)
+    xs = np.array([_x_for_b(a, r0, incl, b) for b in bs])
+    for x, b in zip(xs, bs):
+        st, _ = O.camera_ray(1.0, a, r0, incl, x, 0.0)
+        assert st[6] / st[5] == pytest.approx(b, abs=1e-12)
+    s = O.Setup(a=a, r_obs=r0, incl=incl, method=O.DP45, rtol=1e-12, atol=1e-12)
+    o = O.trace_xy(s, xs, np.zeros_like(xs))
+    np.testing.assert_array_equal(o["fate"], np.array(want))

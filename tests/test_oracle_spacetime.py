@@ -3,7 +3,8 @@
 Each check compares the oracle with something it does not compute itself:
 textbook identities of the Kerr metric, a numerical 4x4 inverse, a
 complex-step derivative of H built on that inverse, Carter's separated form
-and the Schwarzschild limit.
+and the Schwarzschild limit; and the rounding of its relative residual
+next to a horizon against a 50-digit evaluation.
 """
 import math
 
@@ -124,3 +125,42 @@ def test_rhs_phi_independent():
     z1 = [5.0, 1.1, 0.0, 0.3, 2.0]
     z2 = [5.0, 1.1, 2.7, 0.3, 2.0]
     np.testing.assert_array_equal(O.rhs(1.0, 0.7, z1, 0.9, 2.1), O.rhs(1.0, 0.7, z2, 0.9, 2.1))
+
+
+@pytest.mark.parametrize("a,r", [(1.0, 1.0105), (1.0, 1.05), (0.998, 1.075), (0.9, 1.45)])
+def test_relative_residual_rounding_near_the_horizon(a, r):
+    """The oracle's |H|_rel of exactly null states (p_r from H = 0 in 50-digit
+    arithmetic, then rounded to double) against a 50-digit evaluation of the
+    same rounded state: the oracle's own rounding stays within
+    2 eps (r^2 + a^2)^2 / Delta.  The t-phi block of its metric inverse
+    divides by g_t_phi^2 - g_tt g_phi_phi = Delta sin^2 theta, formed from
+    terms of size (r^2 + a^2)^2; next to an extremal horizon, where
+    Delta = (r - M)^2 is ~1e-4 at the capture radius, that rounding reaches
+    ~1e-12, above the truncation residues of an rtol 1e-12 integration."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 50
+    rng = np.random.default_rng(11)
+    M = 1.0
+    bound = 2.0 * np.finfo(float).eps * (r * r + a * a) ** 2 / (r * r - 2 * M * r + a * a)
+    errs = []
+    for _ in range(100):
+        th, b, pth = float(rng.uniform(0.3, 2.8)), float(rng.uniform(-6.5, 1.9)), float(rng.uniform(-1.0, 1.0))
+        R, TH, A = mp.mpf(r), mp.mpf(th), mp.mpf(a)
+        Del = R * R - 2 * R + A * A
+        T = b / mp.sin(TH) - A * mp.sin(TH)
+        W = R * R + A * A - A * b
+        pr2 = (W * W / Del - pth * pth - T * T) / Del
+        if pr2 <= 0:
+            continue
+        z = np.array([r, th, 0.0, -float(mp.sqrt(pr2)), pth])
+        PR, PTH = mp.mpf(z[3]), mp.mpf(pth)
+        K = Del * PR * PR + PTH * PTH + T * T - W * W / Del
+        D = Del * PR * PR + PTH * PTH + T * T + W * W / Del
+        exact = float(abs(K) / D)
+        errs.append(abs(O.hamiltonian_rel(M, a, z, 1.0, b) - exact))
+    errs = np.array(errs)
+    assert errs.size > 50
+    assert errs.max() <= bound, (errs.max(), bound)
+    if a == 1.0 and r < 1.02:
+        # the effect is real at the extremal capture radius, not a loose bound
+        assert np.median(errs) > 1e-13
