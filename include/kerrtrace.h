@@ -161,8 +161,9 @@ typedef struct kt_integrator {
 } kt_integrator;
 
 /* Launch shape.  Pass NULL for the defaults: persistent, block 256,
-   blocks_per_cu 0, batch 4 (16 when the render has 1 to 4 rays per lane of
-   the grid), KT_ORDER_RING.
+   blocks_per_cu 0, batch 4, KT_ORDER_RING.  In a persistent launch each
+   wave's first fetch from the ticket takes 64 ids (one per lane); batch
+   applies to the fetches after it.
    The trace kernels exist in two builds with bit-identical outputs: one for
    2 waves per SIMD and one for 3 (fewer registers, a few more instructions
    per step).  A persistent launch runs the 3-wave build when its shape asks
@@ -175,7 +176,7 @@ typedef struct kt_launch {
                                0: one ray per lane, no refill */
     int32_t block;          /* threads per workgroup: 64, 128 or 256 */
     int32_t blocks_per_cu;  /* persistent grid = CUs * blocks_per_cu; 0 = occupancy */
-    int32_t batch;          /* ray ids taken per ticket fetch, 1..4096 */
+    int32_t batch;          /* ray ids taken per ticket fetch after a wave's first, 1..4096 */
     int32_t order;          /* KT_ORDER_RING (0) or KT_ORDER_ROWS: the order rays go out in */
 } kt_launch;
 

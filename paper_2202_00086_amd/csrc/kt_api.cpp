@@ -84,14 +84,7 @@ double device_wall_khz() {
 // can run a launch shape of 3 or more waves per SIMD.
 constexpr int64_t W3_MIN_RAYS_PER_LANE = 10;
 
-// The default shape's ticket batch.  With a few rays per lane the whole
-// launch is the start and the end of the schedule, and taking 16 ids per
-// ticket fetch instead of 4 measured 25% faster on 512x512 images (2 rays
-// per lane of the 2-wave grid), even at 724x724 (4 rays per lane), and
-// worse from ~8 rays per lane on, where a wave holding ids that no one
-// else can take delays the end (the 1024x1024 Kerr a = 0.9 image).
-constexpr int64_t SMALL_MIN_RAYS_PER_LANE = 1, SMALL_MAX_RAYS_PER_LANE = 4;
-constexpr int32_t DEFAULT_BATCH = 4, SMALL_BATCH = 16;
+constexpr int32_t DEFAULT_BATCH = 4;  // ids per ticket fetch after a wave's first
 
 bool three_wave_form(const kt_launch& ln, int64_t n_rays) {
     if (!ln.persistent) return false;
@@ -414,11 +407,6 @@ int render_images(const kt::Image* table, int32_t n_images, int64_t n_rays, cons
     }
     if (grid < 1) grid = 1;
     p.batch = ln.batch;
-    if (!launch && p.persistent) {
-        const int64_t lanes = static_cast<int64_t>(grid) * ln.block;
-        if (n_rays >= SMALL_MIN_RAYS_PER_LANE * lanes && n_rays <= SMALL_MAX_RAYS_PER_LANE * lanes)
-            p.batch = SMALL_BATCH;
-    }
 
     if (batch && kt::launch_upload_images(table, n_images, reinterpret_cast<kt::Image*>(ws + w.images),
                                           hip_stream))

@@ -218,9 +218,15 @@ trace_kernel(const Hot hp) {
     const uint32_t lane = __lane_id();
     const uint32_t n_total = P.from_list ? *P.fb_count : static_cast<uint32_t>(P.n_rays);
 
-    // this wave's queue of ray ids [q_next, q_end)
+    // this wave's queue of ray ids [q_next, q_end).  A persistent wave's
+    // first fetch takes 64 ids, one per lane, in one atomic; later fetches
+    // take P.batch.  Taken in batch-sized pieces, the start of the launch was
+    // a burst of 64 / batch serial round trips per wave on one address, and
+    // the wave's first rays came from interleaved places in the dispatch
+    // order instead of one run of similar cost.
     uint32_t q_next, q_end;
     bool exhausted;
+    bool first_fetch = P.persistent != 0;
     if (P.persistent) {
         q_next = q_end = 0;
         exhausted = false;
@@ -248,14 +254,16 @@ trace_kernel(const Hot hp) {
                 if (exhausted) break;
                 const int leader = __ffsll(idle) - 1;
                 uint32_t base = 0;
-                if (static_cast<int>(lane) == leader) base = atomicAdd(P.ticket, static_cast<uint32_t>(P.batch));
+                const uint32_t take = first_fetch ? 64u : static_cast<uint32_t>(P.batch);
+                first_fetch = false;
+                if (static_cast<int>(lane) == leader) base = atomicAdd(P.ticket, take);
                 base = static_cast<uint32_t>(__shfl(static_cast<int>(base), leader));
                 if (base >= n_total) {
                     exhausted = true;
                     break;
                 }
                 q_next = base;
-                q_end = min(base + static_cast<uint32_t>(P.batch), n_total);
+                q_end = min(base + take, n_total);
             }
             const uint32_t rank = static_cast<uint32_t>(__popcll(idle & ((1ull << lane) - 1ull)));
             const uint32_t avail = q_end - q_next;

@@ -171,21 +171,24 @@ def test_launch_shapes_are_bit_identical(K):
             np.testing.assert_array_equal(g[key].view(np.uint8), v.view(np.uint8), err_msg=key)
 
 
-def test_small_render_default_ticket_batch(K):
-    """A 512x512 disk image has 2 rays per lane of the default grid, where
-    the default launch takes 16 ids per ticket fetch instead of 4: its
-    outputs equal those of an explicit batch-4 launch bit for bit, and every
-    pixel is traced once."""
+def test_small_render_ticket_fetches(K):
+    """A 512x512 disk image has 2 rays per lane of the default grid, so each
+    wave's first fetch of 64 ids covers half of it.  The default launch,
+    ticket batches 1 and 16 after that fetch, and one ray per lane without
+    refill give the same outputs bit for bit, and every pixel is traced once."""
     params = W.differentiable_disk(n=512)
     want = ("fate", "r_hit", "g", "intensity", "n_cross", "n_steps", "n_evals", "max_rel_h")
-    _announce("default ticket batch at 512x512")
+    _announce("ticket fetches at 512x512")
     base = gpu_render(K, params, want=want)
-    g = gpu_render(K, params, launch=K.kt_launch(1, 256, 0, 4), want=want)
     assert base["stats"].rays == 512 * 512 and sum(base["stats"].fate_count) == 512 * 512
-    assert base["stats"].evals == g["stats"].evals == int(base["n_evals"].astype(np.int64).sum())
-    for key, v in base.items():
-        if key != "stats":
-            np.testing.assert_array_equal(g[key].view(np.uint8), v.view(np.uint8), err_msg=key)
+    assert base["stats"].evals == int(base["n_evals"].astype(np.int64).sum())
+    for ln in (K.kt_launch(1, 256, 0, 1), K.kt_launch(1, 256, 0, 16), K.kt_launch(0, 256, 0, 4)):
+        _announce("launch", ln.persistent, ln.block, ln.blocks_per_cu, ln.batch)
+        g = gpu_render(K, params, launch=ln, want=want)
+        assert g["stats"].evals == base["stats"].evals
+        for key, v in base.items():
+            if key != "stats":
+                np.testing.assert_array_equal(g[key].view(np.uint8), v.view(np.uint8), err_msg=key)
 
 
 @pytest.mark.parametrize("a", [0.0, 0.9])
