@@ -80,9 +80,11 @@ double device_wall_khz() {
 // outputs bit for bit).  The 3-wave form (kt_trace_w3.hip) steps ~7% faster,
 // but each ray takes longer in wall time, so the end of a persistent launch,
 // which waits for the last rays, grows; it pays once every lane of a 3-wave
-// grid has about ten rays or more to trace, and it is the only form that
-// can run a launch shape of 3 or more waves per SIMD.
-constexpr int64_t W3_MIN_RAYS_PER_LANE = 10;
+// grid has about seven rays or more to trace (at 1200x1200, 7.3 per lane, it
+// was 3-5% faster on ring, lensing and disk images and 1.4% slower on a
+// q-metric one; at 1024x1024, 5.3 per lane, even to 6% slower), and it is
+// the only form that can run a launch shape of 3 or more waves per SIMD.
+constexpr int64_t W3_MIN_RAYS_PER_LANE = 7;
 
 constexpr int32_t DEFAULT_BATCH = 4;  // ids per ticket fetch after a wave's first
 
