@@ -77,22 +77,24 @@ double device_wall_khz() {
 }
 
 // Which build of the trace kernels a launch runs (both give the same
-// outputs bit for bit).  The 3-wave form (kt_trace_w3.hip) steps ~7% faster,
-// but each ray takes longer in wall time, so the end of a persistent launch,
-// which waits for the last rays, grows; it pays once every lane of a 3-wave
-// grid has about seven rays or more to trace (at 1200x1200, 7.3 per lane, it
-// was 3-5% faster on ring, lensing and disk images and 1.4% slower on a
-// q-metric one; at 1024x1024, 5.3 per lane, even to 6% slower), and it is
-// the only form that can run a launch shape of 3 or more waves per SIMD.
-constexpr int64_t W3_MIN_RAYS_PER_LANE = 7;
+// outputs bit for bit).  The 3-wave form (kt_trace_w3.hip) keeps the VALU
+// busier, but each ray takes longer in wall time, so the end of a persistent
+// launch, which waits for the last rays, grows; it pays once every lane of a
+// 3-wave grid has enough rays to trace, and it is the only form that can run
+// a launch shape of 3 or more waves per SIMD.  Kerr renders: at 1024x1024
+// (5.3 rays per lane) it was 1-3% faster on ring, lensing and disk images, at
+// 724x724 (2.7 per lane) 5% faster on the ring but 4-8% slower on lensing
+// and disk images.  The q-metric's kernel gains less: 2% slower at 1024x1024,
+// 1% faster at 1200x1200 (7.3 per lane).
+constexpr int64_t W3_MIN_RAYS_PER_LANE_KERR = 4, W3_MIN_RAYS_PER_LANE_Q = 7;
 
 constexpr int32_t DEFAULT_BATCH = 4;  // ids per ticket fetch after a wave's first
 
-bool three_wave_form(const kt_launch& ln, int64_t n_rays) {
+bool three_wave_form(const kt_launch& ln, int64_t n_rays, bool qmetric) {
     if (!ln.persistent) return false;
     if (ln.blocks_per_cu > 0) return static_cast<int64_t>(ln.blocks_per_cu) * ln.block >= 3 * 256;
     const int64_t lanes = static_cast<int64_t>(device_cus()) * 4 * 3 * 64;
-    return n_rays >= W3_MIN_RAYS_PER_LANE * lanes;
+    return n_rays >= (qmetric ? W3_MIN_RAYS_PER_LANE_Q : W3_MIN_RAYS_PER_LANE_KERR) * lanes;
 }
 
 double horizon(const kt_spacetime* st) {
@@ -396,7 +398,7 @@ int render_images(const kt::Image* table, int32_t n_images, int64_t n_rays, cons
     p.from_list = 0;
     p.wall_khz = out->stats ? device_wall_khz() : 0.0;
     const int64_t lane_grid = (n_rays + ln.block - 1) / ln.block;
-    const bool w3 = three_wave_form(ln, n_rays);
+    const bool w3 = three_wave_form(ln, n_rays, table[0].metric == KT_METRIC_Q);
     int grid;
     if (p.persistent) {
         const int per_cu = ln.blocks_per_cu > 0 ? ln.blocks_per_cu

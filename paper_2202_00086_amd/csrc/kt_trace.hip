@@ -246,7 +246,22 @@ trace_kernel(const Hot hp) {
 #pragma unroll
     for (int i = 0; i < 5; ++i) y[i] = k1[i] = 0.0;
 
+#if KT_WAVES_PER_EU == 3
+    // With three waves per SIMD the issue arbiter's preference for the
+    // oldest wave runs the three generations of blocks at very different
+    // speeds, and the rays a slow wave holds end the launch late.  Each wave
+    // alternates its priority between 0 and 1 with the parity of its loop
+    // count, which evens out their shares of the issue slots.
+    uint32_t prio_it = 0;
+#endif
     for (;;) {
+#if KT_WAVES_PER_EU == 3
+        if (prio_it & 1u)
+            __builtin_amdgcn_s_setprio(1);
+        else
+            __builtin_amdgcn_s_setprio(0);
+        ++prio_it;
+#endif
         // ---- refill idle lanes from the wave queue -------------------------
         unsigned long long idle = __ballot(ray < 0);
         while (idle != 0ull) {
