@@ -250,16 +250,20 @@ trace_kernel(const Hot hp) {
     // With three waves per SIMD the issue arbiter's preference for the
     // oldest wave runs the three generations of blocks at very different
     // speeds, and the rays a slow wave holds end the launch late.  Each wave
-    // alternates its priority between 0 and 1 with the parity of its loop
-    // count, which evens out their shares of the issue slots.
+    // steps its priority down from 3 to 0 and round again, one level per
+    // loop iteration; the waves' cycles are out of phase, so the highest
+    // priority moves from wave to wave and their shares of the issue slots
+    // even out.
     uint32_t prio_it = 0;
 #endif
     for (;;) {
 #if KT_WAVES_PER_EU == 3
-        if (prio_it & 1u)
-            __builtin_amdgcn_s_setprio(1);
-        else
-            __builtin_amdgcn_s_setprio(0);
+        switch (prio_it & 3u) {
+            case 0: __builtin_amdgcn_s_setprio(3); break;
+            case 1: __builtin_amdgcn_s_setprio(2); break;
+            case 2: __builtin_amdgcn_s_setprio(1); break;
+            default: __builtin_amdgcn_s_setprio(0); break;
+        }
         ++prio_it;
 #endif
         // ---- refill idle lanes from the wave queue -------------------------
