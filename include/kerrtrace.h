@@ -169,8 +169,7 @@ typedef struct kt_integrator {
    per step).  A persistent launch runs the 3-wave build when its shape asks
    for 3 or more waves per SIMD (blocks_per_cu * block >= 768), or, with
    blocks_per_cu 0, when the render has at least 4 rays per lane of a
-   3-wave grid (about 790k rays on 256 CUs; for the q-metric 7, about 1.4M
-   rays); then blocks_per_cu 0 means the
+   3-wave grid (about 790k rays on 256 CUs); then blocks_per_cu 0 means the
    3-wave build's occupancy.  Other launches run the 2-wave build. */
 typedef struct kt_launch {
     int32_t persistent;     /* 1: persistent waves refill lanes from a global ticket;

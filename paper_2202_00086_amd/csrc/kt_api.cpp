@@ -81,20 +81,19 @@ double device_wall_khz() {
 // busier, but each ray takes longer in wall time, so the end of a persistent
 // launch, which waits for the last rays, grows; it pays once every lane of a
 // 3-wave grid has enough rays to trace, and it is the only form that can run
-// a launch shape of 3 or more waves per SIMD.  Kerr renders: at 1024x1024
-// (5.3 rays per lane) it was 1-3% faster on ring, lensing and disk images, at
-// 724x724 (2.7 per lane) 5% faster on the ring but 4-8% slower on lensing
-// and disk images.  The q-metric's kernel gains less: 2% slower at 1024x1024,
-// 1% faster at 1200x1200 (7.3 per lane).
-constexpr int64_t W3_MIN_RAYS_PER_LANE_KERR = 4, W3_MIN_RAYS_PER_LANE_Q = 7;
+// a launch shape of 3 or more waves per SIMD.  With the priority cycle of
+// the 3-wave kernels, at 1024x1024 (5.3 rays per lane) it was 1-3% faster
+// on ring, lensing, disk and q-metric images; at 724x724 (2.7 per lane) 5%
+// faster on a ring image but 4-11% slower on lensing, disk and q-metric ones.
+constexpr int64_t W3_MIN_RAYS_PER_LANE = 4;
 
 constexpr int32_t DEFAULT_BATCH = 4;  // ids per ticket fetch after a wave's first
 
-bool three_wave_form(const kt_launch& ln, int64_t n_rays, bool qmetric) {
+bool three_wave_form(const kt_launch& ln, int64_t n_rays) {
     if (!ln.persistent) return false;
     if (ln.blocks_per_cu > 0) return static_cast<int64_t>(ln.blocks_per_cu) * ln.block >= 3 * 256;
     const int64_t lanes = static_cast<int64_t>(device_cus()) * 4 * 3 * 64;
-    return n_rays >= (qmetric ? W3_MIN_RAYS_PER_LANE_Q : W3_MIN_RAYS_PER_LANE_KERR) * lanes;
+    return n_rays >= W3_MIN_RAYS_PER_LANE * lanes;
 }
 
 double horizon(const kt_spacetime* st) {
@@ -398,7 +397,7 @@ int render_images(const kt::Image* table, int32_t n_images, int64_t n_rays, cons
     p.from_list = 0;
     p.wall_khz = out->stats ? device_wall_khz() : 0.0;
     const int64_t lane_grid = (n_rays + ln.block - 1) / ln.block;
-    const bool w3 = three_wave_form(ln, n_rays, table[0].metric == KT_METRIC_Q);
+    const bool w3 = three_wave_form(ln, n_rays);
     int grid;
     if (p.persistent) {
         const int per_cu = ln.blocks_per_cu > 0 ? ln.blocks_per_cu
